@@ -1,0 +1,305 @@
+"""Plain FP64 CPU oracle for the CC3 ground-state triples residual.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  The product path (the HIP
+library and its Python binding) never calls it and shares no code with it.
+
+It follows Paul, Myhre & Koch, "A new and efficient implementation of CC3"
+(arXiv 2007.01088): Section "Implementation", Algorithm 1 (CC3 ground-state
+equations), the permutation operator P^{abc}_{ijk}, the orbital-energy
+difference, the contravariant amplitudes and the covariant back-transformation.
+Every step is a numpy einsum over float64 arrays, taken in the order the
+algorithm states; no blocking, fusion or reordering beyond it.
+
+Readings of the paper used here (each is listed in the design notes):
+  * The T1 transformation (Sec. Theory, H = exp(-T1) H exp(T1)) acts on the
+    Cholesky vectors as  Lt^J = (1 - t) L^J (1 + t)  with t[no+a][i] = t^a_i.
+  * F_kc is the ov block of the T1-transformed Fock matrix of a canonical
+    Hartree-Fock reference (whose own ov block vanishes):
+        F_kc = sum_{ld} t^d_l (2 g_kcld - g_kdlc)   (untransformed ov integrals).
+  * The contravariant amplitudes permute the virtual indices only, at fixed
+    (i,j,k), as in the second statement of Algorithm 1.  (The displayed
+    equation that permutes occupied and virtual indices together would be
+    identically zero under the permutational symmetry.)
+  * The denominator uses the canonical orbital energies:
+        eps^{abc}_{ijk} = e_a + e_b + e_c - e_i - e_j - e_k,  tau = -X / eps.
+  * For two equal occupied indices each distinct occupied permutation is
+    applied once (three of them); i == j == k is skipped (tau-tilde vanishes).
+  * Back-transformation  Omega^{ab}_{ij} = 1/3 P^{ab}_{ij}(2 Ot^{ab}_{ij} + Ot^{ba}_{ij})
+    with P^{ab}_{ij} Y^{ab}_{ij} = Y^{ab}_{ij} + Y^{ba}_{ji}, on full square
+    storage.  Absolute agreement with the paper's program at the diagonal
+    (ai == bj) elements is parity unpinned: the paper prints no residual values.
+
+Array layouts (row-major): eps[no+nv] (occupied first), L[nJ][nmo][nmo],
+t1[no][nv] = t^a_i, t2[no][no][nv][nv] = t^{ab}_{ij}, omega1[no][nv],
+omega2[no][no][nv][nv]; integral blocks in the paper's index order,
+g_vvvo[b][d][c][k] = g_{bdck}, g_oovo[l][j][c][k] = g_{ljck},
+g_ovov[j][b][k][c] = g_{jbkc}, g_ooov[j][l][k][c] = g_{jlkc},
+g_vvov[d][b][k][c] = g_{dbkc}, F[k][c].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "t1_transform", "IntegralBlocks", "fock_ov", "w_term", "t3_amplitudes",
+    "contravariant", "occupied_permutations", "unordered_triples", "omega_tilde",
+    "back_transform", "triples_residual", "triples_residual_blocks",
+    "omega_tilde_subset", "nominal_flops", "FlopCounter",
+]
+
+
+class FlopCounter:
+    """Counts 2*M*N*K for every contraction the oracle executes."""
+
+    def __init__(self) -> None:
+        self.total = 0
+
+    def add(self, n: int) -> None:
+        self.total += int(n)
+
+
+def _e(spec: str, *ops, flops: FlopCounter | None = None):
+    """einsum with the FLOP count of a plain contraction: 2 * (output size) * (summed size)."""
+    if flops is not None:
+        ins, out = spec.split("->")
+        dims = {}
+        for lab, op in zip(ins.split(","), ops):
+            for ch, n in zip(lab, op.shape):
+                dims[ch] = n
+        summed = [ch for ch in dims if ch not in out]
+        osz = int(np.prod([dims[ch] for ch in out])) if out else 1
+        ssz = int(np.prod([dims[ch] for ch in summed])) if summed else 1
+        if summed:
+            flops.add(2 * osz * ssz)
+    return np.einsum(spec, *ops, optimize=True)
+
+
+# --------------------------------------------------------------------------
+# Integrals in the T1-transformed basis (Sec. Theory, eq. for H = e^{-T1} H e^{T1};
+# Sec. Implementation: "integrals in T1-transformed basis").
+# --------------------------------------------------------------------------
+
+def t1_transform(L: np.ndarray, t1: np.ndarray) -> np.ndarray:
+    """Lt^J = (1 - t) L^J (1 + t) with t[no+a][i] = t^a_i (all other entries zero).
+
+    exp(-T1) a_p^dagger exp(T1) = sum_q a_q^dagger (1 - t)_{qp} and
+    exp(-T1) a_q exp(T1) = sum_s a_s (1 + t)_{qs}^T, so every one-index object
+    h_pq becomes ((1 - t) h (1 + t))_pq; the Cholesky factors transform alike.
+    """
+    nJ, nmo, _ = L.shape
+    no, nv = t1.shape
+    t = np.zeros((nmo, nmo))
+    t[no:, :no] = t1.T
+    left = np.eye(nmo) - t
+    right = np.eye(nmo) + t
+    return np.ascontiguousarray(np.matmul(np.matmul(left, L), right))
+
+
+class IntegralBlocks:
+    """Integral blocks g_pqrs = sum_J Lt^J_pq Lt^J_rs needed by Algorithm 1.
+
+    The two nv^3 no blocks (vv|vo) and (vv|ov) are built one occupied slab at a
+    time on demand (g_vvvo[:, :, :, k] and g_vvov[:, :, k, :]), so a sampled
+    subset of triples needs only the slabs of its occupied indices.
+    """
+
+    def __init__(self, Lt: np.ndarray, no: int, full: bool = False):
+        self.no = no
+        self.nv = Lt.shape[1] - no
+        o, v = slice(0, no), slice(no, None)
+        self.L_vv = Lt[:, v, v]
+        self.L_vo = Lt[:, v, o]
+        self.L_oo = Lt[:, o, o]
+        self.L_ov = Lt[:, o, v]
+        # the small blocks, complete
+        self.g_oovo = _e("Jlj,Jck->ljck", self.L_oo, self.L_vo)
+        self.g_ovov = _e("Jjb,Jkc->jbkc", self.L_ov, self.L_ov)
+        self.g_ooov = _e("Jjl,Jkc->jlkc", self.L_oo, self.L_ov)
+        self._vvvo: dict[int, np.ndarray] = {}
+        self._vvov: dict[int, np.ndarray] = {}
+        if full:
+            for k in range(no):
+                self.vvvo(k)
+                self.vvov(k)
+
+    def vvvo(self, k: int) -> np.ndarray:
+        """g_vvvo[b][d][c] at fixed k: g_{bdck}."""
+        if k not in self._vvvo:
+            self._vvvo[k] = _e("Jbd,Jc->bdc", self.L_vv, self.L_vo[:, :, k])
+        return self._vvvo[k]
+
+    def vvov(self, k: int) -> np.ndarray:
+        """g_vvov[d][b][c] at fixed k: g_{dbkc}."""
+        if k not in self._vvov:
+            self._vvov[k] = _e("Jdb,Jc->dbc", self.L_vv, self.L_ov[:, k, :])
+        return self._vvov[k]
+
+    @classmethod
+    def from_arrays(cls, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov):
+        """Blocks given directly in the paper's index order (the integral-blocks form)."""
+        self = cls.__new__(cls)
+        self.no = g_oovo.shape[0]
+        self.nv = g_vvvo.shape[0]
+        self.g_oovo, self.g_ovov, self.g_ooov = g_oovo, g_ovov, g_ooov
+        self._vvvo = {k: np.ascontiguousarray(g_vvvo[:, :, :, k]) for k in range(self.no)}
+        self._vvov = {k: np.ascontiguousarray(g_vvov[:, :, k, :]) for k in range(self.no)}
+        return self
+
+    def full_vvvo(self) -> np.ndarray:
+        return np.stack([self.vvvo(k) for k in range(self.no)], axis=3)
+
+    def full_vvov(self) -> np.ndarray:
+        return np.stack([self.vvov(k) for k in range(self.no)], axis=2)
+
+
+def fock_ov(L: np.ndarray, t1: np.ndarray) -> np.ndarray:
+    """F_kc of the T1-transformed Fock matrix (canonical HF reference, whose ov block is zero).
+
+    F_kc = h~_kc + sum_l (2 g~_kcll - g~_kllc); with the ov block of Lt equal to
+    the untransformed one this reduces to sum_{ld} t^d_l (2 g_kcld - g_kdlc).
+    """
+    no, nv = t1.shape
+    Lov = L[:, :no, no:]
+    g_ovov = _e("Jkc,Jld->kcld", Lov, Lov)
+    return np.ascontiguousarray(2.0 * _e("ld,kcld->kc", t1, g_ovov) - _e("ld,kdlc->kc", t1, g_ovov))
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1, inside the restricted loop over i >= j >= k.
+# --------------------------------------------------------------------------
+
+def w_term(p: int, q: int, r: int, t2: np.ndarray, blk: IntegralBlocks,
+           flops: FlopCounter | None = None) -> np.ndarray:
+    """B^{abc}_{pqr} = sum_d t^{ad}_{pq} g_{bdcr} - sum_l t^{ab}_{pl} g_{lqcr}   (Algorithm 1, first statement)."""
+    vv = _e("ad,bdc->abc", t2[p, q], blk.vvvo(r), flops=flops)
+    oo = _e("lab,lc->abc", t2[p], blk.g_oovo[:, q, :, r], flops=flops)
+    return vv - oo
+
+
+def t3_amplitudes(i: int, j: int, k: int, eps: np.ndarray, t2: np.ndarray,
+                  blk: IntegralBlocks, flops: FlopCounter | None = None) -> np.ndarray:
+    """tau^{abc}_{ijk} = -(eps^{abc}_{ijk})^{-1} P^{abc}_{ijk} B^{abc}_{ijk}.
+
+    P^{abc}_{ijk} B = B^{abc}_{ijk} + B^{bac}_{jik} + B^{cba}_{kji} + B^{acb}_{ikj}
+                    + B^{bca}_{jki} + B^{cab}_{kij}   (the permutation operator of Sec. Implementation).
+    """
+    no = t2.shape[0]
+    X = (w_term(i, j, k, t2, blk, flops)
+         + np.einsum("bac->abc", w_term(j, i, k, t2, blk, flops))
+         + np.einsum("cba->abc", w_term(k, j, i, t2, blk, flops))
+         + np.einsum("acb->abc", w_term(i, k, j, t2, blk, flops))
+         + np.einsum("bca->abc", w_term(j, k, i, t2, blk, flops))
+         + np.einsum("cab->abc", w_term(k, i, j, t2, blk, flops)))
+    ev = eps[no:]
+    D = (ev[:, None, None] + ev[None, :, None] + ev[None, None, :]
+         - eps[i] - eps[j] - eps[k])
+    return -X / D
+
+
+def contravariant(tau: np.ndarray) -> np.ndarray:
+    """tau~^{abc} = 4 tau^{abc} - 2 tau^{acb} - 2 tau^{cba} - 2 tau^{bac} + tau^{bca} + tau^{cab} (fixed ijk)."""
+    return (4.0 * tau
+            - 2.0 * np.einsum("acb->abc", tau)
+            - 2.0 * np.einsum("cba->abc", tau)
+            - 2.0 * np.einsum("bac->abc", tau)
+            + np.einsum("bca->abc", tau)
+            + np.einsum("cab->abc", tau))
+
+
+def occupied_permutations(i: int, j: int, k: int, tt: np.ndarray):
+    """The distinct occupied permutations (p,q,r) of (i,j,k) with tau~_{pqr} as a view of tau~_{ijk}.
+
+    From the permutational symmetry tau^{abc}_{ijk} = tau^{bac}_{jik} = tau^{cba}_{kji}
+    = tau^{acb}_{ikj} = tau^{cab}_{kij} = tau^{bca}_{jki} (Sec. Implementation), which
+    tau~ shares because its coefficients are the same for every relabelling:
+      (i,j,k): tt[a,b,c]   (j,i,k): tt[b,a,c]   (k,j,i): tt[c,b,a]
+      (i,k,j): tt[a,c,b]   (j,k,i): tt[c,a,b]   (k,i,j): tt[b,c,a]
+    Six terms when i, j, k differ, three when two are equal.
+    """
+    cand = [
+        ((i, j, k), "abc"), ((j, i, k), "bac"), ((k, j, i), "cba"),
+        ((i, k, j), "acb"), ((j, k, i), "cab"), ((k, i, j), "bca"),
+    ]
+    seen = set()
+    out = []
+    for pqr, lab in cand:
+        if pqr in seen:
+            continue
+        seen.add(pqr)
+        out.append((pqr, np.einsum(lab + "->abc", tt)))
+    return out
+
+
+def unordered_triples(no: int):
+    """The restricted loop i >= j >= k of Algorithm 1, without the i == j == k triples."""
+    return [(i, j, k) for i in range(no) for j in range(i + 1) for k in range(j + 1)
+            if not (i == j == k)]
+
+
+def omega_tilde(eps: np.ndarray, t2: np.ndarray, blk: IntegralBlocks, F: np.ndarray,
+                triples=None, flops: FlopCounter | None = None):
+    """The contravariant residual contributions of Algorithm 1 from the given unordered triples.
+
+    For each distinct permutation (p,q,r) with U = tau~_{pqr}:
+        Ot^a_p     += sum_{bc} U^{abc} g_{qbrc}
+        Ot^{ab}_{pq} += sum_c  U^{abc} F_{rc}
+        Ot^{ab}_{pl} -= sum_c  U^{abc} g_{qlrc}        (all l)
+        Ot^{ad}_{pq} += sum_{bc} U^{abc} g_{dbrc}       (all d)
+    """
+    no, _, nv, _ = t2.shape
+    Ot1 = np.zeros((no, nv))
+    Ot2 = np.zeros((no, no, nv, nv))
+    if triples is None:
+        triples = unordered_triples(no)
+    for (i, j, k) in triples:
+        i, j, k = int(i), int(j), int(k)
+        if i == j == k:
+            continue
+        tau = t3_amplitudes(i, j, k, eps, t2, blk, flops)
+        tt = contravariant(tau)
+        for (p, q, r), U in occupied_permutations(i, j, k, tt):
+            Ot1[p] += _e("abc,bc->a", U, blk.g_ovov[q, :, r, :], flops=flops)
+            Ot2[p, q] += _e("abc,c->ab", U, F[r], flops=flops)
+            Ot2[p] -= _e("abc,lc->lab", U, blk.g_ooov[q, :, r, :], flops=flops)
+            Ot2[p, q] += _e("abc,dbc->ad", U, blk.vvov(r), flops=flops)
+    return Ot1, Ot2
+
+
+def back_transform(Ot1: np.ndarray, Ot2: np.ndarray):
+    """Omega^a_i = Ot^a_i;  Omega^{ab}_{ij} = 1/3 P^{ab}_{ij} (2 Ot^{ab}_{ij} + Ot^{ba}_{ij})."""
+    Y = 2.0 * Ot2 + np.einsum("ijba->ijab", Ot2)
+    return Ot1.copy(), (Y + np.einsum("jiba->ijab", Y)) / 3.0
+
+
+# --------------------------------------------------------------------------
+# Whole calls.
+# --------------------------------------------------------------------------
+
+def triples_residual(eps, L, t1, t2, flops: FlopCounter | None = None):
+    """One evaluation of the CC3 triples contribution (Omega1, Omega2) from Cholesky vectors."""
+    no = t1.shape[0]
+    Lt = t1_transform(L, t1)
+    blk = IntegralBlocks(Lt, no)
+    F = fock_ov(L, t1)
+    return back_transform(*omega_tilde(eps, t2, blk, F, flops=flops))
+
+
+def triples_residual_blocks(eps, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F, t2):
+    """The same evaluation from integral blocks given in the paper's index order."""
+    blk = IntegralBlocks.from_arrays(g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov)
+    return back_transform(*omega_tilde(eps, t2, blk, F))
+
+
+def omega_tilde_subset(eps, L, t1, t2, triples):
+    """Contravariant (Ot1, Ot2) from a listed subset of unordered triples only (no back-transform)."""
+    no = t1.shape[0]
+    Lt = t1_transform(L, t1)
+    blk = IntegralBlocks(Lt, no)
+    F = fock_ov(L, t1)
+    return omega_tilde(eps, t2, blk, F, triples=[tuple(t) for t in triples])
+
+
+def nominal_flops(no: int, nv: int) -> float:
+    """The paper's asymptotic ground-state cost per residual call: 4 nv^4 no^3 FLOP (abstract)."""
+    return 4.0 * float(nv) ** 4 * float(no) ** 3
