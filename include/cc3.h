@@ -1,0 +1,188 @@
+/*
+ * cc3.h - C ABI of libcc3.so, the MI355X (gfx950) implementation of the CC3
+ * ground-state triples contribution to the singles and doubles residual.
+ *
+ * Method: Paul, Myhre & Koch, "A new and efficient implementation of CC3"
+ * (arXiv 2007.01088), Sec. "Implementation", Algorithm 1.  For every
+ * unordered occupied triple i >= j >= k (i == j == k skipped) the library
+ * builds t3 from (bd|ck) t2 and (lj|ck) t2 contractions, the permutation
+ * operator P^{abc}_{ijk} and the orbital-energy denominator, forms the
+ * contravariant amplitudes, and contracts them into the contravariant
+ * residual; a back-transformation gives the covariant Omega.  The full
+ * nv^3 no^3 t3 tensor is never stored.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: CC3_OK (0) or a negative CC3_E_* code; cc3_last_error()
+ *     then returns a thread-local message describing the failure.
+ *   - Unless stated otherwise, array pointers are DEVICE pointers (memory of
+ *     the context's GPU, e.g. torch CUDA tensors or hipMalloc), row-major,
+ *     float64, owned by the caller.  The library keeps no pointer after the
+ *     work it enqueued has completed.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns without waiting for it; results are valid once the
+ *     stream has reached that point.
+ *   - Index order: occupied orbitals first.  eps[no+nv]; L[nchol][nmo][nmo]
+ *     (nmo = no+nv, symmetric in the last two indices); t1[no][nv] = t^a_i;
+ *     t2[no][no][nv][nv] = t^{ab}_{ij} with t2[i][j][a][b] == t2[j][i][b][a];
+ *     omega1[no][nv]; omega2[no][no][nv][nv].
+ *   - Scratch memory comes only from the caller's workspace (size from
+ *     cc3_workspace_size); the library allocates no device memory for the
+ *     residual calls.
+ */
+#ifndef CC3_H
+#define CC3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cc3_ctx cc3_ctx;
+typedef void* cc3_stream_t; /* hipStream_t */
+
+/* status codes */
+enum {
+  CC3_OK = 0,
+  CC3_E_INVAL = -1,    /* bad argument: sizes, null or host pointer, unknown enum */
+  CC3_E_NOMEM = -2,    /* workspace (or arena) too small for the request */
+  CC3_E_DEVICE = -3,   /* a HIP runtime call failed */
+  CC3_E_PRECOND = -4,  /* CC3_CHECK found a violated input symmetry or denominator */
+  CC3_E_NOTFOUND = -5, /* unknown molecule or ticket */
+  CC3_E_BUSY = -6,     /* serving queue full (non-blocking submit) */
+  CC3_E_TIMEOUT = -7,  /* wait timed out */
+  CC3_E_CANCELLED = -8 /* request was cancelled */
+};
+
+/* arithmetic of the W contractions (the t3-building GEMMs, Algorithm 1 first statement) */
+enum {
+  CC3_FP64 = 0,   /* FP64 MFMA everywhere */
+  CC3_FP32 = 1,   /* W contractions on FP32 MFMA with FP32 accumulation */
+  CC3_BF16X3 = 2, /* W on bf16 MFMA, 2-piece split, 3 products, FP32 accumulation */
+  CC3_BF16X6 = 3  /* W on bf16 MFMA, 3-piece split, 6 products, FP32 accumulation */
+};
+/* In every precision the denominator division, the P-symmetrisation, the
+ * contravariant combination and the Omega accumulation are FP64. */
+
+/* flags */
+enum {
+  CC3_ACCUMULATE = 1u,    /* add the triples contribution into omega1/omega2 instead of overwriting */
+  CC3_CHECK = 2u          /* verify input symmetries (t2, L) and positive denominators first */
+};
+
+/* ---------------------------------------------------------------------- */
+/* Context                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device`.  *out receives the handle.
+ * Errors: CC3_E_INVAL (out NULL, device out of range), CC3_E_DEVICE. */
+int cc3_create(cc3_ctx** out, int device);
+
+/* Destroy a context (NULL is accepted).  Waits for nothing: the caller must
+ * have synchronised the streams it used. */
+int cc3_destroy(cc3_ctx* ctx);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* cc3_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* One-shot residual                                                        */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace needed by cc3_triples_residual (nchol > 0) or
+ * cc3_triples_residual_blocks (nchol == 0) for these sizes, precision and
+ * flags.  Host-only computation; no context needed.
+ * Errors: CC3_E_INVAL (no < 1, nv < 1, nchol < 0, bytes NULL, unknown prec). */
+int cc3_workspace_size(int no, int nv, int nchol, int prec, unsigned flags, size_t* bytes);
+
+/* The CC3 ground-state triples contribution (Algorithm 1) from Cholesky vectors.
+ *
+ * The integrals are T1-transformed (H = exp(-T1) H exp(T1), Sec. Theory):
+ * Lt^J = (1 - t) L^J (1 + t) with t[no+a][i] = t1[i][a]; g_pqrs = sum_J Lt^J_pq Lt^J_rs;
+ * F_kc = sum_ld t1[l][d] (2 g_kcld - g_kdlc) (T1-transformed Fock ov block of a
+ * canonical reference).  The integral blocks stay resident in the workspace
+ * for the whole call.
+ *
+ * Inputs (device): eps[no+nv], L[nchol][nmo][nmo], t1[no][nv], t2[no][no][nv][nv].
+ * Outputs (device): omega1[no][nv], omega2[no][no][nv][nv]: the covariant
+ * triples contribution  Omega^a_i = Ot^a_i,
+ * Omega^{ab}_{ij} = 1/3 [(2 Ot^{ab}_{ij} + Ot^{ba}_{ij}) + (2 Ot^{ba}_{ji} + Ot^{ab}_{ji})],
+ * written (or added, with CC3_ACCUMULATE).
+ * workspace: device buffer of at least cc3_workspace_size(no, nv, nchol, prec, flags) bytes,
+ * 256-byte aligned; contents on entry are ignored.
+ * Errors: CC3_E_INVAL, CC3_E_NOMEM (workspace_bytes too small), CC3_E_DEVICE,
+ * CC3_E_PRECOND (with CC3_CHECK). */
+int cc3_triples_residual(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps,
+                         const double* L, const double* t1, const double* t2, double* omega1,
+                         double* omega2, int prec, unsigned flags, void* workspace,
+                         size_t workspace_bytes, cc3_stream_t stream);
+
+/* The same residual from integral blocks already in the T1-transformed basis,
+ * laid out in the paper's index order (device, row-major):
+ *   g_vvvo[b][d][c][k] = g_{bdck},  g_oovo[l][j][c][k] = g_{ljck},
+ *   g_ovov[j][b][k][c] = g_{jbkc},  g_ooov[j][l][k][c] = g_{jlkc},
+ *   g_vvov[d][b][k][c] = g_{dbkc},  F_ov[k][c] = F_{kc}.
+ * Workspace from cc3_workspace_size(no, nv, 0, prec, flags).  Errors as above. */
+int cc3_triples_residual_blocks(cc3_ctx* ctx, int no, int nv, const double* eps,
+                                const double* g_vvvo, const double* g_oovo, const double* g_ovov,
+                                const double* g_ooov, const double* g_vvov, const double* F_ov,
+                                const double* t2, double* omega1, double* omega2, int prec,
+                                unsigned flags, void* workspace, size_t workspace_bytes,
+                                cc3_stream_t stream);
+
+/* Contravariant contributions (before the back-transformation) of a listed
+ * subset of unordered occupied triples only: for each distinct occupied
+ * permutation (p,q,r) of a listed (i,j,k), with U = tau~_{pqr},
+ *   Ot1[p][a] += sum_bc U^{abc} g_{qbrc};  Ot2[p][q][a][b] += sum_c U^{abc} F_{rc};
+ *   Ot2[p][l][a][b] -= sum_c U^{abc} g_{qlrc};  Ot2[p][q][a][d] += sum_bc U^{abc} g_{dbrc}.
+ * triples: HOST int32 array [ntriples][3] with i >= j >= k, not all equal, each
+ * < no (copied before the call returns).  omega1_tilde[no][nv] and
+ * omega2_tilde[no][no][nv][nv] (device) are overwritten.  Used for sampled
+ * parity at large sizes and to emulate a triple-partitioned multi-GPU run.
+ * Workspace as for cc3_triples_residual.  Errors: CC3_E_INVAL (bad triple),
+ * CC3_E_NOMEM, CC3_E_DEVICE. */
+int cc3_triples_residual_subset(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps,
+                                const double* L, const double* t1, const double* t2,
+                                const int32_t* triples, int ntriples, double* omega1_tilde,
+                                double* omega2_tilde, int prec, unsigned flags, void* workspace,
+                                size_t workspace_bytes, cc3_stream_t stream);
+
+/* Debug export of the t3 amplitudes of one ordered triple (i, j, k) (any order,
+ * not all equal): tau[a][b][c] = tau^{abc}_{ijk} = -(eps^{abc}_{ijk})^{-1} P^{abc}_{ijk} B^{abc}_{ijk}
+ * (Algorithm 1, first statement), written to the device array tau[nv][nv][nv].
+ * Inputs as for cc3_triples_residual.  Errors: CC3_E_INVAL, CC3_E_NOMEM, CC3_E_DEVICE. */
+int cc3_t3_block(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps, const double* L,
+                 const double* t1, const double* t2, int i, int j, int k, double* tau, int prec,
+                 void* workspace, size_t workspace_bytes, cc3_stream_t stream);
+
+/* FLOP per residual call: *nominal = 4 nv^4 no^3 (the paper's asymptotic count,
+ * abstract); *executed = the multiply-adds (x2) this library's triple loop
+ * issues for the dominant contractions and their small companions, padding
+ * excluded.  Either pointer may be NULL.  Errors: CC3_E_INVAL. */
+int cc3_flops(int no, int nv, double* nominal, double* executed);
+
+/* ---------------------------------------------------------------------- */
+/* Kernel timing (HIP events on the launch stream)                          */
+/* ---------------------------------------------------------------------- */
+
+typedef struct cc3_kernel_stat {
+  char name[32];      /* kernel family, e.g. "w_build", "omega_contract" */
+  int64_t launches;   /* launches recorded since the last reset */
+  double total_ms;    /* sum of event-measured durations */
+  double flops;       /* algorithmic FLOP of those launches (padding excluded) */
+  double bytes;       /* algorithmic HBM bytes of those launches */
+} cc3_kernel_stat;
+
+/* Turn per-launch event timing on (1) or off (0); turning it on resets the stats. */
+int cc3_profile_enable(cc3_ctx* ctx, int on);
+/* Copy up to `max` kernel-family stats to out; *count receives the number
+ * written.  Synchronises the recorded events (blocks the host).  Errors:
+ * CC3_E_INVAL, CC3_E_DEVICE. */
+int cc3_profile_get(cc3_ctx* ctx, cc3_kernel_stat* out, int max, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CC3_H */

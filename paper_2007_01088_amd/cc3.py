@@ -1,0 +1,212 @@
+"""Thin Python binding of libcc3.so (C ABI in include/cc3.h).
+
+Argument marshalling only: every step of the residual runs in the library's
+HIP kernels.  Arrays are torch CUDA tensors (float64, contiguous); torch
+supplies device memory and the stream, nothing else.  There is no fallback:
+if the library is missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("CC3_LIB", os.path.join(_HERE, "libcc3.so"))
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libcc3.so not found at {LIB_PATH}; build it with "
+                      "`python -m paper_2007_01088_amd.csrc.build` (or __graft_entry__.build())")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_PRECOND, E_NOTFOUND, E_BUSY, E_TIMEOUT, E_CANCELLED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
+ACCUMULATE, CHECK = 1, 2
+
+_c_int, _c_size, _vp, _dp = ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+def _sig(name, args, res=_c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_create = _sig("cc3_create", [ctypes.POINTER(_vp), _c_int])
+_destroy = _sig("cc3_destroy", [_vp])
+_last_error = _sig("cc3_last_error", [], ctypes.c_char_p)
+_ws_size = _sig("cc3_workspace_size", [_c_int, _c_int, _c_int, _c_int, ctypes.c_uint,
+                                       ctypes.POINTER(_c_size)])
+_residual = _sig("cc3_triples_residual", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp,
+                                          _dp, _c_int, ctypes.c_uint, _vp, _c_size, _vp])
+_residual_blocks = _sig("cc3_triples_residual_blocks",
+                        [_vp, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                         _c_int, ctypes.c_uint, _vp, _c_size, _vp])
+_residual_subset = _sig("cc3_triples_residual_subset",
+                        [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _vp, _c_int, _dp, _dp,
+                         _c_int, ctypes.c_uint, _vp, _c_size, _vp])
+_t3_block = _sig("cc3_t3_block", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _c_int, _c_int,
+                                  _c_int, _dp, _c_int, _vp, _c_size, _vp])
+_flops = _sig("cc3_flops", [_c_int, _c_int, ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double)])
+_prof_enable = _sig("cc3_profile_enable", [_vp, _c_int])
+_prof_get = _sig("cc3_profile_get", [_vp, ctypes.POINTER(KernelStat), _c_int,
+                                     ctypes.POINTER(_c_int)])
+
+EXPORTED = ["cc3_create", "cc3_destroy", "cc3_last_error", "cc3_workspace_size",
+            "cc3_triples_residual", "cc3_triples_residual_blocks", "cc3_triples_residual_subset",
+            "cc3_t3_block", "cc3_flops", "cc3_profile_enable", "cc3_profile_get"]
+
+
+class CC3Error(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _last_error().decode(errors="replace")
+        super().__init__(f"{where} failed ({code}): {msg}")
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise CC3Error(rc, where)
+
+
+def last_error() -> str:
+    return _last_error().decode(errors="replace")
+
+
+def _ptr(t: torch.Tensor | None, name: str, dtype=torch.float64) -> int:
+    if t is None:
+        return 0
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA tensor of dtype {dtype}")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def workspace_size(no: int, nv: int, nchol: int, prec: int = FP64, flags: int = 0) -> int:
+    n = _c_size(0)
+    _check(_ws_size(no, nv, nchol, prec, flags, ctypes.byref(n)), "cc3_workspace_size")
+    return n.value
+
+
+def flops(no: int, nv: int) -> tuple[float, float]:
+    a, b = ctypes.c_double(0), ctypes.c_double(0)
+    _check(_flops(no, nv, ctypes.byref(a), ctypes.byref(b)), "cc3_flops")
+    return a.value, b.value
+
+
+class Context:
+    """A libcc3 context on one device, with a cached workspace tensor."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(_create(ctypes.byref(h), device), "cc3_create")
+        self._h = h
+        self.device = device
+        self._ws = None
+
+    def close(self) -> None:
+        if self._h:
+            _destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8,
+                                   device=f"cuda:{self.device}")
+        return self._ws
+
+    # ---- residual calls ------------------------------------------------
+    def triples_residual(self, eps, L, t1, t2, omega1=None, omega2=None, prec=FP64, flags=0,
+                         stream=None):
+        no, nv = t1.shape
+        nchol = L.shape[0]
+        if omega1 is None:
+            omega1 = torch.empty((no, nv), dtype=torch.float64, device=t2.device)
+        if omega2 is None:
+            omega2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=t2.device)
+        nbytes = workspace_size(no, nv, nchol, prec, flags)
+        ws = self.workspace(nbytes)
+        _check(_residual(self._h, no, nv, nchol, _ptr(eps, "eps"), _ptr(L, "L"), _ptr(t1, "t1"),
+                         _ptr(t2, "t2"), _ptr(omega1, "omega1"), _ptr(omega2, "omega2"), prec,
+                         flags, ws.data_ptr(), ws.numel(), _stream(stream)),
+               "cc3_triples_residual")
+        return omega1, omega2
+
+    def triples_residual_blocks(self, eps, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov, t2,
+                                omega1=None, omega2=None, prec=FP64, flags=0, stream=None):
+        no, nv = F_ov.shape
+        if omega1 is None:
+            omega1 = torch.empty((no, nv), dtype=torch.float64, device=t2.device)
+        if omega2 is None:
+            omega2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=t2.device)
+        nbytes = workspace_size(no, nv, 0, prec, flags)
+        ws = self.workspace(nbytes)
+        _check(_residual_blocks(self._h, no, nv, _ptr(eps, "eps"), _ptr(g_vvvo, "g_vvvo"),
+                                _ptr(g_oovo, "g_oovo"), _ptr(g_ovov, "g_ovov"),
+                                _ptr(g_ooov, "g_ooov"), _ptr(g_vvov, "g_vvov"),
+                                _ptr(F_ov, "F_ov"), _ptr(t2, "t2"), _ptr(omega1, "omega1"),
+                                _ptr(omega2, "omega2"), prec, flags, ws.data_ptr(), ws.numel(),
+                                _stream(stream)), "cc3_triples_residual_blocks")
+        return omega1, omega2
+
+    def triples_residual_subset(self, eps, L, t1, t2, triples, prec=FP64, flags=0, stream=None):
+        """Contravariant (Ot1, Ot2) from the listed unordered triples (host int32 [n][3])."""
+        import numpy as np
+        no, nv = t1.shape
+        nchol = L.shape[0]
+        tri = np.ascontiguousarray(np.asarray(triples, dtype=np.int32).reshape(-1, 3))
+        o1 = torch.empty((no, nv), dtype=torch.float64, device=t2.device)
+        o2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=t2.device)
+        nbytes = workspace_size(no, nv, nchol, prec, flags)
+        ws = self.workspace(nbytes)
+        _check(_residual_subset(self._h, no, nv, nchol, _ptr(eps, "eps"), _ptr(L, "L"),
+                                _ptr(t1, "t1"), _ptr(t2, "t2"),
+                                tri.ctypes.data_as(ctypes.c_void_p), int(tri.shape[0]),
+                                _ptr(o1, "o1"), _ptr(o2, "o2"), prec, flags, ws.data_ptr(),
+                                ws.numel(), _stream(stream)), "cc3_triples_residual_subset")
+        return o1, o2
+
+    def t3_block(self, eps, L, t1, t2, i, j, k, prec=FP64, stream=None):
+        no, nv = t1.shape
+        nchol = L.shape[0]
+        tau = torch.empty((nv, nv, nv), dtype=torch.float64, device=t2.device)
+        nbytes = workspace_size(no, nv, nchol, prec, 0)
+        ws = self.workspace(nbytes)
+        _check(_t3_block(self._h, no, nv, nchol, _ptr(eps, "eps"), _ptr(L, "L"), _ptr(t1, "t1"),
+                         _ptr(t2, "t2"), i, j, k, _ptr(tau, "tau"), prec, ws.data_ptr(),
+                         ws.numel(), _stream(stream)), "cc3_t3_block")
+        return tau
+
+    # ---- kernel timing ---------------------------------------------------
+    def profile_enable(self, on: bool = True) -> None:
+        _check(_prof_enable(self._h, 1 if on else 0), "cc3_profile_enable")
+
+    def profile_get(self) -> dict:
+        arr = (KernelStat * 16)()
+        n = _c_int(0)
+        _check(_prof_get(self._h, arr, 16, ctypes.byref(n)), "cc3_profile_get")
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                       "flops": arr[i].flops, "bytes": arr[i].bytes}
+                for i in range(n.value)}

@@ -1,0 +1,80 @@
+// Host-side declarations shared by the C ABI (cc3_api.cpp) and the kernel
+// translation units: the workspace plan and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cc3 {
+
+// Device-resident, internally laid out integral blocks (all float64):
+//   Gw[r][y][d][z] = g_{ydzr}         (vv|vo), the W contraction operand
+//   Go[q][r][l][z] = g_{lqzr}         (oo|vo)
+//   Gv[r][b][d][c] = g_{dbrc}         (vv|ov), the Omega contraction operand
+//   Jo[q][r][b][c] = g_{qbrc}         (ov|ov)
+//   Hs[q][r][l][c] = delta_{lq} F_rc - g_{qlrc}   (oo|ov) and the Fock ov block
+//   F[k][c]
+struct Blocks {
+  double* Gw;
+  double* Go;
+  double* Gv;
+  double* Jo;
+  double* Hs;
+  double* F;
+};
+
+// Intermediates of the T1 transformation (Cholesky form only):
+//   Lvv[J][b][d] = Lt_{bd}, LvvT[J][d][b] = Lt_{bd}, Loo[J][q][l] = Lt_{ql},
+//   LooT[J][l][q] = Lt_{ql}, LvoT[J][k][c] = Lt_{ck}, Lov[J][k][c] = L_{kc},
+//   s[J], M[J][k][l]: partial sums of the Fock ov block.
+struct CholeskyScratch {
+  double *Lvv, *LvvT, *Loo, *LooT, *LvoT, *Lov, *s, *M;
+};
+
+struct Plan {
+  int no, nv, nchol, prec;
+  unsigned flags;
+  int ntri;     // unordered triples i >= j >= k, not all equal
+  int batch;    // triples per batch of the triple loop
+  size_t cube;  // doubles per nv^3 cube
+  // byte offsets into the workspace
+  size_t off_Gw, off_Go, off_Gv, off_Jo, off_Hs, off_F;
+  size_t off_Ot1, off_Ot2, off_tri, off_flag, off_cubes;
+  size_t off_chol;  // Cholesky scratch (aliases the cube region)
+  size_t chol_bytes, cube_bytes;
+  size_t total;
+};
+
+int make_plan(int no, int nv, int nchol, int prec, unsigned flags, Plan* p, int batch_override);
+
+// ---- launchers (all enqueue on `st`) ----
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+void launch_t1_transform(const double* L, const double* t1, const CholeskyScratch& cs, int no,
+                         int nv, int nJ, hipStream_t st);
+void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no, int nv, int nJ,
+                 hipStream_t st);
+void launch_build_blocks(const CholeskyScratch& cs, const Blocks& b, int no, int nv, int nJ,
+                         hipStream_t st);
+void launch_relayout_blocks(const double* g_vvvo, const double* g_oovo, const double* g_ovov,
+                            const double* g_ooov, const double* g_vvov, const double* F_ov,
+                            const Blocks& b, int no, int nv, hipStream_t st);
+void launch_triple_table(int* tri, int no, hipStream_t st);
+void launch_wbuild(const double* t2, const Blocks& b, const int* tri, int ntri, double* cubes,
+                   int no, int nv, bool all_terms, hipStream_t st);
+void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, int no, int nv,
+                hipStream_t st);
+void launch_tau_export(const double* eps, const int* tri, const double* cubes, double* tau, int no,
+                       int nv, hipStream_t st);
+void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Ot1,
+                  double* Ot2, int no, int nv, hipStream_t st);
+void launch_back_transform(const double* Ot1, const double* Ot2, double* O1, double* O2, int no,
+                           int nv, bool accumulate, hipStream_t st);
+void launch_set_triples(int* tri_dev, const int* host_tri, int n, hipStream_t st);
+void launch_check(const double* eps, const double* L, const double* t2, int no, int nv, int nJ,
+                  int* flag, hipStream_t st);
+
+// Algorithmic FLOP of one launch of the two dominant kernels (padding excluded).
+double wbuild_flops(int no, int nv, const int* host_types, int n);
+double omega_flops(int no, int nv, const int* host_types, int n);
+
+}  // namespace cc3

@@ -1,0 +1,378 @@
+// Preparation kernels run once per residual call, before the triple loop:
+// the T1 transformation of the Cholesky vectors, the Fock ov block, the
+// integral-block build (FP64 MFMA GEMMs over the Cholesky index, writing the
+// internal layouts the triple loop streams), the re-layout of caller-given
+// blocks, the triple table, and the covariant back-transformation after it.
+#include "cc3_device.hpp"
+#include "cc3_internal.hpp"
+
+namespace cc3 {
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  unsigned g = nblk(n, 256);
+  if (g > 65536u) g = 65536u;
+  hipLaunchKernelGGL(k_fill, dim3(g), dim3(256), 0, st, p, n, v);
+}
+
+// ---------------------------------------------------------------------------
+// T1 transformation (exp(-T1) H exp(T1)):  Lt = (1 - t) L (1 + t), t[no+a][i] = t1[i][a].
+//   Lt_bd = L_bd - sum_l t1[l][b] L_ld        Lt_lj = L_lj + sum_d L_ld t1[j][d]
+//   Lt_ck = L_ck + sum_d L_cd t1[k][d] - sum_l t1[l][c] Lt_lk      Lt_kc = L_kc
+// ---------------------------------------------------------------------------
+__global__ void k_t1_vv(const double* __restrict__ L, const double* __restrict__ t1,
+                        double* __restrict__ Lvv, double* __restrict__ LvvT, int no, int nv) {
+  const int J = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nv * nv) return;
+  const int b = (int)(idx / nv), d = (int)(idx % nv);
+  const int nmo = no + nv;
+  const double* LJ = L + (int64_t)J * nmo * nmo;
+  double v = LJ[(int64_t)(no + b) * nmo + no + d];
+  for (int l = 0; l < no; ++l) v -= t1[(int64_t)l * nv + b] * LJ[(int64_t)l * nmo + no + d];
+  const int64_t base = (int64_t)J * nv * nv;
+  Lvv[base + (int64_t)b * nv + d] = v;
+  LvvT[base + (int64_t)d * nv + b] = v;
+}
+
+__global__ void k_t1_oo(const double* __restrict__ L, const double* __restrict__ t1,
+                        double* __restrict__ Loo, double* __restrict__ LooT,
+                        double* __restrict__ Lov, int no, int nv) {
+  const int J = blockIdx.y;
+  const int nmo = no + nv;
+  const double* LJ = L + (int64_t)J * nmo * nmo;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < no * no) {
+    const int l = idx / no, j = idx % no;
+    double v = LJ[(int64_t)l * nmo + j];
+    for (int d = 0; d < nv; ++d) v += LJ[(int64_t)l * nmo + no + d] * t1[(int64_t)j * nv + d];
+    Loo[(int64_t)J * no * no + (int64_t)l * no + j] = v;
+    LooT[(int64_t)J * no * no + (int64_t)j * no + l] = v;
+  }
+  // untransformed ov block, Lov[J][k][c] = L_{k, no+c}
+  for (int e = idx; e < no * nv; e += gridDim.x * blockDim.x) {
+    const int k = e / nv, c = e % nv;
+    Lov[(int64_t)J * no * nv + e] = LJ[(int64_t)k * nmo + no + c];
+  }
+}
+
+__global__ void k_t1_vo(const double* __restrict__ L, const double* __restrict__ t1,
+                        const double* __restrict__ Loo, double* __restrict__ LvoT, int no, int nv) {
+  const int J = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= no * nv) return;
+  const int k = idx / nv, c = idx % nv;
+  const int nmo = no + nv;
+  const double* LJ = L + (int64_t)J * nmo * nmo;
+  double v = LJ[(int64_t)(no + c) * nmo + k];
+  for (int d = 0; d < nv; ++d) v += LJ[(int64_t)(no + c) * nmo + no + d] * t1[(int64_t)k * nv + d];
+  const double* LooJ = Loo + (int64_t)J * no * no;
+  for (int l = 0; l < no; ++l) v -= t1[(int64_t)l * nv + c] * LooJ[(int64_t)l * no + k];
+  LvoT[(int64_t)J * no * nv + (int64_t)k * nv + c] = v;
+}
+
+void launch_t1_transform(const double* L, const double* t1, const CholeskyScratch& cs, int no,
+                         int nv, int nJ, hipStream_t st) {
+  hipLaunchKernelGGL(k_t1_vv, dim3(nblk((int64_t)nv * nv, 256), nJ), dim3(256), 0, st, L, t1,
+                     cs.Lvv, cs.LvvT, no, nv);
+  int m = no * no > no * nv ? no * no : no * nv;
+  hipLaunchKernelGGL(k_t1_oo, dim3(nblk(m, 256), nJ), dim3(256), 0, st, L, t1, cs.Loo, cs.LooT,
+                     cs.Lov, no, nv);
+  hipLaunchKernelGGL(k_t1_vo, dim3(nblk((int64_t)no * nv, 256), nJ), dim3(256), 0, st, L, t1,
+                     cs.Loo, cs.LvoT, no, nv);
+}
+
+// ---------------------------------------------------------------------------
+// Fock ov block of the T1-transformed Hamiltonian (canonical reference):
+//   F_kc = sum_ld t1[l][d] (2 g_kcld - g_kdlc),  g_kcld = sum_J L_kc L_ld
+//        = sum_J [ 2 s_J L_kc - sum_l M_J[k][l] L_lc ],
+//   s_J = sum_ld t1[l][d] L_ld,  M_J[k][l] = sum_d L_kd t1[l][d].
+// ---------------------------------------------------------------------------
+__global__ void k_fock_sm(const double* __restrict__ t1, const double* __restrict__ Lov,
+                          double* __restrict__ s, double* __restrict__ M, int no, int nv) {
+  const int J = blockIdx.x;
+  const double* LJ = Lov + (int64_t)J * no * nv;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < no * nv; e += blockDim.x) acc += t1[e] * LJ[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s[J] = red[0];
+  for (int e = threadIdx.x; e < no * no; e += blockDim.x) {
+    const int k = e / no, l = e % no;
+    double v = 0.0;
+    for (int d = 0; d < nv; ++d) v += LJ[(int64_t)k * nv + d] * t1[(int64_t)l * nv + d];
+    M[(int64_t)J * no * no + e] = v;
+  }
+}
+
+__global__ void k_fock(const double* __restrict__ Lov, const double* __restrict__ s,
+                       const double* __restrict__ M, double* __restrict__ F, int no, int nv,
+                       int nJ) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= no * nv) return;
+  const int k = idx / nv, c = idx % nv;
+  double v = 0.0;
+  for (int J = 0; J < nJ; ++J) {
+    const double* LJ = Lov + (int64_t)J * no * nv;
+    double w = 2.0 * s[J] * LJ[(int64_t)k * nv + c];
+    const double* MJ = M + (int64_t)J * no * no + (int64_t)k * no;
+    for (int l = 0; l < no; ++l) w -= MJ[l] * LJ[(int64_t)l * nv + c];
+    v += w;
+  }
+  F[idx] = v;
+}
+
+void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no, int nv, int nJ,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_fock_sm, dim3(nJ), dim3(256), 0, st, t1, cs.Lov, cs.s, cs.M, no, nv);
+  hipLaunchKernelGGL(k_fock, dim3(nblk((int64_t)no * nv, 128)), dim3(128), 0, st, cs.Lov, cs.s,
+                     cs.M, F, no, nv, nJ);
+}
+
+// ---------------------------------------------------------------------------
+// Integral-block build: C[m][n] = sum_J A(m, J) B(J, n) on FP64 MFMA, batched
+// over blockIdx.z, with an output map per block kind.
+// ---------------------------------------------------------------------------
+enum BuildKind { BUILD_PLAIN = 0, BUILD_JO = 1, BUILD_HS = 2, BUILD_GO = 3 };
+
+typedef TileCfg<2, 2, 4, 4> BuildCfg;
+
+__global__ __launch_bounds__(BuildCfg::NT) void k_build(
+    const double* __restrict__ Ap, int64_t a_sm, int64_t a_sk, int64_t a_bs,
+    const double* __restrict__ Bp, int64_t b_sk, int64_t b_sn, int64_t b_bs, int M, int N, int K,
+    double* __restrict__ C, int64_t c_bs, int kind, int no, int nv, const double* __restrict__ F) {
+  typedef BuildCfg T;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int mt = (M + T::BM - 1) / T::BM;
+  const int m0 = (blockIdx.x % mt) * T::BM;
+  const int n0 = (blockIdx.x / mt) * T::BN;
+  const int z = blockIdx.z;
+  const double* A = Ap + (int64_t)z * a_bs;
+  const double* B = Bp + (int64_t)z * b_bs;
+  d4v acc[T::FM][T::FN];
+  zero_acc<T>(acc);
+  const int nsteps = (K + T::BK - 1) / T::BK;
+  auto ops = [&](int s, Opnd& oa, Opnd& ob, int& k0) {
+    k0 = s * T::BK;
+    oa = make_opnd(A, a_sm, a_sk, M, K, 1.0, true);
+    ob = make_opnd(B, b_sn, b_sk, N, K, 1.0, true);
+  };
+  auto none = [](int) {};
+  k_loop<T>(nsteps, m0, n0, ops, none, acc, lds);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % T::WM, wn = wave / T::WM;
+  double* Cz = C + (int64_t)z * c_bs;
+#pragma unroll
+  for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < T::FN; ++fn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + acc_row<T>(wm, fm, lane, r);
+        const int n = n0 + acc_col<T>(wn, fn, lane);
+        if (m >= M || n >= N) continue;
+        const double v = acc[fm][fn][r];
+        if (kind == BUILD_PLAIN) {
+          Cz[(int64_t)m * N + n] = v;
+        } else if (kind == BUILD_JO) {  // m = q*nv + b, n = r*nv + c -> Jo[q][r][b][c]
+          const int q = m / nv, b = m % nv, rr = n / nv, c = n % nv;
+          Cz[(((int64_t)q * no + rr) * nv + b) * nv + c] = v;
+        } else if (kind == BUILD_HS) {  // m = q*no + l, n = r*nv + c -> Hs[q][r][l][c]
+          const int q = m / no, l = m % no, rr = n / nv, c = n % nv;
+          Cz[(((int64_t)q * no + rr) * no + l) * nv + c] = (l == q ? F[(int64_t)rr * nv + c] : 0.0) - v;
+        } else {  // BUILD_GO: m = q*no + l, n = r*nv + z -> Go[q][r][l][z]
+          const int q = m / no, l = m % no, rr = n / nv, c = n % nv;
+          Cz[(((int64_t)q * no + rr) * no + l) * nv + c] = v;
+        }
+      }
+}
+
+static void build(const double* A, int64_t a_sm, int64_t a_sk, int64_t a_bs, const double* B,
+                  int64_t b_sk, int64_t b_sn, int64_t b_bs, int M, int N, int K, double* C,
+                  int64_t c_bs, int batch, int kind, int no, int nv, const double* F,
+                  hipStream_t st) {
+  typedef BuildCfg T;
+  const unsigned mt = nblk(M, T::BM), nt = nblk(N, T::BN);
+  hipLaunchKernelGGL(k_build, dim3(mt * nt, 1, batch), dim3(T::NT), 0, st, A, a_sm, a_sk, a_bs, B,
+                     b_sk, b_sn, b_bs, M, N, K, C, c_bs, kind, no, nv, F);
+}
+
+void launch_build_blocks(const CholeskyScratch& cs, const Blocks& bl, int no, int nv, int nJ,
+                         hipStream_t st) {
+  const int64_t nv2 = (int64_t)nv * nv, nv3 = nv2 * nv, onv = (int64_t)no * nv;
+  // Gw[r][(y,d)][z] = sum_J Lvv[J][(y,d)] LvoT[J][r][z]
+  build(cs.Lvv, 1, nv2, 0, cs.LvoT, onv, 1, nv, (int)nv2, nv, nJ, bl.Gw, nv3, no, BUILD_PLAIN, no,
+        nv, nullptr, st);
+  // Gv[r][(b,d)][c] = sum_J LvvT[J][(b,d)] Lov[J][r][c]
+  build(cs.LvvT, 1, nv2, 0, cs.Lov, onv, 1, nv, (int)nv2, nv, nJ, bl.Gv, nv3, no, BUILD_PLAIN, no,
+        nv, nullptr, st);
+  // Jo[q][r][b][c] = sum_J Lov[J][q][b] Lov[J][r][c]
+  build(cs.Lov, 1, onv, 0, cs.Lov, onv, 1, 0, (int)onv, (int)onv, nJ, bl.Jo, 0, 1, BUILD_JO, no,
+        nv, nullptr, st);
+  // Hs[q][r][l][c] = delta_lq F[r][c] - sum_J Loo[J][q][l] Lov[J][r][c]
+  build(cs.Loo, 1, (int64_t)no * no, 0, cs.Lov, onv, 1, 0, no * no, (int)onv, nJ, bl.Hs, 0, 1,
+        BUILD_HS, no, nv, bl.F, st);
+  // Go[q][r][l][z] = sum_J LooT[J][q][l] LvoT[J][r][z]   (LooT[J][q][l] = Lt_lq)
+  build(cs.LooT, 1, (int64_t)no * no, 0, cs.LvoT, onv, 1, 0, no * no, (int)onv, nJ, bl.Go, 0, 1,
+        BUILD_GO, no, nv, nullptr, st);
+}
+
+// ---------------------------------------------------------------------------
+// Integral blocks given in the paper's index order -> internal layouts.
+// ---------------------------------------------------------------------------
+__global__ void k_relayout_vv(const double* __restrict__ g_vvvo, const double* __restrict__ g_vvov,
+                              double* __restrict__ Gw, double* __restrict__ Gv, int no, int nv) {
+  // output index (r, y, d, z) of an nv^3 slab; z fastest
+  const int64_t nv3 = (int64_t)nv * nv * nv;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (e >= nv3) return;
+  const int y = (int)(e / ((int64_t)nv * nv)), d = (int)((e / nv) % nv), z = (int)(e % nv);
+  // Gw[r][y][d][z] = g_vvvo[y][d][z][r]
+  Gw[(int64_t)r * nv3 + e] = g_vvvo[(((int64_t)y * nv + d) * nv + z) * no + r];
+  // Gv[r][b=y][d][c=z] = g_vvov[d][b][r][c]
+  Gv[(int64_t)r * nv3 + e] = g_vvov[(((int64_t)d * nv + y) * no + r) * nv + z];
+}
+
+__global__ void k_relayout_small(const double* __restrict__ g_oovo, const double* __restrict__ g_ovov,
+                                 const double* __restrict__ g_ooov, const double* __restrict__ F_ov,
+                                 double* __restrict__ Go, double* __restrict__ Jo,
+                                 double* __restrict__ Hs, double* __restrict__ F, int no, int nv) {
+  const int q = blockIdx.y / no, r = blockIdx.y % no;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nv * nv; e += gridDim.x * blockDim.x) {
+    const int b = e / nv, c = e % nv;  // Jo[q][r][b][c] = g_ovov[q][b][r][c]
+    Jo[(((int64_t)q * no + r) * nv + b) * nv + c] = g_ovov[(((int64_t)q * nv + b) * no + r) * nv + c];
+  }
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < no * nv; e += gridDim.x * blockDim.x) {
+    const int l = e / nv, c = e % nv;
+    // Go[q][r][l][z] = g_oovo[l][q][z][r]
+    Go[(((int64_t)q * no + r) * no + l) * nv + c] = g_oovo[(((int64_t)l * no + q) * nv + c) * no + r];
+    // Hs[q][r][l][c] = delta_lq F[r][c] - g_ooov[q][l][r][c]
+    Hs[(((int64_t)q * no + r) * no + l) * nv + c] =
+        (l == q ? F_ov[(int64_t)r * nv + c] : 0.0) - g_ooov[(((int64_t)q * no + l) * no + r) * nv + c];
+  }
+  if (blockIdx.y == 0)
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < no * nv; e += gridDim.x * blockDim.x)
+      F[e] = F_ov[e];
+}
+
+void launch_relayout_blocks(const double* g_vvvo, const double* g_oovo, const double* g_ovov,
+                            const double* g_ooov, const double* g_vvov, const double* F_ov,
+                            const Blocks& b, int no, int nv, hipStream_t st) {
+  const int64_t nv3 = (int64_t)nv * nv * nv;
+  hipLaunchKernelGGL(k_relayout_vv, dim3(nblk(nv3, 256), no), dim3(256), 0, st, g_vvvo, g_vvov,
+                     b.Gw, b.Gv, no, nv);
+  unsigned gx = nblk((int64_t)nv * nv, 256);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(k_relayout_small, dim3(gx, no * no), dim3(256), 0, st, g_oovo, g_ovov,
+                     g_ooov, F_ov, b.Go, b.Jo, b.Hs, b.F, no, nv);
+}
+
+// ---------------------------------------------------------------------------
+// Triple table: the restricted loop i >= j >= k in lexicographic order without
+// the i == j == k triples; rank = C(i+2,3) + j(j+1)/2 + k - i.
+// ---------------------------------------------------------------------------
+__global__ void k_triples(int* __restrict__ tri, int no) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= no * no * no) return;
+  const int i = e / (no * no), j = (e / no) % no, k = e % no;
+  if (!(i >= j && j >= k) || (i == j && j == k)) return;
+  const int rank = i * (i + 1) * (i + 2) / 6 + j * (j + 1) / 2 + k - i;
+  tri[3 * rank + 0] = i;
+  tri[3 * rank + 1] = j;
+  tri[3 * rank + 2] = k;
+}
+
+void launch_triple_table(int* tri, int no, hipStream_t st) {
+  hipLaunchKernelGGL(k_triples, dim3(nblk((int64_t)no * no * no, 256)), dim3(256), 0, st, tri, no);
+}
+
+void launch_set_triples(int* tri_dev, const int* host_tri, int n, hipStream_t st) {
+  hipMemcpyAsync(tri_dev, host_tri, sizeof(int) * 3 * (size_t)n, hipMemcpyHostToDevice, st);
+}
+
+// ---------------------------------------------------------------------------
+// Covariant back-transformation:
+//   Omega^a_i = Ot^a_i
+//   Omega^{ab}_{ij} = 1/3 [(2 Ot^{ab}_{ij} + Ot^{ba}_{ij}) + (2 Ot^{ba}_{ji} + Ot^{ab}_{ji})]
+// ---------------------------------------------------------------------------
+__global__ void k_back(const double* __restrict__ Ot1, const double* __restrict__ Ot2,
+                       double* __restrict__ O1, double* __restrict__ O2, int no, int nv, int acc) {
+  const int64_t n2 = (int64_t)no * no * nv * nv;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n2) {
+    const int b = (int)(e % nv), a = (int)((e / nv) % nv);
+    const int j = (int)((e / ((int64_t)nv * nv)) % no), i = (int)(e / ((int64_t)nv * nv * no));
+    const int64_t ij = ((int64_t)i * no + j) * nv, ji = ((int64_t)j * no + i) * nv;
+    const double v = (2.0 * Ot2[(ij + a) * nv + b] + Ot2[(ij + b) * nv + a] +
+                      2.0 * Ot2[(ji + b) * nv + a] + Ot2[(ji + a) * nv + b]) / 3.0;
+    O2[e] = acc ? O2[e] + v : v;
+  }
+  if (e < (int64_t)no * nv) O1[e] = acc ? O1[e] + Ot1[e] : Ot1[e];
+}
+
+void launch_back_transform(const double* Ot1, const double* Ot2, double* O1, double* O2, int no,
+                           int nv, bool accumulate, hipStream_t st) {
+  const int64_t n2 = (int64_t)no * no * nv * nv;
+  hipLaunchKernelGGL(k_back, dim3(nblk(n2, 256)), dim3(256), 0, st, Ot1, Ot2, O1, O2, no, nv,
+                     accumulate ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Input checks (CC3_CHECK): pair symmetry of t2, symmetry of L in (p, q), and
+// positive denominators (3 min e_vir - 3 max e_occ > 0).  Sets bits of *flag.
+// ---------------------------------------------------------------------------
+__device__ inline bool differs(double x, double y) {
+  const double s = fmax(fabs(x), fabs(y));
+  return fabs(x - y) > 1e-12 * s;
+}
+
+__global__ void k_check(const double* __restrict__ eps, const double* __restrict__ L,
+                        const double* __restrict__ t2, int no, int nv, int nJ, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nvl = nv, n2 = (int64_t)no * no * nvl * nvl;
+  int bits = 0;
+  for (int64_t e = e0; e < n2; e += stride) {
+    const int b = (int)(e % nvl), a = (int)((e / nvl) % nvl);
+    const int j = (int)((e / (nvl * nvl)) % no), i = (int)(e / (nvl * nvl * no));
+    if (differs(t2[e], t2[(((int64_t)j * no + i) * nvl + b) * nvl + a])) bits |= 1;
+  }
+  if (L) {
+    const int64_t nmo = no + nv, nl = (int64_t)nJ * nmo * nmo;
+    for (int64_t e = e0; e < nl; e += stride) {
+      const int64_t q = e % nmo, pp = (e / nmo) % nmo, J = e / (nmo * nmo);
+      if (differs(L[e], L[(J * nmo + q) * nmo + pp])) bits |= 2;
+    }
+  }
+  if (e0 == 0) {
+    double emax = eps[0], vmin = eps[no];
+    for (int i = 1; i < no; ++i) emax = fmax(emax, eps[i]);
+    for (int a = 1; a < nv; ++a) vmin = fmin(vmin, eps[no + a]);
+    if (!(3.0 * vmin - 3.0 * emax > 0.0)) bits |= 4;
+  }
+  if (bits) atomicOr(flag, bits);
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+void launch_check(const double* eps, const double* L, const double* t2, int no, int nv, int nJ,
+                  int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, flag);
+  hipLaunchKernelGGL(k_check, dim3(1024), dim3(256), 0, st, eps, L, t2, no, nv, nJ, flag);
+}
+
+}  // namespace cc3

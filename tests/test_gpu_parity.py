@@ -1,0 +1,206 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on an MI355X.
+
+Tolerance (the FP64 bar): for each result separately,
+    ||Omega_gpu - Omega_oracle||_2   <= 1e-11 ||Omega_oracle||_2   and
+    max |Omega_gpu - Omega_oracle|  <= 1e-11 max |Omega_oracle|.
+Both sides compute in FP64 from the same seeded inputs; the bound absorbs
+re-association of the sums (observed differences are ~1e-15).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cc3_oracle as O
+from paper_2007_01088_amd.synth import make_inputs, sample_triples
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _torch()
+    from paper_2007_01088_amd import cc3
+    c = cc3.Context(0)
+    yield c
+    c.close()
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(torch, d):
+    return {k: torch.from_numpy(np.ascontiguousarray(d[k])).cuda() for k in ("eps", "L", "t1", "t2")}
+
+
+def assert_close(name, got, ref):
+    got = np.asarray(got)
+    nref = np.linalg.norm(ref)
+    assert nref > 0, name
+    err = np.linalg.norm(got - ref) / nref
+    emax = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"  {name}: rel2 {err:.3e} relmax {emax:.3e}")
+    assert err <= TOL and emax <= TOL, (name, err, emax)
+
+
+@pytest.mark.parametrize("no,nv,nJ,t1z", [(4, 20, 60, False), (4, 20, 60, True), (3, 9, 12, False),
+                                          (5, 37, 50, False), (6, 130, 40, False)])
+def test_full_residual_parity(ctx, no, nv, nJ, t1z):
+    """Whole call from Cholesky vectors; sizes cover one and two 128-wide tiles and ragged
+    8-blocks (nv = 9, 37, 130)."""
+    torch = _torch()
+    say(f"full residual no={no} nv={nv} nJ={nJ} t1_zero={t1z}")
+    d = make_inputs(no, nv, nJ, t1_zero=t1z)
+    r1, r2 = O.triples_residual(d["eps"], d["L"], d["t1"], d["t2"])
+    g = dev(torch, d)
+    o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
+    torch.cuda.synchronize()
+    assert_close("Omega1", o1.cpu().numpy(), r1)
+    assert_close("Omega2", o2.cpu().numpy(), r2)
+
+
+def test_blocks_form_parity(ctx):
+    torch = _torch()
+    no, nv, nJ = 5, 21, 30
+    say(f"blocks form no={no} nv={nv}")
+    d = make_inputs(no, nv, nJ)
+    Lt = O.t1_transform(d["L"], d["t1"])
+    blk = O.IntegralBlocks(Lt, no, full=True)
+    F = O.fock_ov(d["L"], d["t1"])
+    args = [blk.full_vvvo(), blk.g_oovo, blk.g_ovov, blk.g_ooov, blk.full_vvov(), F]
+    r1, r2 = O.triples_residual_blocks(d["eps"], *args, d["t2"])
+    ga = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in args]
+    g = dev(torch, d)
+    o1, o2 = ctx.triples_residual_blocks(g["eps"], *ga, g["t2"])
+    torch.cuda.synchronize()
+    assert_close("Omega1", o1.cpu().numpy(), r1)
+    assert_close("Omega2", o2.cpu().numpy(), r2)
+
+
+def test_t3_symmetry_and_value(ctx):
+    """t3 from the device equals the oracle's and obeys tau^{abc}_{ijk} = tau^{bac}_{jik} = ..."""
+    torch = _torch()
+    no, nv, nJ = 5, 19, 24
+    d = make_inputs(no, nv, nJ)
+    g = dev(torch, d)
+    Lt = O.t1_transform(d["L"], d["t1"])
+    blk = O.IntegralBlocks(Lt, no, full=True)
+    i, j, k = 4, 2, 1
+    t = ctx.t3_block(g["eps"], g["L"], g["t1"], g["t2"], i, j, k).cpu().numpy()
+    ref = O.t3_amplitudes(i, j, k, d["eps"], d["t2"], blk)
+    assert_close("tau_ijk", t, ref)
+    for (p, q, r), lab in [((j, i, k), "bac"), ((k, j, i), "cba"), ((i, k, j), "acb"),
+                           ((k, i, j), "cab"), ((j, k, i), "bca")]:
+        o = ctx.t3_block(g["eps"], g["L"], g["t1"], g["t2"], p, q, r).cpu().numpy()
+        assert np.abs(np.einsum(lab + "->abc", o) - t).max() <= 1e-13 * np.abs(t).max()
+
+
+def test_accumulate_flag(ctx):
+    torch = _torch()
+    from paper_2007_01088_amd import cc3
+    d = make_inputs(4, 20, 60)
+    g = dev(torch, d)
+    o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
+    b1 = torch.full_like(o1, 0.5)
+    b2 = torch.full_like(o2, -0.25)
+    ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], omega1=b1, omega2=b2,
+                         flags=cc3.ACCUMULATE)
+    torch.cuda.synchronize()
+    assert torch.allclose(b1, o1 + 0.5, rtol=0, atol=1e-15)
+    assert torch.allclose(b2, o2 - 0.25, rtol=0, atol=1e-15)
+
+
+def test_edge_cases_vanish(ctx):
+    """no = 1 (only i == j == k) and nv = 1 (virtual-symmetric t3) give Omega = 0 exactly."""
+    torch = _torch()
+    for no, nv in [(1, 7), (3, 1), (2, 1)]:
+        d = make_inputs(no, nv, 6)
+        g = dev(torch, d)
+        o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
+        torch.cuda.synchronize()
+        assert float(o1.abs().max()) < 1e-20 and float(o2.abs().max()) < 1e-20, (no, nv)
+
+
+def test_errors_are_reported(ctx):
+    torch = _torch()
+    from paper_2007_01088_amd import cc3
+    d = make_inputs(3, 8, 10)
+    g = dev(torch, d)
+    # asymmetric t2 under CC3_CHECK
+    bad = g["t2"].clone()
+    bad[0, 1, 2, 3] += 1e-3
+    with pytest.raises(cc3.CC3Error) as e:
+        ctx.triples_residual(g["eps"], g["L"], g["t1"], bad, flags=cc3.CHECK)
+    assert e.value.code == cc3.E_PRECOND
+    # the check passes on valid inputs
+    ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], flags=cc3.CHECK)
+    # host pointer -> INVAL
+    with pytest.raises(ValueError):
+        ctx.triples_residual(g["eps"].cpu(), g["L"], g["t1"], g["t2"])
+    # bad subset triple
+    with pytest.raises(cc3.CC3Error) as e:
+        ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], [[1, 2, 0]])
+    assert e.value.code == cc3.E_INVAL
+    # workspace too small
+    import ctypes
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    o1 = torch.empty((3, 8), dtype=torch.float64, device="cuda")
+    o2 = torch.empty((3, 3, 8, 8), dtype=torch.float64, device="cuda")
+    rc = cc3._residual(ctx._h, 3, 8, 10, g["eps"].data_ptr(), g["L"].data_ptr(),
+                       g["t1"].data_ptr(), g["t2"].data_ptr(), o1.data_ptr(), o2.data_ptr(), 0, 0,
+                       ws.data_ptr(), 1024, torch.cuda.current_stream().cuda_stream)
+    assert rc == cc3.E_NOMEM
+
+
+def test_subset_sums_to_whole(ctx):
+    """Disjoint triple subsets (the per-GPU shares of a triple-partitioned run) sum to the
+    whole contravariant residual."""
+    torch = _torch()
+    no, nv = 6, 24
+    d = make_inputs(no, nv, 30)
+    g = dev(torch, d)
+    allt = np.array(O.unordered_triples(no), dtype=np.int32)
+    parts = [allt[s::3] for s in range(3)]
+    tot1 = tot2 = 0
+    for part in parts:
+        a, b = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], part)
+        tot1 = tot1 + a.cpu().numpy()
+        tot2 = tot2 + b.cpu().numpy()
+    w1, w2 = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], allt)
+    assert_close("Ot1 parts", tot1, w1.cpu().numpy())
+    assert_close("Ot2 parts", tot2, w2.cpu().numpy())
+    r1, r2 = O.omega_tilde_subset(d["eps"], d["L"], d["t1"], d["t2"], allt)
+    assert_close("Ot1", w1.cpu().numpy(), r1)
+    assert_close("Ot2", w2.cpu().numpy(), r2)
+
+
+@pytest.mark.parametrize("no,nv,nJ,count", [(12, 120, 400, 10), (23, 250, 800, 2),
+                                            (31, 400, 1200, 0)])
+def test_sampled_parity_full_sizes(ctx, no, nv, nJ, count):
+    """At the benchmark sizes the oracle evaluates a seeded sample of triples plus one
+    distinct and two two-equal triples, one by one; the device evaluates the same subset in
+    the same launch configuration as the full call."""
+    torch = _torch()
+    d = make_inputs(no, nv, nJ)
+    extra = np.array([[no - 1, no // 2, 0], [no - 1, no - 1, 0], [no - 1, 0, 0]], dtype=np.int32)
+    tri = np.concatenate([sample_triples(no, count, seed=5), extra]) if count else extra
+    tri = np.unique(tri, axis=0)
+    say(f"sampled parity no={no} nv={nv} nJ={nJ} triples={tri.tolist()}")
+    g = dev(torch, d)
+    o1, o2 = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], tri)
+    torch.cuda.synchronize()
+    o1, o2 = o1.cpu().numpy(), o2.cpu().numpy()
+    del g
+    r1, r2 = O.omega_tilde_subset(d["eps"], d["L"], d["t1"], d["t2"], tri)
+    assert_close("Ot1", o1, r1)
+    assert_close("Ot2", o2, r2)
