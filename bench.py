@@ -112,6 +112,9 @@ def main() -> int:
     ap.add_argument("--prec", default="fp64", choices=["fp64"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic, used to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the triple loop would "
@@ -132,6 +135,14 @@ def main() -> int:
     o1 = torch.empty((no, nv), dtype=torch.float64, device=dev)
     o2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=dev)
     ctx = cc3.Context(0)
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb << 17  # doubles
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 8} bytes read and {n * 8} bytes written")
+        del src, dst
     for w in range(args.warmup):
         ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], o1, o2)
         torch.cuda.synchronize()

@@ -93,7 +93,8 @@ const char* cc3_last_error(void);
 /* Bytes of device workspace needed by cc3_triples_residual (nchol > 0) or
  * cc3_triples_residual_blocks (nchol == 0) for these sizes, precision and
  * flags.  Host-only computation; no context needed.
- * Errors: CC3_E_INVAL (no < 1, nv < 1, nchol < 0, bytes NULL, unknown prec). */
+ * Supported sizes: 1 <= no <= 63, 1 <= nv <= 1024.
+ * Errors: CC3_E_INVAL (sizes out of range, nchol < 0, bytes NULL, unknown prec). */
 int cc3_workspace_size(int no, int nv, int nchol, int prec, unsigned flags, size_t* bytes);
 
 /* The CC3 ground-state triples contribution (Algorithm 1) from Cholesky vectors.

@@ -51,9 +51,15 @@ struct TimedLaunch {
   double flops, bytes;
 };
 
-static const char* kFamilies[] = {"t1_transform", "block_build", "w_build",
-                                  "mix",          "omega_contract", "back_transform"};
-enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_BACK, NFAM };
+static const char* kFamilies[] = {"t1_transform", "block_build",  "w_build",
+                                  "mix",          "omega_contract", "reduce", "back_transform"};
+enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_REDUCE, FAM_BACK, NFAM };
+
+// The triple loop alternates its batches between two internal streams (each
+// with its own cube and slab buffers), so that one batch's W build and mix
+// overlap the previous batch's Omega contraction; the reductions into the
+// residual are chained by events in batch order.
+enum { NSTREAM = 2 };
 
 struct cc3_ctx {
   int device;
@@ -61,7 +67,24 @@ struct cc3_ctx {
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> pool;
   std::mutex mu;
+  bool have_streams = false;
+  hipStream_t s[NSTREAM];
+  hipEvent_t ev_fork, ev_done[NSTREAM], ev_red[NSTREAM];
 };
+
+static int ensure_streams(cc3_ctx* c) {
+  if (c->have_streams) return CC3_OK;
+  for (int k = 0; k < NSTREAM; ++k) {
+    if (hipStreamCreateWithFlags(&c->s[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_done[k], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_red[k], hipEventDisableTiming) != hipSuccess)
+      return fail(CC3_E_DEVICE, "could not create the internal streams");
+  }
+  if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
+    return fail(CC3_E_DEVICE, "could not create the internal streams");
+  c->have_streams = true;
+  return CC3_OK;
+}
 
 static hipEvent_t take_event(cc3_ctx* c) {
   if (!c->pool.empty()) {
@@ -114,6 +137,14 @@ extern "C" int cc3_destroy(cc3_ctx* c) {
   if (!c) return CC3_OK;
   for (auto& t : c->timed) { hipEventDestroy(t.start); hipEventDestroy(t.stop); }
   for (auto e : c->pool) hipEventDestroy(e);
+  if (c->have_streams) {
+    for (int k = 0; k < NSTREAM; ++k) {
+      hipStreamDestroy(c->s[k]);
+      hipEventDestroy(c->ev_done[k]);
+      hipEventDestroy(c->ev_red[k]);
+    }
+    hipEventDestroy(c->ev_fork);
+  }
   delete c;
   return CC3_OK;
 }
@@ -169,18 +200,22 @@ int make_plan(int no, int nv, int nchol, int prec, unsigned flags, Plan* p, int 
   const size_t o = no, v = nv, J = nchol;
   p->ntri = (int)((size_t)no * (no + 1) * (no + 2) / 6 - no);
   p->cube = v * v * v;
-  // triples per batch: enough workgroups per launch to fill 256 CUs several
-  // times over, bounded by a cube-memory budget
+  // triples per batch: enough W-build workgroups per launch to fill 256 CUs
+  // many times over, bounded by a cube-memory budget
   const size_t wg_per_triple = 3 * v * ((v + 127) / 128) * ((v + 127) / 128);
-  int batch = (int)std::max<size_t>(1, (size_t)(4096 + wg_per_triple - 1) / wg_per_triple);
-  const size_t budget = (size_t)env_int("CC3_CUBE_BUDGET_MB", 6144) << 20;
+  int batch = (int)std::max<size_t>(1, (size_t)(12288 + wg_per_triple - 1) / wg_per_triple);
+  const size_t budget = (size_t)env_int("CC3_CUBE_BUDGET_MB", 4096) << 20;
   const size_t per_triple = 5 * p->cube * sizeof(double);
   batch = (int)std::min<size_t>((size_t)batch, std::max<size_t>(1, budget / per_triple));
   batch = env_int("CC3_BATCH", batch);
   if (batch_override > 0) batch = batch_override;
+  batch = std::min(batch, 160);  // the reduction lists at most 6 * 160 pairs per p
   batch = std::max(1, std::min(batch, std::max(1, p->ntri)));
   p->batch = batch;
-
+  // largest (triples x chunks) product over the batch sizes the loop can see
+  size_t tc = 1;
+  for (int nb = 1; nb <= batch; ++nb) tc = std::max(tc, (size_t)nb * omega_nbchunks(nv, nb));
+  p->pvv_entries = tc;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
   p->off_Gw = take(o * v * v * v * 8);
@@ -191,14 +226,20 @@ int make_plan(int no, int nv, int nchol, int prec, unsigned flags, Plan* p, int 
   p->off_F = take(o * v * 8);
   p->off_Ot1 = take(o * v * 8);
   p->off_Ot2 = take(o * o * v * v * 8);
+  p->off_OtT = take(o * o * v * v * 8);
+  p->off_t2N = take(o * o * v * v * 8);
+  p->pvv_bytes = align256(tc * 6 * v * (v + 1) * 8);
+  p->soo_bytes = align256((size_t)batch * 6 * o * v * v * 8);
+  p->off_Pvv = take(2 * p->pvv_bytes);
+  p->off_Soo = take(2 * p->soo_bytes);
   p->off_tri = take((size_t)std::max(1, p->ntri) * 3 * sizeof(int) + 64);
   p->off_flag = take(64);
   // the Cholesky scratch is dead once the blocks are built: it shares the cube region
   p->chol_bytes = J ? align256(J * v * v * 8) * 2 + align256(J * o * o * 8) * 2 +
                           align256(J * o * v * 8) * 2 + align256(J * 8) + align256(J * o * o * 8)
                     : 0;
-  p->cube_bytes = (size_t)batch * 5 * p->cube * 8;
-  p->off_cubes = take(std::max(p->chol_bytes, p->cube_bytes));
+  p->cube_bytes = align256((size_t)batch * 5 * p->cube * 8);
+  p->off_cubes = take(std::max(p->chol_bytes, 2 * p->cube_bytes));
   p->off_chol = p->off_cubes;
   p->total = off;
   return CC3_OK;
@@ -209,7 +250,9 @@ int make_plan(int no, int nv, int nchol, int prec, unsigned flags, Plan* p, int 
 static int check_sizes(int no, int nv, int nchol, int prec) {
   if (no < 1 || nv < 1) return fail(CC3_E_INVAL, "sizes must be positive (no=%d nv=%d)", no, nv);
   if (nchol < 0) return fail(CC3_E_INVAL, "nchol must be >= 0 (got %d)", nchol);
-  if (no > 255 || nv > 4096) return fail(CC3_E_INVAL, "sizes too large (no=%d nv=%d)", no, nv);
+  if (no > 63 || nv > 1024)
+    return fail(CC3_E_INVAL, "sizes beyond the supported range no <= 63, nv <= 1024 (no=%d nv=%d)",
+                no, nv);
   if (prec != CC3_FP64) return fail(CC3_E_INVAL, "precision %d is not available", prec);
   return CC3_OK;
 }
@@ -257,7 +300,8 @@ static int check_dev_ptr(const void* p, const char* what) {
 struct Ws {
   Blocks b;
   CholeskyScratch cs;
-  double *Ot1, *Ot2, *cubes;
+  double *Ot1, *Ot2, *OtT, *t2N;
+  double *cubes[2], *Pvv[2], *Soo[2];
   int* tri;
   int* flag;
 };
@@ -273,9 +317,15 @@ static Ws carve(const Plan& p, void* ws) {
   w.b.F = (double*)(base + p.off_F);
   w.Ot1 = (double*)(base + p.off_Ot1);
   w.Ot2 = (double*)(base + p.off_Ot2);
+  w.OtT = (double*)(base + p.off_OtT);
+  w.t2N = (double*)(base + p.off_t2N);
+  for (int k = 0; k < 2; ++k) {
+    w.Pvv[k] = (double*)(base + p.off_Pvv + k * p.pvv_bytes);
+    w.Soo[k] = (double*)(base + p.off_Soo + k * p.soo_bytes);
+    w.cubes[k] = (double*)(base + p.off_cubes + k * p.cube_bytes);
+  }
   w.tri = (int*)(base + p.off_tri);
   w.flag = (int*)(base + p.off_flag);
-  w.cubes = (double*)(base + p.off_cubes);
   const size_t J = p.nchol, o = p.no, v = p.nv;
   char* c = base + p.off_chol;
   size_t off = 0;
@@ -302,29 +352,49 @@ static void host_triples(int no, std::vector<int>& t) {
 static int kind_of(int i, int j, int k) { return (i == j) ? 1 : (j == k) ? 2 : 0; }
 
 // The batched triple loop over a device triple table `tri` of n entries whose
-// host copy is `ht` (for FLOP accounting only).
-static void triple_loop(cc3_ctx* c, const Plan& p, const Ws& w, const double* eps, const double* t2,
-                        const int* tri, const int* ht, int n, double* Ot1, double* Ot2,
-                        hipStream_t st) {
+// host copy is `ht` (for FLOP accounting only).  Batch b runs on internal
+// stream b % 2 with buffer set b % 2; reduction b waits for reduction b - 1.
+static int triple_loop(cc3_ctx* c, const Plan& p, const Ws& w, const double* eps, const double* t2,
+                       const int* tri, const int* ht, int n, hipStream_t st) {
+  int rc = ensure_streams(c);
+  if (rc) return rc;
   std::vector<int> kinds;
-  for (int t0 = 0; t0 < n; t0 += p.batch) {
+  launch_t2N(t2, w.t2N, p.no, p.nv, st);
+  HIPCHK(hipEventRecord(c->ev_fork, st));
+  for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(c->s[k], c->ev_fork, 0));
+  int nbatch = 0;
+  for (int t0 = 0; t0 < n; t0 += p.batch, ++nbatch) {
     const int nb = std::min(p.batch, n - t0);
+    const int k = nbatch % NSTREAM;
+    hipStream_t sk = c->s[k];
     kinds.resize(nb);
     for (int t = 0; t < nb; ++t)
       kinds[t] = kind_of(ht[3 * (t0 + t)], ht[3 * (t0 + t) + 1], ht[3 * (t0 + t) + 2]);
+    const int* tb = tri + 3 * t0;
     {
-      Timer tm(c, st, FAM_W, wbuild_flops(p.no, p.nv, kinds.data(), nb), 0.0);
-      launch_wbuild(t2, w.b, tri + 3 * t0, nb, w.cubes, p.no, p.nv, false, st);
+      Timer tm(c, sk, FAM_W, wbuild_flops(p.no, p.nv, kinds.data(), nb), 0.0);
+      launch_wbuild(t2, w.t2N, w.b, tb, nb, w.cubes[k], p.no, p.nv, false, sk);
     }
     {
-      Timer tm(c, st, FAM_MIX, 0.0, 0.0);
-      launch_mix(eps, tri + 3 * t0, nb, w.cubes, p.no, p.nv, st);
+      Timer tm(c, sk, FAM_MIX, 0.0, 0.0);
+      launch_mix(eps, tb, nb, w.cubes[k], p.no, p.nv, sk);
     }
     {
-      Timer tm(c, st, FAM_OMEGA, omega_flops(p.no, p.nv, kinds.data(), nb), 0.0);
-      launch_omega(w.cubes, w.b, tri + 3 * t0, nb, Ot1, Ot2, p.no, p.nv, st);
+      Timer tm(c, sk, FAM_OMEGA, omega_flops(p.no, p.nv, kinds.data(), nb), 0.0);
+      launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], w.Soo[k], p.no, p.nv, sk);
     }
+    if (nbatch > 0) HIPCHK(hipStreamWaitEvent(sk, c->ev_red[(nbatch - 1) % NSTREAM], 0));
+    {
+      Timer tm(c, sk, FAM_REDUCE, 0.0, 0.0);
+      launch_reduce(tb, nb, w.Pvv[k], w.Soo[k], w.Ot1, w.Ot2, w.OtT, p.no, p.nv, sk);
+    }
+    HIPCHK(hipEventRecord(c->ev_red[k], sk));
   }
+  for (int k = 0; k < NSTREAM; ++k) {
+    HIPCHK(hipEventRecord(c->ev_done[k], c->s[k]));
+    HIPCHK(hipStreamWaitEvent(st, c->ev_done[k], 0));
+  }
+  return CC3_OK;
 }
 
 static int prepare_cholesky(cc3_ctx* c, const Plan& p, const Ws& w, const double* L,
@@ -391,13 +461,15 @@ extern "C" int cc3_triples_residual(cc3_ctx* c, int no, int nv, int nchol, const
   prepare_cholesky(c, p, w, L, t1, st);
   launch_fill(w.Ot1, (int64_t)no * nv, 0.0, st);
   launch_fill(w.Ot2, (int64_t)no * no * nv * nv, 0.0, st);
+  launch_fill(w.OtT, (int64_t)no * no * nv * nv, 0.0, st);
   launch_triple_table(w.tri, no, st);
   std::vector<int> ht;
   host_triples(no, ht);
-  triple_loop(c, p, w, eps, t2, w.tri, ht.data(), p.ntri, w.Ot1, w.Ot2, st);
+  if ((rc = triple_loop(c, p, w, eps, t2, w.tri, ht.data(), p.ntri, st))) return rc;
   {
     Timer tm(c, st, FAM_BACK, 0.0, 0.0);
-    launch_back_transform(w.Ot1, w.Ot2, omega1, omega2, no, nv, (flags & CC3_ACCUMULATE) != 0, st);
+    launch_back_transform(w.Ot1, w.Ot2, w.OtT, omega1, omega2, no, nv,
+                          (flags & CC3_ACCUMULATE) != 0, st);
   }
   HIPCHK(hipGetLastError());
   return CC3_OK;
@@ -428,13 +500,15 @@ extern "C" int cc3_triples_residual_blocks(cc3_ctx* c, int no, int nv, const dou
   }
   launch_fill(w.Ot1, (int64_t)no * nv, 0.0, st);
   launch_fill(w.Ot2, (int64_t)no * no * nv * nv, 0.0, st);
+  launch_fill(w.OtT, (int64_t)no * no * nv * nv, 0.0, st);
   launch_triple_table(w.tri, no, st);
   std::vector<int> ht;
   host_triples(no, ht);
-  triple_loop(c, p, w, eps, t2, w.tri, ht.data(), p.ntri, w.Ot1, w.Ot2, st);
+  if ((rc = triple_loop(c, p, w, eps, t2, w.tri, ht.data(), p.ntri, st))) return rc;
   {
     Timer tm(c, st, FAM_BACK, 0.0, 0.0);
-    launch_back_transform(w.Ot1, w.Ot2, omega1, omega2, no, nv, (flags & CC3_ACCUMULATE) != 0, st);
+    launch_back_transform(w.Ot1, w.Ot2, w.OtT, omega1, omega2, no, nv,
+                          (flags & CC3_ACCUMULATE) != 0, st);
   }
   HIPCHK(hipGetLastError());
   return CC3_OK;
@@ -468,13 +542,15 @@ extern "C" int cc3_triples_residual_subset(cc3_ctx* c, int no, int nv, int nchol
   std::lock_guard<std::mutex> g(c->mu);
   if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, L, t2, st))) return rc;
   prepare_cholesky(c, p, w, L, t1, st);
-  launch_fill(omega1_tilde, (int64_t)no * nv, 0.0, st);
-  launch_fill(omega2_tilde, (int64_t)no * no * nv * nv, 0.0, st);
+  launch_fill(w.Ot1, (int64_t)no * nv, 0.0, st);
+  launch_fill(w.Ot2, (int64_t)no * no * nv * nv, 0.0, st);
+  launch_fill(w.OtT, (int64_t)no * no * nv * nv, 0.0, st);
   if (ntriples > 0) {
     HIPCHK(hipMemcpyAsync(w.tri, triples, sizeof(int) * 3 * (size_t)ntriples,
                           hipMemcpyHostToDevice, st));
-    triple_loop(c, p, w, eps, t2, w.tri, triples, ntriples, omega1_tilde, omega2_tilde, st);
+    if ((rc = triple_loop(c, p, w, eps, t2, w.tri, triples, ntriples, st))) return rc;
   }
+  launch_combine(w.Ot1, w.Ot2, w.OtT, omega1_tilde, omega2_tilde, no, nv, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return CC3_OK;
@@ -501,8 +577,9 @@ extern "C" int cc3_t3_block(cc3_ctx* c, int no, int nv, int nchol, const double*
   prepare_cholesky(c, p, w, L, t1, st);
   const int h[3] = {i, j, k};
   HIPCHK(hipMemcpyAsync(w.tri, h, sizeof h, hipMemcpyHostToDevice, st));
-  launch_wbuild(t2, w.b, w.tri, 1, w.cubes, no, nv, true, st);
-  launch_tau_export(eps, w.tri, w.cubes, tau, no, nv, st);
+  launch_t2N(t2, w.t2N, no, nv, st);
+  launch_wbuild(t2, w.t2N, w.b, w.tri, 1, w.cubes[0], no, nv, true, st);
+  launch_tau_export(eps, w.tri, w.cubes[0], tau, no, nv, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return CC3_OK;

@@ -9,69 +9,98 @@ namespace cc3 {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-// A strided 2D operand view: element (x, k) lives at p[x * sx + k * sk] and is
-// multiplied by `scale`; outside [0, xlim) x [0, klim) it reads as zero.
-// `xfast` selects the thread mapping used for the global loads: true when
-// x is the contiguous index, false when k is.
+// A strided 2D operand view: element (x, k) lives at p[x * sx + k * sk]; outside
+// [0, xlim) x [0, klim) it reads as zero.  `xfast` selects the thread mapping
+// of the global loads: true when x is the contiguous index, false when k is.
+// Offsets relative to p must fit in 32 bits (p itself is 64-bit).
 struct Opnd {
   const double* p;
-  int64_t sx, sk;
+  int sx, sk;
   int xlim, klim;
-  double scale;
   bool xfast;
 };
 
 __device__ inline Opnd make_opnd(const double* p, int64_t sx, int64_t sk, int xlim, int klim,
-                                 double scale, bool xfast) {
+                                 bool xfast) {
   Opnd o;
-  o.p = p; o.sx = sx; o.sk = sk; o.xlim = xlim; o.klim = klim; o.scale = scale; o.xfast = xfast;
+  o.p = p; o.sx = (int)sx; o.sk = (int)sk; o.xlim = xlim; o.klim = klim; o.xfast = xfast;
   return o;
 }
 
 // Tile geometry: WM x WN wavefronts, each owning FM x FN blocks of 16x16
-// outputs; BK = 8 (two k=4 MFMA steps) per LDS stage.
-template <int WM_, int WN_, int FM_, int FN_>
+// outputs; BK (a multiple of 4) k values per LDS stage.
+template <int WM_, int WN_, int FM_, int FN_, int BK_ = 8>
 struct TileCfg {
   static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_;
   static constexpr int NW = WM * WN;
   static constexpr int NT = 64 * NW;
   static constexpr int BM = 16 * WM * FM;
   static constexpr int BN = 16 * WN * FN;
-  static constexpr int BK = 8;
-  static constexpr int LDA = BM + 16;  // row stride (doubles) of the k-major LDS tiles
-  static constexpr int LDB = BN + 16;
+  static constexpr int BK = BK_;
+  static constexpr int LDA = BM;  // k-major LDS tiles, XOR-swizzled (see lds_idx)
+  static constexpr int LDB = BN;
   static constexpr int EA = (BM * BK + NT - 1) / NT;
   static constexpr int EB = (BN * BK + NT - 1) / NT;
   static constexpr int STAGE = BK * (LDA + LDB);  // doubles per LDS stage
   static constexpr int LDS_DOUBLES = 2 * STAGE;
 };
 
-// Global -> registers for one (X x BK) stage of an operand, x0/k0 the tile origin.
+// LDS position of tile element (k, x) of a stage with BK rows: row k, with the
+// low four bits of x XOR-ed by a k-dependent pattern that spreads the BK rows
+// over the 16 slots of a 128-byte group (k for BK = 16, 2k for BK = 8).  A
+// fragment read (16 consecutive x of one row) stays a permutation of one
+// 128-byte group; a k-fast store (16 lanes covering BK rows and 16/BK adjacent
+// x) lands on 16 different 8-byte bank pairs instead of one.
+template <int BK>
+__device__ inline int lds_swz(int k) { return (k & (BK - 1)) * (16 / BK); }
+template <int BK>
+__device__ inline int lds_idx(int k, int x, int ld) { return k * ld + (x ^ lds_swz<BK>(k)); }
+
+// Per-thread element mapping of an (X x BK) stage: element e of thread `tid`
+// sits at (x_t + e*dx, k_t + e*dk).
+template <int X, int BK, int NT>
+struct StageMap {
+  static_assert(NT % BK == 0, "BK must divide the thread count");
+  static_assert(BK == 4 || BK == 8 || BK == 16, "BK must be 4, 8 or 16");
+  static constexpr bool XF_OK = (NT % X == 0);  // x-fast mapping keeps x fixed per thread
+  int x_t, k_t, dx, dk;
+  __device__ StageMap(bool xfast, int tid) {
+    if (xfast && XF_OK) { x_t = tid % X; k_t = tid / X; dx = 0; dk = NT / X; }
+    else { k_t = tid % BK; x_t = tid / BK; dx = NT / BK; dk = 0; }
+  }
+};
+
+// Global -> registers for one (X x BK) stage of an operand; x0/k0 the tile origin.
 template <int X, int BK, int E, int NT>
 __device__ inline void load_stage(const Opnd& o, int x0, int k0, double (&r)[E], int tid) {
+  const StageMap<X, BK, NT> mp(o.xfast, tid);
+  const double* base = o.p + ((int64_t)x0 * o.sx + (int64_t)k0 * o.sk);
+  const int off0 = mp.x_t * o.sx + mp.k_t * o.sk;
+  const int step = mp.dx * o.sx + mp.dk * o.sk;
+  const bool interior = (x0 + X <= o.xlim) && (k0 + BK <= o.klim);
+  if (interior) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int idx = e * NT + tid;
-    int x, k;
-    if (o.xfast) { x = idx % X; k = idx / X; } else { k = idx % BK; x = idx / BK; }
-    double v = 0.0;
-    if (idx < X * BK && x0 + x < o.xlim && k0 + k < o.klim)
-      v = o.p[(int64_t)(x0 + x) * o.sx + (int64_t)(k0 + k) * o.sk] * o.scale;
-    r[e] = v;
+    for (int e = 0; e < E; ++e) {
+      const bool in = (e * NT + tid) < X * BK;
+      r[e] = in ? base[off0 + e * step] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = x0 + mp.x_t + e * mp.dx, k = k0 + mp.k_t + e * mp.dk;
+      const bool in = (e * NT + tid) < X * BK && x < o.xlim && k < o.klim;
+      r[e] = in ? base[off0 + e * step] : 0.0;
+    }
   }
 }
 
-// Registers -> k-major LDS tile s[k * LD + x] (same element mapping as load_stage).
+// Registers -> swizzled k-major LDS tile (same element mapping as load_stage).
 template <int X, int BK, int E, int NT, int LD>
 __device__ inline void store_stage(bool xfast, const double (&r)[E], double* s, int tid) {
+  const StageMap<X, BK, NT> mp(xfast, tid);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int idx = e * NT + tid;
-    if (idx < X * BK) {
-      int x, k;
-      if (xfast) { x = idx % X; k = idx / X; } else { k = idx % BK; x = idx / BK; }
-      s[k * LD + x] = r[e];
-    }
+    if ((e * NT + tid) < X * BK) s[lds_idx<BK>(mp.k_t + e * mp.dk, mp.x_t + e * mp.dx, LD)] = r[e];
   }
 }
 
@@ -84,11 +113,12 @@ __device__ inline void mfma_stage(const double* sa, const double* sb, d4v (&acc)
 #pragma unroll
   for (int kk = 0; kk < T::BK / 4; ++kk) {
     const int kr = kk * 4 + (lane >> 4);
+    const int sw = (lane & 15) ^ lds_swz<T::BK>(kr);
     double a[T::FM], b[T::FN];
 #pragma unroll
-    for (int fm = 0; fm < T::FM; ++fm) a[fm] = sa[kr * T::LDA + (wm * T::FM + fm) * 16 + (lane & 15)];
+    for (int fm = 0; fm < T::FM; ++fm) a[fm] = sa[kr * T::LDA + (wm * T::FM + fm) * 16 + sw];
 #pragma unroll
-    for (int fn = 0; fn < T::FN; ++fn) b[fn] = sb[kr * T::LDB + (wn * T::FN + fn) * 16 + (lane & 15)];
+    for (int fn = 0; fn < T::FN; ++fn) b[fn] = sb[kr * T::LDB + (wn * T::FN + fn) * 16 + sw];
 #pragma unroll
     for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
@@ -117,13 +147,12 @@ __device__ inline void zero_acc(d4v (&acc)[T::FM][T::FN]) {
 }
 
 // The K loop: `ops(step, A, B, k0)` fills the operand views of K step `step`
-// (k0 = first k of the step within its operands); `after(step)` runs after the
-// MFMAs of each step (used to flush partial results).  Double-buffered LDS with
+// (k0 = first k of the step within its operands).  Double-buffered LDS with
 // one barrier per step; the next stage's global loads are in flight during the
 // current stage's MFMAs.
-template <class T, class Ops, class After>
-__device__ inline void k_loop(int nsteps, int m0, int n0, Ops ops, After after,
-                              d4v (&acc)[T::FM][T::FN], double* lds) {
+template <class T, class Ops>
+__device__ inline void k_loop(int nsteps, int m0, int n0, Ops ops, d4v (&acc)[T::FM][T::FN],
+                              double* lds) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
@@ -147,7 +176,6 @@ __device__ inline void k_loop(int nsteps, int m0, int n0, Ops ops, After after,
       load_stage<T::BN, T::BK, T::EB, T::NT>(B, n0, k0, rb, tid);
     }
     mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
-    after(s);
     if (more) {
       store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(A.xfast, ra, nxt, tid);
       store_stage<T::BN, T::BK, T::EB, T::NT, T::LDB>(B.xfast, rb, nxt + T::BK * T::LDA, tid);

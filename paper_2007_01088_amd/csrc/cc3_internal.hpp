@@ -36,12 +36,13 @@ struct Plan {
   unsigned flags;
   int ntri;     // unordered triples i >= j >= k, not all equal
   int batch;    // triples per batch of the triple loop
+  size_t pvv_entries;  // max (triples x b-chunks) of one Omega launch
   size_t cube;  // doubles per nv^3 cube
   // byte offsets into the workspace
   size_t off_Gw, off_Go, off_Gv, off_Jo, off_Hs, off_F;
-  size_t off_Ot1, off_Ot2, off_tri, off_flag, off_cubes;
+  size_t off_Ot1, off_Ot2, off_OtT, off_t2N, off_Pvv, off_Soo, off_tri, off_flag, off_cubes;
   size_t off_chol;  // Cholesky scratch (aliases the cube region)
-  size_t chol_bytes, cube_bytes;
+  size_t chol_bytes, cube_bytes, pvv_bytes, soo_bytes;  // per buffer set (two sets)
   size_t total;
 };
 
@@ -59,16 +60,25 @@ void launch_relayout_blocks(const double* g_vvvo, const double* g_oovo, const do
                             const double* g_ooov, const double* g_vvov, const double* F_ov,
                             const Blocks& b, int no, int nv, hipStream_t st);
 void launch_triple_table(int* tri, int no, hipStream_t st);
-void launch_wbuild(const double* t2, const Blocks& b, const int* tri, int ntri, double* cubes,
-                   int no, int nv, bool all_terms, hipStream_t st);
+void launch_t2N(const double* t2, double* t2N, int no, int nv, hipStream_t st);
+void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
+                   double* cubes, int no, int nv, bool all_terms, hipStream_t st);
 void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, int no, int nv,
                 hipStream_t st);
 void launch_tau_export(const double* eps, const int* tri, const double* cubes, double* tau, int no,
                        int nv, hipStream_t st);
-void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Ot1,
-                  double* Ot2, int no, int nv, hipStream_t st);
-void launch_back_transform(const double* Ot1, const double* Ot2, double* O1, double* O2, int no,
-                           int nv, bool accumulate, hipStream_t st);
+// Omega contraction of a batch into per-(triple, permutation) partial slabs Pvv
+// and Soo; then their fixed-order reduction into Ot1/Ot2/OtT (added, not overwritten).
+void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pvv,
+                  double* Soo, int no, int nv, hipStream_t st);
+void launch_reduce(const int* tri, int ntri, const double* Pvv, const double* Soo, double* Ot1,
+                   double* Ot2, double* OtT, int no, int nv, hipStream_t st);
+// Ot~2[p][q][a][b] = Ot2[p][q][a][b] + OtT[p][q][b][a]  (contravariant doubles residual)
+void launch_combine(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
+                    double* O2, int no, int nv, hipStream_t st);
+int omega_nbchunks(int nv, int ntri);
+void launch_back_transform(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
+                           double* O2, int no, int nv, bool accumulate, hipStream_t st);
 void launch_set_triples(int* tri_dev, const int* host_tri, int n, hipStream_t st);
 void launch_check(const double* eps, const double* L, const double* t2, int no, int nv, int nJ,
                   int* flag, hipStream_t st);

@@ -118,28 +118,38 @@ __global__ void k_fock_sm(const double* __restrict__ t1, const double* __restric
   }
 }
 
-__global__ void k_fock(const double* __restrict__ Lov, const double* __restrict__ s,
-                       const double* __restrict__ M, double* __restrict__ F, int no, int nv,
-                       int nJ) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= no * nv) return;
-  const int k = idx / nv, c = idx % nv;
+// F[k][c] for 64 consecutive c of one k; four slices of the Cholesky index
+// summed through LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_fock(const double* __restrict__ Lov,
+                                              const double* __restrict__ s,
+                                              const double* __restrict__ M, double* __restrict__ F,
+                                              int no, int nv, int nJ) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int js = threadIdx.x >> 6;
   double v = 0.0;
-  for (int J = 0; J < nJ; ++J) {
-    const double* LJ = Lov + (int64_t)J * no * nv;
-    double w = 2.0 * s[J] * LJ[(int64_t)k * nv + c];
-    const double* MJ = M + (int64_t)J * no * no + (int64_t)k * no;
-    for (int l = 0; l < no; ++l) w -= MJ[l] * LJ[(int64_t)l * nv + c];
-    v += w;
+  if (c < nv) {
+    for (int J = js; J < nJ; J += 4) {
+      const double* LJ = Lov + (int64_t)J * no * nv;
+      double w = 2.0 * s[J] * LJ[(int64_t)k * nv + c];
+      const double* MJ = M + (int64_t)J * no * no + (int64_t)k * no;
+      for (int l = 0; l < no; ++l) w -= MJ[l] * LJ[(int64_t)l * nv + c];
+      v += w;
+    }
   }
-  F[idx] = v;
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (js == 0 && c < nv)
+    F[(int64_t)k * nv + c] = (red[threadIdx.x] + red[threadIdx.x + 64]) +
+                             (red[threadIdx.x + 128] + red[threadIdx.x + 192]);
 }
 
 void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no, int nv, int nJ,
                  hipStream_t st) {
   hipLaunchKernelGGL(k_fock_sm, dim3(nJ), dim3(256), 0, st, t1, cs.Lov, cs.s, cs.M, no, nv);
-  hipLaunchKernelGGL(k_fock, dim3(nblk((int64_t)no * nv, 128)), dim3(128), 0, st, cs.Lov, cs.s,
-                     cs.M, F, no, nv, nJ);
+  hipLaunchKernelGGL(k_fock, dim3(no, nblk(nv, 64)), dim3(256), 0, st, cs.Lov, cs.s, cs.M, F, no,
+                     nv, nJ);
 }
 
 // ---------------------------------------------------------------------------
@@ -148,9 +158,9 @@ void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no,
 // ---------------------------------------------------------------------------
 enum BuildKind { BUILD_PLAIN = 0, BUILD_JO = 1, BUILD_HS = 2, BUILD_GO = 3 };
 
-typedef TileCfg<2, 2, 4, 4> BuildCfg;
+typedef TileCfg<2, 2, 4, 4, 16> BuildCfg;
 
-__global__ __launch_bounds__(BuildCfg::NT) void k_build(
+__global__ __launch_bounds__(BuildCfg::NT, 2) void k_build(
     const double* __restrict__ Ap, int64_t a_sm, int64_t a_sk, int64_t a_bs,
     const double* __restrict__ Bp, int64_t b_sk, int64_t b_sn, int64_t b_bs, int M, int N, int K,
     double* __restrict__ C, int64_t c_bs, int kind, int no, int nv, const double* __restrict__ F) {
@@ -167,11 +177,10 @@ __global__ __launch_bounds__(BuildCfg::NT) void k_build(
   const int nsteps = (K + T::BK - 1) / T::BK;
   auto ops = [&](int s, Opnd& oa, Opnd& ob, int& k0) {
     k0 = s * T::BK;
-    oa = make_opnd(A, a_sm, a_sk, M, K, 1.0, true);
-    ob = make_opnd(B, b_sn, b_sk, N, K, 1.0, true);
+    oa = make_opnd(A, a_sm, a_sk, M, K, true);
+    ob = make_opnd(B, b_sn, b_sk, N, K, true);
   };
-  auto none = [](int) {};
-  k_loop<T>(nsteps, m0, n0, ops, none, acc, lds);
+  k_loop<T>(nsteps, m0, n0, ops, acc, lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
   double* Cz = C + (int64_t)z * c_bs;
@@ -305,30 +314,56 @@ void launch_set_triples(int* tri_dev, const int* host_tri, int n, hipStream_t st
 }
 
 // ---------------------------------------------------------------------------
-// Covariant back-transformation:
+// Covariant back-transformation.  The contravariant doubles residual is held
+// in two parts, Ot~[i][j][a][b] = Ot2[i][j][a][b] + OtT[i][j][b][a]; then
 //   Omega^a_i = Ot^a_i
-//   Omega^{ab}_{ij} = 1/3 [(2 Ot^{ab}_{ij} + Ot^{ba}_{ij}) + (2 Ot^{ba}_{ji} + Ot^{ab}_{ji})]
+//   Omega^{ab}_{ij} = 1/3 [(2 Ot~^{ab}_{ij} + Ot~^{ba}_{ij}) + (2 Ot~^{ba}_{ji} + Ot~^{ab}_{ji})]
 // ---------------------------------------------------------------------------
+__device__ inline double ot2(const double* __restrict__ Ot2, const double* __restrict__ OtT,
+                             int64_t ij, int64_t nv, int a, int b) {
+  return Ot2[(ij + a) * nv + b] + OtT[(ij + b) * nv + a];
+}
+
 __global__ void k_back(const double* __restrict__ Ot1, const double* __restrict__ Ot2,
-                       double* __restrict__ O1, double* __restrict__ O2, int no, int nv, int acc) {
-  const int64_t n2 = (int64_t)no * no * nv * nv;
+                       const double* __restrict__ OtT, double* __restrict__ O1,
+                       double* __restrict__ O2, int no, int nv, int acc) {
+  const int64_t nvl = nv, n2 = (int64_t)no * no * nvl * nvl;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n2) {
-    const int b = (int)(e % nv), a = (int)((e / nv) % nv);
-    const int j = (int)((e / ((int64_t)nv * nv)) % no), i = (int)(e / ((int64_t)nv * nv * no));
-    const int64_t ij = ((int64_t)i * no + j) * nv, ji = ((int64_t)j * no + i) * nv;
-    const double v = (2.0 * Ot2[(ij + a) * nv + b] + Ot2[(ij + b) * nv + a] +
-                      2.0 * Ot2[(ji + b) * nv + a] + Ot2[(ji + a) * nv + b]) / 3.0;
+    const int b = (int)(e % nvl), a = (int)((e / nvl) % nvl);
+    const int j = (int)((e / (nvl * nvl)) % no), i = (int)(e / (nvl * nvl * no));
+    const int64_t ij = ((int64_t)i * no + j) * nvl, ji = ((int64_t)j * no + i) * nvl;
+    const double v = (2.0 * ot2(Ot2, OtT, ij, nvl, a, b) + ot2(Ot2, OtT, ij, nvl, b, a) +
+                      2.0 * ot2(Ot2, OtT, ji, nvl, b, a) + ot2(Ot2, OtT, ji, nvl, a, b)) / 3.0;
     O2[e] = acc ? O2[e] + v : v;
   }
   if (e < (int64_t)no * nv) O1[e] = acc ? O1[e] + Ot1[e] : Ot1[e];
 }
 
-void launch_back_transform(const double* Ot1, const double* Ot2, double* O1, double* O2, int no,
-                           int nv, bool accumulate, hipStream_t st) {
+void launch_back_transform(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
+                           double* O2, int no, int nv, bool accumulate, hipStream_t st) {
   const int64_t n2 = (int64_t)no * no * nv * nv;
-  hipLaunchKernelGGL(k_back, dim3(nblk(n2, 256)), dim3(256), 0, st, Ot1, Ot2, O1, O2, no, nv,
+  hipLaunchKernelGGL(k_back, dim3(nblk(n2, 256)), dim3(256), 0, st, Ot1, Ot2, OtT, O1, O2, no, nv,
                      accumulate ? 1 : 0);
+}
+
+__global__ void k_combine(const double* __restrict__ Ot1, const double* __restrict__ Ot2,
+                          const double* __restrict__ OtT, double* __restrict__ O1,
+                          double* __restrict__ O2, int no, int nv) {
+  const int64_t nvl = nv, n2 = (int64_t)no * no * nvl * nvl;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n2) {
+    const int b = (int)(e % nvl), a = (int)((e / nvl) % nvl);
+    O2[e] = ot2(Ot2, OtT, (e / (nvl * nvl)) * nvl, nvl, a, b);
+  }
+  if (e < (int64_t)no * nv) O1[e] = Ot1[e];
+}
+
+void launch_combine(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
+                    double* O2, int no, int nv, hipStream_t st) {
+  const int64_t n2 = (int64_t)no * no * nv * nv;
+  hipLaunchKernelGGL(k_combine, dim3(nblk(n2, 256)), dim3(256), 0, st, Ot1, Ot2, OtT, O1, O2, no,
+                     nv);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,7 +20,11 @@
 //              Ot2[p][q][a][d] += sum_bc U[a,b,c] g_{dbrc}    (columns d < nv)
 //              Ot1[p][a]       += sum_bc U[a,b,c] g_{qbrc}    (column nv)
 //              Ot2[p][l][a][b] += sum_c  U[a,b,c] (delta_lq F_rc - g_{qlrc})  (separate
-//                                 accumulator blocks, flushed after every b)
+//                                 accumulator blocks, stored after every b)
+//            written as per-(triple, permutation) partial slabs with plain stores;
+//            the last term is kept transposed, OtT[p][l][b][a], so that its
+//            stores run along a;
+//  k_reduce  adds the slabs into Ot1/Ot2/OtT in a fixed order (deterministic, no atomics).
 #include "cc3_device.hpp"
 #include "cc3_internal.hpp"
 
@@ -31,10 +35,30 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 // triple kinds
 enum { TRI_DISTINCT = 0, TRI_IJ = 1, TRI_JK = 2 };
 
-__device__ inline int tri_kind(int i, int j, int k) {
+__host__ __device__ inline int tri_kind(int i, int j, int k) {
   if (i == j) return TRI_IJ;  // i == j > k
   if (j == k) return TRI_JK;  // i > j == k
   return TRI_DISTINCT;
+}
+
+// The occupied permutation pi of (i,j,k) used for the contravariant contributions:
+// 0 (i,j,k)  1 (j,i,k)  2 (k,j,i)  3 (i,k,j)  4 (j,k,i)  5 (k,i,j).
+// All six are distinct when i, j, k differ; {0,2,3} when i == j; {0,1,2} when j == k.
+__host__ __device__ inline bool perm_active(int kind, int pi) {
+  if (kind == TRI_IJ) return pi == 0 || pi == 2 || pi == 3;
+  if (kind == TRI_JK) return pi <= 2;
+  return true;
+}
+
+__host__ __device__ inline void perm_pqr(int pi, int i, int j, int k, int& p, int& q, int& r) {
+  switch (pi) {
+    case 0: p = i; q = j; r = k; break;
+    case 1: p = j; q = i; r = k; break;
+    case 2: p = k; q = j; r = i; break;
+    case 3: p = i; q = k; r = j; break;
+    case 4: p = j; q = k; r = i; break;
+    default: p = k; q = i; r = j; break;
+  }
 }
 
 // cube slots of one triple's workspace
@@ -43,9 +67,10 @@ enum { SLOT_P0 = 0, SLOT_P1 = 1, SLOT_P2 = 2, SLOT_TT = 3, SLOT_TTT = 4, NSLOT =
 // ---------------------------------------------------------------------------
 // W build
 // ---------------------------------------------------------------------------
-typedef TileCfg<4, 1, 2, 8> WCfg;  // 128 x 128 output plane tile
+typedef TileCfg<4, 1, 2, 8, 16> WCfg;  // 128 x 128 output plane tile, 16 k per stage
 
 __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ t2,
+                                                     const double* __restrict__ t2N,
                                                      const double* __restrict__ Gw,
                                                      const double* __restrict__ Go,
                                                      const int* __restrict__ tri,
@@ -73,16 +98,17 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
   const int nvs = (nv + T::BK - 1) / T::BK, nos = (no + T::BK - 1) / T::BK;
   const int nsteps = two ? 2 * (nvs + nos) : (nvs + nos);
 
-  // term 1: Acc[m][n] += sum_d t2[p1][q1][m][d] Gw[r1][y][d][n] - sum_l t2[p1][l][m][y] Go[q1][r1][l][n]
-  // term 2: Acc[m][n] += sum_d Gw[r2][y][d][m] t2[p2][q2][n][d] - sum_l Go[q2][r2][l][m] t2[p2][l][n][y]
+  // term 1: Acc[m][n] += sum_d t2[p1][q1][m][d] Gw[r1][y][d][n] + sum_l t2N[p1][y][m][l] Go[q1][r1][l][n]
+  // term 2: Acc[m][n] += sum_d Gw[r2][y][d][m] t2[p2][q2][n][d] + sum_l Go[q2][r2][l][m] t2N[p2][y][n][l]
+  // with t2N[p][y][x][l] = -t2[p][l][x][y] (contiguous in l).
   const double* a0 = t2 + ((int64_t)p1 * no + q1) * nv2;
   const double* b0 = Gw + ((int64_t)r1 * nv + y) * nv2;
-  const double* a1 = t2 + (int64_t)p1 * no * nv2 + y;
+  const double* a1 = t2N + ((int64_t)p1 * nv + y) * nv * no;
   const double* b1 = Go + ((int64_t)q1 * no + r1) * no * nv;
   const double* a2 = Gw + ((int64_t)r2 * nv + y) * nv2;
   const double* b2 = t2 + ((int64_t)p2 * no + q2) * nv2;
   const double* a3 = Go + ((int64_t)q2 * no + r2) * no * nv;
-  const double* b3 = t2 + (int64_t)p2 * no * nv2 + y;
+  const double* b3 = t2N + ((int64_t)p2 * nv + y) * nv * no;
 
   auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
     int seg = 0, ls = s;
@@ -91,23 +117,22 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
         if (ls >= nvs) { ls -= nvs; seg = 3; } } }
     k0 = ls * T::BK;
     if (seg == 0) {
-      A = make_opnd(a0, nv, 1, nv, nv, 1.0, false);
-      B = make_opnd(b0, 1, nv, nv, nv, 1.0, true);
+      A = make_opnd(a0, nv, 1, nv, nv, false);
+      B = make_opnd(b0, 1, nv, nv, nv, true);
     } else if (seg == 1) {
-      A = make_opnd(a1, nv, nv2, nv, no, -1.0, true);
-      B = make_opnd(b1, 1, nv, nv, no, 1.0, true);
+      A = make_opnd(a1, no, 1, nv, no, false);
+      B = make_opnd(b1, 1, nv, nv, no, true);
     } else if (seg == 2) {
-      A = make_opnd(a2, 1, nv, nv, nv, 1.0, true);
-      B = make_opnd(b2, nv, 1, nv, nv, 1.0, false);
+      A = make_opnd(a2, 1, nv, nv, nv, true);
+      B = make_opnd(b2, nv, 1, nv, nv, false);
     } else {
-      A = make_opnd(a3, 1, nv, nv, no, 1.0, true);
-      B = make_opnd(b3, nv, nv2, nv, no, -1.0, true);
+      A = make_opnd(a3, 1, nv, nv, no, true);
+      B = make_opnd(b3, no, 1, nv, no, false);
     }
   };
-  auto none = [](int) {};
   d4v acc[T::FM][T::FN];
   zero_acc<T>(acc);
-  k_loop<T>(nsteps, m0, n0, ops, none, acc, lds);
+  k_loop<T>(nsteps, m0, n0, ops, acc, lds);
 
   double* out = cubes + ((int64_t)z * NSLOT + plane) * nv3 + (int64_t)y * nv2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -124,12 +149,27 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
       }
 }
 
-void launch_wbuild(const double* t2, const Blocks& b, const int* tri, int ntri, double* cubes,
-                   int no, int nv, bool all_terms, hipStream_t st) {
+void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
+                   double* cubes, int no, int nv, bool all_terms, hipStream_t st) {
   typedef WCfg T;
   const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + T::BN - 1) / T::BN;
-  hipLaunchKernelGGL(k_wbuild, dim3(nv * tm * tn, 3, ntri), dim3(T::NT), 0, st, t2, b.Gw, b.Go,
-                     tri, cubes, no, nv, tm, tn, all_terms ? 1 : 0);
+  hipLaunchKernelGGL(k_wbuild, dim3(nv * tm * tn, 3, ntri), dim3(T::NT), 0, st, t2, t2N, b.Gw,
+                     b.Go, tri, cubes, no, nv, tm, tn, all_terms ? 1 : 0);
+}
+
+// t2N[p][y][x][l] = -t2[p][l][x][y]
+__global__ void k_t2N(const double* __restrict__ t2, double* __restrict__ t2N, int no, int nv) {
+  const int64_t nvl = nv, n = (int64_t)no * no * nvl * nvl;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int l = (int)(e % no), x = (int)((e / no) % nvl), y = (int)((e / (no * nvl)) % nvl);
+  const int p = (int)(e / (no * nvl * nvl));
+  t2N[e] = -t2[(((int64_t)p * no + l) * nvl + x) * nvl + y];
+}
+
+void launch_t2N(const double* t2, double* t2N, int no, int nv, hipStream_t st) {
+  const int64_t n = (int64_t)no * no * nv * nv;
+  hipLaunchKernelGGL(k_t2N, dim3(nblk(n, 256)), dim3(256), 0, st, t2, t2N, no, nv);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,9 +177,22 @@ void launch_wbuild(const double* t2, const Blocks& b, const int* tri, int ntri, 
 // ---------------------------------------------------------------------------
 #define MT 8
 #define MT3 (MT * MT * MT)
+// padded LDS position of tile element (u, v, w): strides 73 and 9 keep every
+// permuted access pattern of the orbit conflict-free across 8 lanes
+#define TP(u, v, w) ((u) * 73 + (v) * 9 + (w))
+#define TSZ 584
 
 // the six orientations of a block triple, as positions into (A, B, C)
-__constant__ int c_orient[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+__host__ __device__ inline void orient(int o, int& p0, int& p1, int& p2) {
+  switch (o) {
+    case 0: p0 = 0; p1 = 1; p2 = 2; break;
+    case 1: p0 = 0; p1 = 2; p2 = 1; break;
+    case 2: p0 = 1; p1 = 0; p2 = 2; break;
+    case 3: p0 = 1; p1 = 2; p2 = 0; break;
+    case 4: p0 = 2; p1 = 0; p2 = 1; break;
+    default: p0 = 2; p1 = 1; p2 = 0; break;
+  }
+}
 
 __device__ inline int orient_of(int p0, int p1) {
   // the orientation index whose first two positions are (p0, p1)
@@ -176,74 +229,143 @@ __device__ inline double xval(const double* __restrict__ cz, int kind, int64_t n
 __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
                                              const int* __restrict__ tri,
                                              double* __restrict__ cubes, int no, int nv) {
-  __shared__ double Xs[6 * MT3];
-  __shared__ double Ts[6 * MT3];
-  __shared__ int blk3[3];
+  __shared__ double Xs[6 * TSZ];
   const int z = blockIdx.y;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   const int kind = tri_kind(i, j, k);
-  const int64_t nvl = nv, nv3 = nvl * nvl * nvl;
+  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
   double* cz = cubes + (int64_t)z * NSLOT * nv3;
-  if (threadIdx.x == 0) {
-    int A, B, C;
-    decode_block_triple(blockIdx.x, A, B, C);
-    blk3[0] = A; blk3[1] = B; blk3[2] = C;
-  }
-  __syncthreads();
+  int blk[3];
+  decode_block_triple(blockIdx.x, blk[0], blk[1], blk[2]);
   const double eijk = eps[i] + eps[j] + eps[k];
-  // 1. X on the orbit
-  for (int e = threadIdx.x; e < 6 * MT3; e += 256) {
-    const int o = e / MT3, u = (e / (MT * MT)) % MT, v = (e / MT) % MT, w = e % MT;
-    const int a = blk3[c_orient[o][0]] * MT + u;
-    const int b = blk3[c_orient[o][1]] * MT + v;
-    const int c = blk3[c_orient[o][2]] * MT + w;
-    Xs[e] = (a < nv && b < nv && c < nv) ? xval(cz, kind, nvl, a, b, c) : 0.0;
+  const double* P0 = cz + SLOT_P0 * nv3;
+  const double* P1 = cz + SLOT_P1 * nv3;
+  const double* P2 = cz + SLOT_P2 * nv3;
+  const int t = threadIdx.x;
+  // 1. X on the orbit.  Each orientation tile is summed in up to three passes
+  //    whose thread mapping makes the contiguous index of the cubes read in
+  //    that pass the fastest one (c, b, then a).
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
+    const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = t + 256 * h;
+      const int u = e >> 6, v = (e >> 3) & 7, w = e & 7;  // pass 0: c fastest
+      const int a = A0 + u, b = B0 + v, c = C0 + w;
+      double x = 0.0;
+      if (a < nv && b < nv && c < nv)
+        x = P0[b * nv2 + a * nvl + c] + (kind == TRI_IJ ? P0 : P1)[a * nv2 + b * nvl + c];
+      Xs[o * TSZ + TP(u, v, w)] = x;
+    }
   }
   __syncthreads();
-  // 2. tau~ on the orbit
-  for (int e = threadIdx.x; e < 6 * MT3; e += 256) {
-    const int o = e / MT3, u = (e / (MT * MT)) % MT, v = (e / MT) % MT, w = e % MT;
-    const int p0 = c_orient[o][0], p1 = c_orient[o][1], p2 = c_orient[o][2];
-    const int a = blk3[p0] * MT + u, b = blk3[p1] * MT + v, c = blk3[p2] * MT + w;
-    double t = 0.0;
-    if (a < nv && b < nv && c < nv) {
-      // X at permuted virtual labels: (a,c,b), (c,b,a), (b,a,c), (b,c,a), (c,a,b)
-      const double x_abc = Xs[e];
-      const double x_acb = Xs[orient_of(p0, p2) * MT3 + (u * MT + w) * MT + v];
-      const double x_cba = Xs[orient_of(p2, p1) * MT3 + (w * MT + v) * MT + u];
-      const double x_bac = Xs[orient_of(p1, p0) * MT3 + (v * MT + u) * MT + w];
-      const double x_bca = Xs[orient_of(p1, p2) * MT3 + (v * MT + w) * MT + u];
-      const double x_cab = Xs[orient_of(p2, p0) * MT3 + (w * MT + u) * MT + v];
-      const double D = eps[no + a] + eps[no + b] + eps[no + c] - eijk;
-      t = -(4.0 * x_abc - 2.0 * x_acb - 2.0 * x_cba - 2.0 * x_bac + x_bca + x_cab) / D;
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
+    const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = t + 256 * h;
+      const int u = e >> 6, w = (e >> 3) & 7, v = e & 7;  // pass 1: b fastest
+      const int a = A0 + u, b = B0 + v, c = C0 + w;
+      if (a < nv && b < nv && c < nv) {
+        double x;
+        if (kind == TRI_JK) x = P1[a * nv2 + c * nvl + b] + P0[c * nv2 + a * nvl + b];
+        else x = P2[c * nv2 + a * nvl + b];
+        Xs[o * TSZ + TP(u, v, w)] += x;
+      }
     }
-    Ts[e] = t;
   }
+  if (kind == TRI_IJ) {
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+      int q0, q1, q2;
+      orient(o, q0, q1, q2);
+      const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = t + 256 * h;
+        const int v = e >> 6, w = (e >> 3) & 7, u = e & 7;  // pass 2: a fastest
+        const int a = A0 + u, b = B0 + v, c = C0 + w;
+        if (a < nv && b < nv && c < nv) Xs[o * TSZ + TP(u, v, w)] += P2[c * nv2 + b * nvl + a];
+      }
+    }
+  }
+  __syncthreads();
+  // 2. tau~ on the orbit, held in registers until every thread has read X
+  double tt[6][2];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
+    const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
+    const int o_acb = orient_of(q0, q2), o_cba = orient_of(q2, q1), o_bac = orient_of(q1, q0);
+    const int o_bca = orient_of(q1, q2), o_cab = orient_of(q2, q0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = t + 256 * h;
+      const int u = e >> 6, v = (e >> 3) & 7, w = e & 7;
+      const int a = A0 + u, b = B0 + v, c = C0 + w;
+      double val = 0.0;
+      if (a < nv && b < nv && c < nv) {
+        // X at permuted virtual labels: (a,c,b), (c,b,a), (b,a,c), (b,c,a), (c,a,b)
+        const double x_abc = Xs[o * TSZ + TP(u, v, w)];
+        const double x_acb = Xs[o_acb * TSZ + TP(u, w, v)];
+        const double x_cba = Xs[o_cba * TSZ + TP(w, v, u)];
+        const double x_bac = Xs[o_bac * TSZ + TP(v, u, w)];
+        const double x_bca = Xs[o_bca * TSZ + TP(v, w, u)];
+        const double x_cab = Xs[o_cab * TSZ + TP(w, u, v)];
+        const double D = eps[no + a] + eps[no + b] + eps[no + c] - eijk;
+        val = -(4.0 * x_abc - 2.0 * x_acb - 2.0 * x_cba - 2.0 * x_bac + x_bca + x_cab) / D;
+      }
+      tt[o][h] = val;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < 6; ++o)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = t + 256 * h;
+      Xs[o * TSZ + TP(e >> 6, (e >> 3) & 7, e & 7)] = tt[o][h];
+    }
   __syncthreads();
   // 3. write tau~[a][b][c] (w fastest) and tau~T[a][c][b] (v fastest), skipping
   //    orientations that repeat an earlier one (equal blocks)
   double* TT = cz + SLOT_TT * nv3;
   double* TTT = cz + SLOT_TTT * nv3;
-  for (int e = threadIdx.x; e < 6 * MT3; e += 256) {
-    const int o = e / MT3;
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
     bool dup = false;
-    for (int o2 = 0; o2 < o; ++o2)
-      dup |= (blk3[c_orient[o2][0]] == blk3[c_orient[o][0]] &&
-              blk3[c_orient[o2][1]] == blk3[c_orient[o][1]] &&
-              blk3[c_orient[o2][2]] == blk3[c_orient[o][2]]);
-    if (dup) continue;
-    {  // tau~, element (u, v, w) with w fastest
-      const int u = (e / (MT * MT)) % MT, v = (e / MT) % MT, w = e % MT;
-      const int a = blk3[c_orient[o][0]] * MT + u, b = blk3[c_orient[o][1]] * MT + v,
-                c = blk3[c_orient[o][2]] * MT + w;
-      if (a < nv && b < nv && c < nv) TT[(a * nvl + b) * nvl + c] = Ts[e];
+#pragma unroll
+    for (int o2 = 0; o2 < 6; ++o2) {
+      if (o2 >= o) break;
+      int r0, r1, r2;
+      orient(o2, r0, r1, r2);
+      dup |= (blk[r0] == blk[q0] && blk[r1] == blk[q1] && blk[r2] == blk[q2]);
     }
-    {  // tau~T, element (u, w, v) with v fastest
-      const int u = (e / (MT * MT)) % MT, w = (e / MT) % MT, v = e % MT;
-      const int a = blk3[c_orient[o][0]] * MT + u, b = blk3[c_orient[o][1]] * MT + v,
-                c = blk3[c_orient[o][2]] * MT + w;
-      if (a < nv && b < nv && c < nv)
-        TTT[(a * nvl + c) * nvl + b] = Ts[o * MT3 + (u * MT + v) * MT + w];
+    if (dup) continue;
+    const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = t + 256 * h;
+      {
+        const int u = e >> 6, v = (e >> 3) & 7, w = e & 7;
+        const int a = A0 + u, b = B0 + v, c = C0 + w;
+        if (a < nv && b < nv && c < nv) TT[(a * nvl + b) * nvl + c] = Xs[o * TSZ + TP(u, v, w)];
+      }
+      {
+        const int u = e >> 6, w = (e >> 3) & 7, v = e & 7;
+        const int a = A0 + u, b = B0 + v, c = C0 + w;
+        if (a < nv && b < nv && c < nv) TTT[(a * nvl + c) * nvl + b] = Xs[o * TSZ + TP(u, v, w)];
+      }
     }
   }
 }
@@ -278,40 +400,34 @@ void launch_tau_export(const double* eps, const int* tri, const double* cubes, d
 // ---------------------------------------------------------------------------
 // Omega contraction
 // ---------------------------------------------------------------------------
-// Output columns of one (triple, permutation) GEMM over K = (b, c):
-//   n < nv       : d of Ot2[p][q][a][d]    (B = Gv[r][b][d][c])
-//   n == nv      : Ot1[p][a]               (B = Jo[q][r][b][c])
-// plus, in separate accumulator blocks owned by the first N tile,
-//   l < no       : Ot2[p][l][a][b]         (B = Hs[q][r][l][c]), flushed per b.
-typedef TileCfg<4, 1, 2, 8> OCfg;  // 128 x 128 for the (d, Omega1) columns
+// One (triple, permutation) GEMM over K = (b, c), rows a:
+//   vv columns d < nv          : Ot2[p][q][a][d] += sum_bc U[a,b,c] Gv[r][b][d][c]
+// and a second, transposed product (rows l, columns a) owned by the first N tile:
+//   rows l < no                : Ot2[p][l][a][b] += sum_c U[a,b,c] Hs[q][r][l][c]
+//                                (complete after each b, stored as SooT[z][pi][l][b][a])
+//   row l == no                : Ot1[p][a] += sum_bc U[a,b,c] Jo[q][r][b][c]
+//                                (summed over the chunk's b in registers)
+// Partial results: Pvv[z][pi][chunk][a][n] (n < nv: d columns, n == nv: Omega1),
+// SooT[z][pi][l][b][a].
+typedef TileCfg<4, 1, 2, 8, 8> OCfg;  // 128 x 128 vv tile
 
 template <int FNO>
-__global__ __launch_bounds__(OCfg::NT) void k_omega(
+__global__ __launch_bounds__(OCfg::NT, FNO == 1 ? 2 : 1) void k_omega(
     const double* __restrict__ cubes, const double* __restrict__ Gv, const double* __restrict__ Jo,
-    const double* __restrict__ Hs, const int* __restrict__ tri, double* __restrict__ Ot1,
-    double* __restrict__ Ot2, int no, int nv, int bchunk, int nbchunks, int tiles_n) {
+    const double* __restrict__ Hs, const int* __restrict__ tri, double* __restrict__ Pvv,
+    double* __restrict__ Soo, int no, int nv, int bchunk, int nbchunks, int tiles_n) {
   typedef OCfg T;
-  constexpr int BO = 16 * FNO;            // oo columns per tile
-  constexpr int LDO = BO + 16;
+  constexpr int BO = 16 * FNO;  // oo rows per tile (no of them used, plus the Omega1 row)
   constexpr int EO = (BO * T::BK + T::NT - 1) / T::NT;
-  constexpr int STAGE = T::BK * (T::LDA + T::LDB + LDO);
+  constexpr int STAGE = T::BK * (T::LDA + T::LDB + BO);
   __shared__ double lds[2 * STAGE];
   const int pi = blockIdx.y;
   const int z = blockIdx.z;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   const int kind = tri_kind(i, j, k);
-  // distinct occupied permutations: all six, {0,2,3} when i == j, {0,1,2} when j == k
-  if (kind == TRI_IJ && (pi == 1 || pi == 4 || pi == 5)) return;
-  if (kind == TRI_JK && pi >= 3) return;
+  if (!perm_active(kind, pi)) return;
   int p, q, r;
-  switch (pi) {
-    case 0: p = i; q = j; r = k; break;
-    case 1: p = j; q = i; r = k; break;
-    case 2: p = k; q = j; r = i; break;
-    case 3: p = i; q = k; r = j; break;
-    case 4: p = j; q = k; r = i; break;
-    default: p = k; q = i; r = j; break;
-  }
+  perm_pqr(pi, i, j, k, p, q, r);
   const int bc = blockIdx.x % nbchunks;
   const int tile = blockIdx.x / nbchunks;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
@@ -321,19 +437,19 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
   if (bb0 >= bb1) return;
 
   const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
-  const double* TT = cubes + ((int64_t)z * NSLOT + SLOT_TT) * nv3;
-  const double* TTT = cubes + ((int64_t)z * NSLOT + SLOT_TTT) * nv3;
+  const int NV1 = nv + 1;
+  const double* cz = cubes + (int64_t)z * NSLOT * nv3;
   // U_pi[a, b, c] at fixed b as a strided (a, c) view: base + b * sbb, (sm, sk)
-  const double* ub;
-  int64_t sbb, sm, sk;
+  int slot, sbb, sm, sk;
   switch (pi) {
-    case 0: ub = TT; sbb = nvl; sm = nv2; sk = 1; break;     // tau~[a][b][c]
-    case 1: ub = TT; sbb = nv2; sm = nvl; sk = 1; break;     // tau~[b][a][c]
-    case 2: ub = TT; sbb = nvl; sm = 1; sk = nv2; break;     // tau~[c][b][a]
-    case 3: ub = TTT; sbb = nvl; sm = nv2; sk = 1; break;    // tau~[a][c][b] = tau~T[a][b][c]
-    case 4: ub = TTT; sbb = nvl; sm = 1; sk = nv2; break;    // tau~[c][a][b] = tau~T[c][b][a]
-    default: ub = TT; sbb = nv2; sm = 1; sk = nvl; break;    // tau~[b][c][a]
+    case 0: slot = SLOT_TT; sbb = nv; sm = nv * nv; sk = 1; break;    // tau~[a][b][c]
+    case 1: slot = SLOT_TT; sbb = nv * nv; sm = nv; sk = 1; break;    // tau~[b][a][c]
+    case 2: slot = SLOT_TT; sbb = nv; sm = 1; sk = nv * nv; break;    // tau~[c][b][a]
+    case 3: slot = SLOT_TTT; sbb = nv; sm = nv * nv; sk = 1; break;   // tau~[a][c][b] = tau~T[a][b][c]
+    case 4: slot = SLOT_TTT; sbb = nv; sm = 1; sk = nv * nv; break;   // tau~[c][a][b] = tau~T[c][b][a]
+    default: slot = SLOT_TT; sbb = nv * nv; sm = 1; sk = nv; break;   // tau~[b][c][a]
   }
+  const double* ub = cz + slot * nv3;
   const bool afast = (sm == 1);
   const int cs = (nv + T::BK - 1) / T::BK;  // c steps per b
   const int nsteps = (bb1 - bb0) * cs;
@@ -345,46 +461,46 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
   d4v acc[T::FM][T::FN];
-  d4v aco[T::FM][FNO];
+  d4v aco[FNO][T::FM];  // rows l = f*16 + lane/16 + 4r, columns a = m0 + (wm*FM + fm)*16 + lane%16
   zero_acc<T>(acc);
 #pragma unroll
-  for (int fm = 0; fm < T::FM; ++fm)
+  for (int f = 0; f < FNO; ++f)
 #pragma unroll
-    for (int f = 0; f < FNO; ++f) aco[fm][f] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int fm = 0; fm < T::FM; ++fm) aco[f][fm] = d4v{0.0, 0.0, 0.0, 0.0};
+  double om1[T::FM];  // Omega1 partial for this lane's a columns (held by the lanes of row no)
+#pragma unroll
+  for (int fm = 0; fm < T::FM; ++fm) om1[fm] = 0.0;
   double ra[T::EA], rb[T::EB], ro[EO];
+  // oo rows: thread -> (c = k_t, l = x_t + e * NT/BK), the same mapping store_stage uses
+  const int ok_t = tid % T::BK, ox_t = tid / T::BK;
+  constexpr int ODX = T::NT / T::BK;
 
   auto load = [&](int s) {
     const int b = bb0 + s / cs, c0 = (s % cs) * T::BK;
-    const Opnd A = make_opnd(ub + (int64_t)b * sbb, sm, sk, nv, nv, 1.0, afast);
+    const Opnd A = make_opnd(ub + (int64_t)b * sbb, sm, sk, nv, nv, afast);
     load_stage<T::BM, T::BK, T::EA, T::NT>(A, m0, c0, ra, tid);
-    const double* gb = Gr + (int64_t)b * nv2;
-    const double* jb = Jqr + (int64_t)b * nvl;
-#pragma unroll
-    for (int e = 0; e < T::EB; ++e) {
-      const int idx = e * T::NT + tid;
-      const int kk = idx % T::BK, n = n0 + idx / T::BK, c = c0 + kk;
-      double v = 0.0;
-      if (idx < T::BN * T::BK && c < nv) {
-        if (n < nv) v = gb[(int64_t)n * nvl + c];
-        else if (n == nv) v = jb[c];
-      }
-      rb[e] = v;
-    }
+    const Opnd B = make_opnd(Gr + (int64_t)b * nv2, nv, 1, nv, nv, false);
+    load_stage<T::BN, T::BK, T::EB, T::NT>(B, n0, c0, rb, tid);
     if (do_oo) {
+      const int c = c0 + ok_t;
 #pragma unroll
       for (int e = 0; e < EO; ++e) {
-        const int idx = e * T::NT + tid;
-        const int kk = idx % T::BK, l = idx / T::BK, c = c0 + kk;
-        ro[e] = (idx < BO * T::BK && c < nv && l < no) ? Hqr[(int64_t)l * nvl + c] : 0.0;
+        const int l = ox_t + e * ODX;
+        const double* src = (l < no) ? Hqr + (int64_t)l * nvl : Jqr + (int64_t)b * nvl;
+        const bool in = (e * T::NT + tid) < BO * T::BK && c < nv && l <= no;
+        double v = 0.0;
+        if (in) v = src[c];
+        ro[e] = v;
       }
     }
   };
   auto store = [&](double* st) {
     store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(afast, ra, st, tid);
     store_stage<T::BN, T::BK, T::EB, T::NT, T::LDB>(false, rb, st + T::BK * T::LDA, tid);
-    if (do_oo) store_stage<BO, T::BK, EO, T::NT, LDO>(false, ro, st + T::BK * (T::LDA + T::LDB), tid);
+    if (do_oo) store_stage<BO, T::BK, EO, T::NT, BO>(false, ro, st + T::BK * (T::LDA + T::LDB), tid);
   };
 
+  double* soo = Soo + ((int64_t)z * 6 + pi) * no * nv2;
   load(0);
   store(lds);
   __syncthreads();
@@ -399,38 +515,40 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
 #pragma unroll
       for (int kk = 0; kk < T::BK / 4; ++kk) {
         const int kr = kk * 4 + (lane >> 4);
+        const int sw = (lane & 15) ^ lds_swz<T::BK>(kr);
         double a[T::FM], bo[FNO];
 #pragma unroll
-        for (int fm = 0; fm < T::FM; ++fm) a[fm] = cur[kr * T::LDA + (wm * T::FM + fm) * 16 + (lane & 15)];
+        for (int fm = 0; fm < T::FM; ++fm) a[fm] = cur[kr * T::LDA + (wm * T::FM + fm) * 16 + sw];
 #pragma unroll
-        for (int f = 0; f < FNO; ++f) bo[f] = so[kr * LDO + f * 16 + (lane & 15)];
+        for (int f = 0; f < FNO; ++f) bo[f] = so[kr * BO + f * 16 + sw];
 #pragma unroll
-        for (int fm = 0; fm < T::FM; ++fm)
+        for (int f = 0; f < FNO; ++f)
 #pragma unroll
-          for (int f = 0; f < FNO; ++f)
-            aco[fm][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fm], bo[f], aco[fm][f], 0, 0, 0);
+          for (int fm = 0; fm < T::FM; ++fm)
+            aco[f][fm] = __builtin_amdgcn_mfma_f64_16x16x4f64(bo[f], a[fm], aco[f][fm], 0, 0, 0);
       }
-      if ((s % cs) == cs - 1) {  // b complete: Ot2[p][l][a][b] += aco(a, l)
+      if ((s % cs) == cs - 1) {  // b complete: SooT[l][b][a] = aco(l, a); row no -> Omega1
         const int b = bb0 + s / cs;
 #pragma unroll
-        for (int fm = 0; fm < T::FM; ++fm)
+        for (int f = 0; f < FNO; ++f)
 #pragma unroll
-          for (int f = 0; f < FNO; ++f) {
+          for (int fm = 0; fm < T::FM; ++fm) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-              const int a = m0 + acc_row<T>(wm, fm, lane, rr);
-              const int l = f * 16 + (lane & 15);
-              if (a < nv && l < no)
-                unsafeAtomicAdd(&Ot2[(((int64_t)p * no + l) * nvl + a) * nvl + b], aco[fm][f][rr]);
+              const int l = f * 16 + (lane >> 4) + 4 * rr;
+              const int a = m0 + (wm * T::FM + fm) * 16 + (lane & 15);
+              if (a < nv && l < no) soo[((int64_t)l * nvl + b) * nvl + a] = aco[f][fm][rr];
+              if (l == no) om1[fm] += aco[f][fm][rr];
             }
-            aco[fm][f] = d4v{0.0, 0.0, 0.0, 0.0};
+            aco[f][fm] = d4v{0.0, 0.0, 0.0, 0.0};
           }
       }
     }
     if (more) store(nxt);
     __syncthreads();
   }
-  // (d, Omega1) columns
+  double* pvv = Pvv + (((int64_t)z * 6 + pi) * nbchunks + bc) * nvl * NV1;
+  // d columns of this chunk
 #pragma unroll
   for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
@@ -439,27 +557,120 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
       for (int rr = 0; rr < 4; ++rr) {
         const int a = m0 + acc_row<T>(wm, fm, lane, rr);
         const int n = n0 + acc_col<T>(wn, fn, lane);
-        if (a >= nv) continue;
-        if (n < nv) unsafeAtomicAdd(&Ot2[(((int64_t)p * no + q) * nvl + a) * nvl + n], acc[fm][fn][rr]);
-        else if (n == nv) unsafeAtomicAdd(&Ot1[(int64_t)p * nvl + a], acc[fm][fn][rr]);
+        if (a < nv && n < nv) pvv[(int64_t)a * NV1 + n] = acc[fm][fn][rr];
       }
+  if (do_oo) {  // Omega1 column, held by the lanes whose oo row is l == no
+#pragma unroll
+    for (int fm = 0; fm < T::FM; ++fm) {
+      const int a = m0 + (wm * T::FM + fm) * 16 + (lane & 15);
+      bool mine = false;
+#pragma unroll
+      for (int f = 0; f < FNO; ++f)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) mine |= (f * 16 + (lane >> 4) + 4 * rr == no);
+      if (mine && a < nv) pvv[(int64_t)a * NV1 + nv] = om1[fm];
+    }
+  }
 }
 
-void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Ot1,
-                  double* Ot2, int no, int nv, hipStream_t st) {
+// For output block (p, x):
+//   Ot2[p][x][a][d] += sum of Pvv[z][pi][chunk][a][d] over the batch's (triple,
+//                      permutation) pairs with that p and q == x, and chunks;
+//   OtT[p][x][b][a] += sum of SooT[z][pi][x][b][a] over the pairs with that p;
+//   Ot1[p][a]       += column nv of Pvv (block x == 0).
+// Fixed summation order: triple, permutation, chunk.
+#define REDUCE_MAXL 1024
+__global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int ntri,
+                                                const double* __restrict__ Pvv,
+                                                const double* __restrict__ SooT,
+                                                double* __restrict__ Ot1, double* __restrict__ Ot2,
+                                                double* __restrict__ OtT, int no, int nv,
+                                                int nbchunks) {
+  __shared__ int lz[REDUCE_MAXL];  // (z * 6 + pi) of the pairs with this p, in order
+  __shared__ int lq[REDUCE_MAXL];
+  __shared__ int cnt;
+  const int p = blockIdx.z, x = blockIdx.y;
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int z = 0; z < ntri; ++z) {
+      const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+      const int kind = tri_kind(i, j, k);
+      for (int pi = 0; pi < 6; ++pi) {
+        if (!perm_active(kind, pi)) continue;
+        int pp, q, r;
+        perm_pqr(pi, i, j, k, pp, q, r);
+        if (pp == p && n < REDUCE_MAXL) { lz[n] = z * 6 + pi; lq[n] = q; ++n; }
+      }
+    }
+    cnt = n;
+  }
+  __syncthreads();
+  const int64_t nvl = nv, nv2 = nvl * nvl;
+  const int NV1 = nv + 1;
+  const int64_t pvs = (int64_t)nvl * NV1;  // one chunk slab
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool o2 = e < nv2;
+  const bool o1 = (x == 0) && e < nv;  // Omega1 element a = e
+  if (!o2 && !o1) return;
+  const int a = (int)(e / nvl), d = (int)(e % nvl);
+  const int n = cnt;
+  double s2 = 0.0, st = 0.0, s1 = 0.0;
+  if (o2) {
+#pragma unroll 4
+    for (int t = 0; t < n; ++t) st += SooT[((int64_t)lz[t] * no + x) * nv2 + e];
+    for (int t = 0; t < n; ++t) {
+      if (lq[t] != x) continue;
+      const double* pv = Pvv + (int64_t)lz[t] * nbchunks * pvs + (int64_t)a * NV1 + d;
+#pragma unroll 4
+      for (int c = 0; c < nbchunks; ++c) s2 += pv[c * pvs];
+    }
+    Ot2[((int64_t)p * no + x) * nv2 + e] += s2;
+    OtT[((int64_t)p * no + x) * nv2 + e] += st;
+  }
+  if (o1) {
+    for (int t = 0; t < n; ++t) {
+      const double* pv = Pvv + (int64_t)lz[t] * nbchunks * pvs + (int64_t)e * NV1 + nv;
+      for (int c = 0; c < nbchunks; ++c) s1 += pv[c * pvs];
+    }
+    Ot1[(int64_t)p * nvl + e] += s1;
+  }
+}
+
+// Number of b chunks the Omega GEMM of one (triple, permutation) is split into:
+// enough workgroups for 256 CUs at two per CU, no more.
+int omega_nbchunks(int nv, int ntri) {
+  const int tm = (nv + OCfg::BM - 1) / OCfg::BM, tn = (nv + OCfg::BN - 1) / OCfg::BN;
+  const int per = 6 * tm * tn * (ntri > 0 ? ntri : 1);
+  int nbc = (640 + per - 1) / per;
+  if (nbc < 1) nbc = 1;
+  if (nbc > nv) nbc = nv;
+  const int bchunk = (nv + nbc - 1) / nbc;
+  return (nv + bchunk - 1) / bchunk;
+}
+
+void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pvv,
+                  double* Soo, int no, int nv, hipStream_t st) {
   typedef OCfg T;
-  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + 1 + T::BN - 1) / T::BN;
-  const int bchunk = 8;
-  const int nbc = (nv + bchunk - 1) / bchunk;
+  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + T::BN - 1) / T::BN;
+  const int nbc = omega_nbchunks(nv, ntri);
+  const int bchunk = (nv + nbc - 1) / nbc;
   const dim3 grid(nbc * tm * tn, 6, ntri), block(T::NT);
-  if (no <= 16)
-    hipLaunchKernelGGL(k_omega<1>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Ot1, Ot2, no, nv, bchunk, nbc, tn);
-  else if (no <= 32)
-    hipLaunchKernelGGL(k_omega<2>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Ot1, Ot2, no, nv, bchunk, nbc, tn);
-  else if (no <= 48)
-    hipLaunchKernelGGL(k_omega<3>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Ot1, Ot2, no, nv, bchunk, nbc, tn);
+  if (no + 1 <= 16)
+    hipLaunchKernelGGL(k_omega<1>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, bchunk, nbc, tn);
+  else if (no + 1 <= 32)
+    hipLaunchKernelGGL(k_omega<2>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, bchunk, nbc, tn);
+  else if (no + 1 <= 48)
+    hipLaunchKernelGGL(k_omega<3>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, bchunk, nbc, tn);
   else
-    hipLaunchKernelGGL(k_omega<4>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Ot1, Ot2, no, nv, bchunk, nbc, tn);
+    hipLaunchKernelGGL(k_omega<4>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, bchunk, nbc, tn);
+}
+
+void launch_reduce(const int* tri, int ntri, const double* Pvv, const double* Soo, double* Ot1,
+                   double* Ot2, double* OtT, int no, int nv, hipStream_t st) {
+  const int nbc = omega_nbchunks(nv, ntri);
+  const int64_t nv2 = (int64_t)nv * nv;
+  hipLaunchKernelGGL(k_reduce, dim3(nblk(nv2, 256), no, no), dim3(256), 0, st, tri, ntri, Pvv, Soo,
+                     Ot1, Ot2, OtT, no, nv, nbc);
 }
 
 // FLOP of the dominant contractions and their companions, padding excluded.
