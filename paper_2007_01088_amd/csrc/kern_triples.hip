@@ -67,7 +67,7 @@ enum { SLOT_P0 = 0, SLOT_P1 = 1, SLOT_P2 = 2, SLOT_TT = 3, SLOT_TTT = 4, NSLOT =
 // ---------------------------------------------------------------------------
 // W build
 // ---------------------------------------------------------------------------
-typedef TileCfg<4, 1, 2, 8, 16> WCfg;  // 128 x 128 output plane tile, 16 k per stage
+typedef TileCfg<4, 2, 2, 4, 16> WCfg;  // 128 x 128 output plane tile, 8 wavefronts, 16 k per stage
 
 __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ t2,
                                                      const double* __restrict__ t2N,
@@ -409,10 +409,10 @@ void launch_tau_export(const double* eps, const int* tri, const double* cubes, d
 //                                (summed over the chunk's b in registers)
 // Partial results: Pvv[z][pi][chunk][a][n] (n < nv: d columns, n == nv: Omega1),
 // SooT[z][pi][l][b][a].
-typedef TileCfg<4, 1, 2, 8, 8> OCfg;  // 128 x 128 vv tile
+typedef TileCfg<4, 2, 2, 4, 16> OCfg;  // 128 x 128 vv tile, 8 wavefronts
 
 template <int FNO>
-__global__ __launch_bounds__(OCfg::NT, FNO == 1 ? 2 : 1) void k_omega(
+__global__ __launch_bounds__(OCfg::NT) void k_omega(
     const double* __restrict__ cubes, const double* __restrict__ Gv, const double* __restrict__ Jo,
     const double* __restrict__ Hs, const int* __restrict__ tri, double* __restrict__ Pvv,
     double* __restrict__ Soo, int no, int nv, int bchunk, int nbchunks, int tiles_n) {
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(OCfg::NT, FNO == 1 ? 2 : 1) void k_omega(
     const bool more = (s + 1 < nsteps);
     if (more) load(s + 1);
     mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
-    if (do_oo) {
+    if (do_oo && wn == 0) {  // the oo product: one wavefront per row block of a
       const double* so = cur + T::BK * (T::LDA + T::LDB);
 #pragma unroll
       for (int kk = 0; kk < T::BK / 4; ++kk) {
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(OCfg::NT, FNO == 1 ? 2 : 1) void k_omega(
         const int n = n0 + acc_col<T>(wn, fn, lane);
         if (a < nv && n < nv) pvv[(int64_t)a * NV1 + n] = acc[fm][fn][rr];
       }
-  if (do_oo) {  // Omega1 column, held by the lanes whose oo row is l == no
+  if (do_oo && wn == 0) {  // Omega1 column, held by the lanes whose oo row is l == no
 #pragma unroll
     for (int fm = 0; fm < T::FM; ++fm) {
       const int a = m0 + (wm * T::FM + fm) * 16 + (lane & 15);
