@@ -110,6 +110,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip timing the mixed-precision W contractions (FP32, BF16x3, BF16x6)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -176,6 +178,35 @@ def main() -> int:
     # one sampled parity check of the timed output against nothing else than its own symmetry
     sym = float((o2 - o2.permute(1, 0, 3, 2)).abs().max() / o2.abs().max())
 
+    mixed = {}
+    if not args.no_mixed:
+        # the same call with the W contractions in low precision; errors against the FP64
+        # result of this GPU (equal to the CPU oracle to ~1e-15 in the parity tests)
+        for name, prec in (("fp32", cc3.FP32), ("bf16x6", cc3.BF16X6), ("bf16x3", cc3.BF16X3)):
+            m1 = torch.empty_like(o1)
+            m2 = torch.empty_like(o2)
+            ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=prec)
+            torch.cuda.synchronize()
+            ctx.profile_enable(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=prec)
+            torch.cuda.synchronize()
+            dtm = (time.perf_counter() - t0) / args.steps
+            st_m = ctx.profile_get()
+            ctx.profile_enable(False)
+            w = st_m.get("w_build", {"total_ms": 0.0, "launches": 1, "flops": 0.0})
+            mixed[name] = {
+                "value": nominal / dtm / 1e12, "ms_per_step": dtm * 1e3,
+                "rel_err_omega1": float((m1 - o1).norm() / o1.norm()),
+                "rel_err_omega2": float((m2 - o2).norm() / o2.norm()),
+                "w_build_tflops": w["flops"] / (w["total_ms"] * 1e-3) / 1e12 if w["total_ms"] else None,
+                "peak_tflops": PEAK_TFLOPS["fp32"] if name == "fp32" else PEAK_TFLOPS["bf16"] /
+                (3 if name == "bf16x3" else 6),
+            }
+            log(f"mixed {name}: {mixed[name]['value']:.2f} TFLOP/s, "
+                f"err {mixed[name]['rel_err_omega1']:.2e}/{mixed[name]['rel_err_omega2']:.2e}")
+
     out = {
         "metric": "Triples-residual TFLOP/s (4nv^4no^3/call)",
         "value": value,
@@ -196,6 +227,8 @@ def main() -> int:
         "kernels": kernels,
         "omega2_pair_symmetry": sym,
     }
+    if mixed:
+        out["mixed"] = mixed
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(no, nv, nchol, args.cpu_budget)

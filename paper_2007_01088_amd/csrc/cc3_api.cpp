@@ -228,6 +228,7 @@ int make_plan(int no, int nv, int nchol, int prec, unsigned flags, Plan* p, int 
   p->off_Ot2 = take(o * o * v * v * 8);
   p->off_OtT = take(o * o * v * v * 8);
   p->off_t2N = take(o * o * v * v * 8);
+  p->off_lp = take(lp_operand_bytes(prec, no, nv));
   p->pvv_bytes = align256(tc * 6 * v * (v + 1) * 8);
   p->soo_bytes = align256((size_t)batch * 6 * o * v * v * 8);
   p->off_Pvv = take(2 * p->pvv_bytes);
@@ -253,7 +254,8 @@ static int check_sizes(int no, int nv, int nchol, int prec) {
   if (no > 63 || nv > 1024)
     return fail(CC3_E_INVAL, "sizes beyond the supported range no <= 63, nv <= 1024 (no=%d nv=%d)",
                 no, nv);
-  if (prec != CC3_FP64) return fail(CC3_E_INVAL, "precision %d is not available", prec);
+  if (prec != CC3_FP64 && prec != CC3_FP32 && prec != CC3_BF16X3 && prec != CC3_BF16X6)
+    return fail(CC3_E_INVAL, "unknown precision %d", prec);
   return CC3_OK;
 }
 
@@ -304,6 +306,7 @@ struct Ws {
   double *cubes[2], *Pvv[2], *Soo[2];
   int* tri;
   int* flag;
+  LpOperands lp;
 };
 
 static Ws carve(const Plan& p, void* ws) {
@@ -319,6 +322,7 @@ static Ws carve(const Plan& p, void* ws) {
   w.Ot2 = (double*)(base + p.off_Ot2);
   w.OtT = (double*)(base + p.off_OtT);
   w.t2N = (double*)(base + p.off_t2N);
+  lp_operand_ptrs(p.prec, p.no, p.nv, base + p.off_lp, w.lp);
   for (int k = 0; k < 2; ++k) {
     w.Pvv[k] = (double*)(base + p.off_Pvv + k * p.pvv_bytes);
     w.Soo[k] = (double*)(base + p.off_Soo + k * p.soo_bytes);
@@ -360,6 +364,7 @@ static int triple_loop(cc3_ctx* c, const Plan& p, const Ws& w, const double* eps
   if (rc) return rc;
   std::vector<int> kinds;
   launch_t2N(t2, w.t2N, p.no, p.nv, st);
+  if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, p.no, p.nv, w.lp, st);
   HIPCHK(hipEventRecord(c->ev_fork, st));
   for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(c->s[k], c->ev_fork, 0));
   int nbatch = 0;
@@ -373,7 +378,10 @@ static int triple_loop(cc3_ctx* c, const Plan& p, const Ws& w, const double* eps
     const int* tb = tri + 3 * t0;
     {
       Timer tm(c, sk, FAM_W, wbuild_flops(p.no, p.nv, kinds.data(), nb), 0.0);
-      launch_wbuild(t2, w.t2N, w.b, tb, nb, w.cubes[k], p.no, p.nv, false, sk);
+      if (p.prec == CC3_FP64)
+        launch_wbuild(t2, w.t2N, w.b, tb, nb, w.cubes[k], p.no, p.nv, false, sk);
+      else
+        launch_wbuild_lp(w.lp, tb, nb, w.cubes[k], p.no, p.nv, false, sk);
     }
     {
       Timer tm(c, sk, FAM_MIX, 0.0, 0.0);
@@ -578,7 +586,12 @@ extern "C" int cc3_t3_block(cc3_ctx* c, int no, int nv, int nchol, const double*
   const int h[3] = {i, j, k};
   HIPCHK(hipMemcpyAsync(w.tri, h, sizeof h, hipMemcpyHostToDevice, st));
   launch_t2N(t2, w.t2N, no, nv, st);
-  launch_wbuild(t2, w.t2N, w.b, w.tri, 1, w.cubes[0], no, nv, true, st);
+  if (prec == CC3_FP64) {
+    launch_wbuild(t2, w.t2N, w.b, w.tri, 1, w.cubes[0], no, nv, true, st);
+  } else {
+    launch_lp_convert(t2, w.b, no, nv, w.lp, st);
+    launch_wbuild_lp(w.lp, w.tri, 1, w.cubes[0], no, nv, true, st);
+  }
   launch_tau_export(eps, w.tri, w.cubes[0], tau, no, nv, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));

@@ -40,11 +40,23 @@ struct Plan {
   size_t cube;  // doubles per nv^3 cube
   // byte offsets into the workspace
   size_t off_Gw, off_Go, off_Gv, off_Jo, off_Hs, off_F;
-  size_t off_Ot1, off_Ot2, off_OtT, off_t2N, off_Pvv, off_Soo, off_tri, off_flag, off_cubes;
+  size_t off_Ot1, off_Ot2, off_OtT, off_lp, off_t2N, off_Pvv, off_Soo, off_tri, off_flag, off_cubes;
   size_t off_chol;  // Cholesky scratch (aliases the cube region)
   size_t chol_bytes, cube_bytes, pvv_bytes, soo_bytes;  // per buffer set (two sets)
   size_t total;
 };
+
+// Low-precision copies of the W operands (FP32, or BF16 pieces), see kern_wlp.hip.
+struct LpOperands {
+  void *t2, *t2N, *GwT, *GoT;
+  int prec;
+};
+size_t lp_operand_bytes(int prec, int no, int nv);
+void lp_operand_ptrs(int prec, int no, int nv, void* base, LpOperands& lp);
+void launch_lp_convert(const double* t2, const Blocks& b, int no, int nv, const LpOperands& lp,
+                       hipStream_t st);
+void launch_wbuild_lp(const LpOperands& lp, const int* tri, int ntri, double* cubes, int no, int nv,
+                      bool all_terms, hipStream_t st);
 
 int make_plan(int no, int nv, int nchol, int prec, unsigned flags, Plan* p, int batch_override);
 

@@ -1,0 +1,361 @@
+// Low-precision W build (the t3-building contractions of Algorithm 1's first
+// statement) on gfx950 MFMA, with FP32 accumulation:
+//   CC3_FP32   : v_mfma_f32_16x16x4f32 on FP32 copies of the operands;
+//   CC3_BF16X3 : v_mfma_f32_16x16x32_bf16 on a 2-piece split x = hi + lo,
+//                products hi*hi + hi*lo + lo*hi;
+//   CC3_BF16X6 : 3-piece split x = hi + mid + lo, products hi*hi + hi*mid +
+//                mid*hi + hi*lo + mid*mid + lo*hi.
+// Each W term is accumulated in FP32 over its K range; the two terms of a plane
+// are converted and summed in FP64 and the plane is stored in FP64, so the
+// permutation sum, the denominator division, the contravariant combination
+// and the Omega accumulation downstream stay FP64.
+//
+// The operands are re-laid out once per call so that the contracted index is
+// contiguous and zero-padded to a multiple of 32 (tiles load as 16-byte
+// chunks into row-major LDS rows, and the K loop needs no bounds checks):
+//   t2L [piece][p][q][x][dk]  = t2[p][q][x][d]
+//   t2NL[piece][p][y][x][lk]  = -t2[p][l][x][y]
+//   GwTL[piece][r][y][z][dk]  = Gw[r][y][d][z]   (= g_{ydzr})
+//   GoTL[piece][q][r][z][lk]  = Go[q][r][l][z]   (= g_{lqzr})
+#include <hip/hip_bf16.h>
+
+#include "cc3.h"
+#include "cc3_device.hpp"
+#include "cc3_internal.hpp"
+
+namespace cc3 {
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__host__ __device__ inline int kpad(int k) { return (k + 31) / 32 * 32; }
+
+// ---------------------------------------------------------------------------
+// Operand conversion: FP64 value -> pieces
+// ---------------------------------------------------------------------------
+__device__ inline uint16_t bf16_rn(double x) {
+  // round-to-nearest-even of the FP32 rounding of x (x is representable after
+  // the first rounding to FP32 for the magnitudes of the pieces used here)
+  const float f = (float)x;
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline double bf16_val(uint16_t h) { return (double)__uint_as_float(((uint32_t)h) << 16); }
+
+// pieces of x: piece 0 = hi, 1 = next, 2 = last (BF16); FP32 uses one float
+template <int P>
+__device__ inline void split_bf16(double x, uint16_t (&pc)[P]) {
+  double rest = x;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    pc[i] = bf16_rn(rest);
+    rest -= bf16_val(pc[i]);
+  }
+}
+
+// Generic re-layout: out[piece][outer][x][kk] (kk < K padded) from an FP64
+// source element (outer, x, k) at src[outer * so + x * sx + k * sk] * sign.
+// `piece_stride` is the element distance between pieces of the whole array.
+template <int MODE>  // 0: FP32, 2: BF16 2-piece, 3: BF16 3-piece
+__global__ void k_lp_copy(const double* __restrict__ src, int64_t so, int64_t sx, int64_t sk,
+                          double sign, int nouter, int nx, int K, void* __restrict__ dst,
+                          int64_t piece_stride) {
+  const int Kp = kpad(K);
+  const int64_t n = (int64_t)nouter * nx * Kp;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int kk = (int)(e % Kp);
+  const int x = (int)((e / Kp) % nx);
+  const int64_t o = e / ((int64_t)Kp * nx);
+  const double v = (kk < K) ? sign * src[o * so + (int64_t)x * sx + (int64_t)kk * sk] : 0.0;
+  if constexpr (MODE == 0) {
+    ((float*)dst)[e] = (float)v;
+  } else {
+    constexpr int P = MODE;
+    uint16_t pc[P];
+    split_bf16<P>(v, pc);
+#pragma unroll
+    for (int i = 0; i < P; ++i) ((uint16_t*)dst)[i * piece_stride + e] = pc[i];
+  }
+}
+
+static int mode_of(int prec) { return prec == CC3_FP32 ? 0 : prec == CC3_BF16X3 ? 2 : 3; }
+
+size_t lp_operand_bytes(int prec, int no, int nv) {
+  if (prec == CC3_FP64) return 0;
+  const size_t o = no, v = nv, dk = kpad(nv), lk = kpad(no);
+  const size_t elems = o * o * v * dk + o * v * v * lk + o * v * v * dk + o * o * v * lk;
+  const size_t esz = prec == CC3_FP32 ? 4 : 2;
+  const size_t pieces = prec == CC3_FP32 ? 1 : prec == CC3_BF16X3 ? 2 : 3;
+  return elems * esz * pieces + 4 * 256;
+}
+
+void lp_operand_ptrs(int prec, int no, int nv, void* base, LpOperands& lp) {
+  const size_t o = no, v = nv, dk = kpad(nv), lk = kpad(no);
+  const size_t esz = prec == CC3_FP32 ? 4 : 2;
+  const size_t pieces = prec == CC3_FP32 ? 1 : prec == CC3_BF16X3 ? 2 : 3;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char* b = (char*)base;
+  lp.t2 = b;
+  b += al(o * o * v * dk * esz * pieces);
+  lp.t2N = b;
+  b += al(o * v * v * lk * esz * pieces);
+  lp.GwT = b;
+  b += al(o * v * v * dk * esz * pieces);
+  lp.GoT = b;
+  lp.prec = prec;
+}
+
+template <int MODE>
+static void lp_copy(const double* src, int64_t so, int64_t sx, int64_t sk, double sign, int nouter,
+                    int nx, int K, void* dst, int64_t piece_stride, hipStream_t st) {
+  const int64_t n = (int64_t)nouter * nx * kpad(K);
+  hipLaunchKernelGGL(k_lp_copy<MODE>, dim3(nblk(n, 256)), dim3(256), 0, st, src, so, sx, sk, sign,
+                     nouter, nx, K, dst, piece_stride);
+}
+
+void launch_lp_convert(const double* t2, const Blocks& b, int no, int nv, const LpOperands& lp,
+                       hipStream_t st) {
+  const int64_t v = nv, o = no, dk = kpad(nv), lk = kpad(no);
+  auto run = [&](auto mode_tag) {
+    constexpr int M = decltype(mode_tag)::value;
+    constexpr int64_t esz = (M == 0 ? 4 : 2);
+    // t2L[p][q][x][d] = t2[p][q][x][d]
+    lp_copy<M>(t2, v * v, v, 1, 1.0, no * no, nv, nv, lp.t2, o * o * v * dk, st);
+    // t2NL[p][y][x][l] = -t2[p][l][x][y]: for each p, outer = y, x = x, k = l
+    for (int p = 0; p < no; ++p)
+      lp_copy<M>(t2 + (int64_t)p * o * v * v, 1, v, v * v, -1.0, nv, nv, no,
+                 (char*)lp.t2N + (size_t)p * v * v * lk * esz, o * v * v * lk, st);
+    // GwTL[r][y][z][d] = Gw[r][y][d][z]: outer = (r, y), x = z, k = d
+    lp_copy<M>(b.Gw, v * v, 1, v, 1.0, no * nv, nv, nv, lp.GwT, o * v * v * dk, st);
+    // GoTL[q][r][z][l] = Go[q][r][l][z]: outer = (q, r), x = z, k = l
+    lp_copy<M>(b.Go, o * v, 1, v, 1.0, no * no, nv, no, lp.GoT, o * o * v * lk, st);
+  };
+  const int m = mode_of(lp.prec);
+  if (m == 0) run(std::integral_constant<int, 0>());
+  else if (m == 2) run(std::integral_constant<int, 2>());
+  else run(std::integral_constant<int, 3>());
+}
+
+// ---------------------------------------------------------------------------
+// W build in low precision
+// ---------------------------------------------------------------------------
+// 8 wavefronts as 4 (rows) x 2 (columns), each 32 x 64 outputs (2 x 4 blocks).
+constexpr int LWM = 4, LWN = 2, LFM = 2, LFN = 4;
+constexpr int LNT = 64 * LWM * LWN;
+constexpr int LBM = 16 * LWM * LFM, LBN = 16 * LWN * LFN;  // 128 x 128
+
+// Engine traits.  An LDS tile is row-major [x][k] with rows of BK elements plus
+// 16 bytes of padding (rows of 80 bytes: the 16 rows read by one fragment load
+// land on distinct banks).  One 16-byte chunk per thread per piece per operand.
+struct EngF32 {
+  static constexpr int BK = 16, P = 1, NPROD = 1, ESZ = 4;
+  static constexpr int ROWB = BK * ESZ + 16;  // bytes per LDS row
+};
+template <int P_>
+struct EngBF16 {
+  static constexpr int BK = 32, P = P_, NPROD = (P_ == 2 ? 3 : 6), ESZ = 2;
+  static constexpr int ROWB = BK * ESZ + 16;
+};
+
+// the piece pairs of the split products
+__device__ inline void prod_pair(int P, int t, int& pa, int& pb) {
+  if (P == 2) {
+    const int a[3] = {0, 0, 1}, b[3] = {0, 1, 0};
+    pa = a[t]; pb = b[t];
+  } else {
+    const int a[6] = {0, 0, 1, 0, 1, 2}, b[6] = {0, 1, 0, 2, 1, 0};
+    pa = a[t]; pb = b[t];
+  }
+}
+
+struct LpSeg {
+  const char* a;  // piece 0 base of the A rows (row x at a + x * a_rs bytes)
+  const char* b;
+  int64_t a_rs, b_rs;   // row strides in bytes
+  int64_t a_ps, b_ps;   // piece strides in bytes
+  int ksteps;           // K steps of BK
+};
+
+template <class E>
+__global__ __launch_bounds__(LNT) void k_wbuild_lp(
+    const char* __restrict__ t2L, const char* __restrict__ t2NL, const char* __restrict__ GwTL,
+    const char* __restrict__ GoTL, const int* __restrict__ tri, double* __restrict__ cubes, int no,
+    int nv, int tiles_m, int tiles_n, int all_terms) {
+  constexpr int BK = E::BK, P = E::P, ESZ = E::ESZ, ROWB = E::ROWB;
+  constexpr int TILEB = LBM * ROWB;  // one operand tile, one piece (LBM == LBN)
+  constexpr int STAGEB = 2 * P * TILEB;
+  __shared__ __attribute__((aligned(16))) char lds[2 * STAGEB];
+  const int tpp = tiles_m * tiles_n;
+  const int y = blockIdx.x / tpp;
+  const int tile = blockIdx.x % tpp;
+  const int m0 = (tile / tiles_n) * LBM, n0 = (tile % tiles_n) * LBN;
+  const int plane = blockIdx.y;
+  const int z = blockIdx.z;
+  const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+  int kind = (i == j) ? 1 : (j == k) ? 2 : 0;
+  if (all_terms) kind = 0;
+  if ((kind == 1 && plane == 1) || (kind == 2 && plane == 2)) return;
+  const bool two = (kind == 0) || plane == 0;
+  int p1, q1, r1, p2, q2, r2;
+  if (plane == 0) { p1 = i; q1 = j; r1 = k; p2 = k; q2 = j; r2 = i; }
+  else if (plane == 1) { p1 = j; q1 = i; r1 = k; p2 = k; q2 = i; r2 = j; }
+  else { p1 = i; q1 = k; r1 = j; p2 = j; q2 = k; r2 = i; }
+
+  const int64_t dk = kpad(nv), lk = kpad(no), v = nv, o = no;
+  // piece strides (elements) of the four arrays
+  const int64_t ps_t2 = o * o * v * dk, ps_t2N = o * v * v * lk, ps_Gw = o * v * v * dk,
+                ps_Go = o * o * v * lk;
+  // segments: term 1 vv, term 1 oo, term 2 vv, term 2 oo (rows m for A, n for B)
+  LpSeg seg[4];
+  seg[0] = {t2L + ((p1 * o + q1) * v) * dk * ESZ, GwTL + ((r1 * v + y) * v) * dk * ESZ,
+            dk * ESZ, dk * ESZ, ps_t2 * ESZ, ps_Gw * ESZ, (int)(dk / BK)};
+  seg[1] = {t2NL + ((p1 * v + y) * v) * lk * ESZ, GoTL + ((q1 * o + r1) * v) * lk * ESZ,
+            lk * ESZ, lk * ESZ, ps_t2N * ESZ, ps_Go * ESZ, (int)(lk / BK)};
+  seg[2] = {GwTL + ((r2 * v + y) * v) * dk * ESZ, t2L + ((p2 * o + q2) * v) * dk * ESZ,
+            dk * ESZ, dk * ESZ, ps_Gw * ESZ, ps_t2 * ESZ, (int)(dk / BK)};
+  seg[3] = {GoTL + ((q2 * o + r2) * v) * lk * ESZ, t2NL + ((p2 * v + y) * v) * lk * ESZ,
+            lk * ESZ, lk * ESZ, ps_Go * ESZ, ps_t2N * ESZ, (int)(lk / BK)};
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % LWM, wn = wave / LWM;
+  // this thread's 16-byte chunk of a tile: row cr, chunk cc within the row
+  constexpr int CPR = BK * ESZ / 16;  // chunks per row (4)
+  const int cr = tid / CPR, cc = tid % CPR;
+  const bool rowA_ok = (m0 + cr) < nv, rowB_ok = (n0 + cr) < nv;
+
+  double out[LFM][LFN][4];
+#pragma unroll
+  for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < LFN; ++fn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[fm][fn][r] = 0.0;
+
+  for (int term = 0; term < (two ? 2 : 1); ++term) {
+    f4v acc[LFM][LFN];
+#pragma unroll
+    for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < LFN; ++fn) acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+    const LpSeg& s0 = seg[2 * term];
+    const LpSeg& s1 = seg[2 * term + 1];
+    const int nsteps = s0.ksteps + s1.ksteps;
+    uint4 ra[P], rb[P];
+    auto load = [&](int s) {
+      const LpSeg& g = (s < s0.ksteps) ? s0 : s1;
+      const int ks = (s < s0.ksteps) ? s : s - s0.ksteps;
+      const int64_t koff = (int64_t)ks * BK * ESZ + cc * 16;
+      const char* pa = g.a + (int64_t)(m0 + cr) * g.a_rs + koff;
+      const char* pb = g.b + (int64_t)(n0 + cr) * g.b_rs + koff;
+#pragma unroll
+      for (int pc = 0; pc < P; ++pc) {
+        ra[pc] = rowA_ok ? *(const uint4*)(pa + pc * g.a_ps) : make_uint4(0, 0, 0, 0);
+        rb[pc] = rowB_ok ? *(const uint4*)(pb + pc * g.b_ps) : make_uint4(0, 0, 0, 0);
+      }
+    };
+    auto store = [&](char* st) {
+#pragma unroll
+      for (int pc = 0; pc < P; ++pc) {
+        *(uint4*)(st + pc * TILEB + cr * ROWB + cc * 16) = ra[pc];
+        *(uint4*)(st + (P + pc) * TILEB + cr * ROWB + cc * 16) = rb[pc];
+      }
+    };
+    load(0);
+    store(lds);
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+      char* cur = lds + (s & 1) * STAGEB;
+      char* nxt = lds + ((s + 1) & 1) * STAGEB;
+      const bool more = s + 1 < nsteps;
+      if (more) load(s + 1);
+      if constexpr (P == 1) {
+        // FP32: four k=4 MFMA steps; lane supplies A[m = l%16][k = l/16], B[k = l/16][n = l%16]
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+          const int kc = kk * 4 + (lane >> 4);
+          float a[LFM], b[LFN];
+#pragma unroll
+          for (int fm = 0; fm < LFM; ++fm)
+            a[fm] = *(const float*)(cur + ((wm * LFM + fm) * 16 + (lane & 15)) * ROWB + kc * 4);
+#pragma unroll
+          for (int fn = 0; fn < LFN; ++fn)
+            b[fn] = *(const float*)(cur + TILEB + ((wn * LFN + fn) * 16 + (lane & 15)) * ROWB + kc * 4);
+#pragma unroll
+          for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < LFN; ++fn)
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
+        }
+      } else {
+        // BF16: one k=32 step per product; lane supplies A[m = l%16][k = 8(l/16)..+7]
+        const int kb = (lane >> 4) * 16;  // byte offset of the 8 k values
+        bf8v a[P][LFM], b[P][LFN];
+#pragma unroll
+        for (int pc = 0; pc < P; ++pc) {
+#pragma unroll
+          for (int fm = 0; fm < LFM; ++fm)
+            a[pc][fm] = *(const bf8v*)(cur + pc * TILEB + ((wm * LFM + fm) * 16 + (lane & 15)) * ROWB + kb);
+#pragma unroll
+          for (int fn = 0; fn < LFN; ++fn)
+            b[pc][fn] = *(const bf8v*)(cur + (P + pc) * TILEB + ((wn * LFN + fn) * 16 + (lane & 15)) * ROWB + kb);
+        }
+#pragma unroll
+        for (int t = 0; t < E::NPROD; ++t) {
+          int pa, pb;
+          prod_pair(P, t, pa, pb);
+#pragma unroll
+          for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < LFN; ++fn)
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa][fm], b[pb][fn], acc[fm][fn], 0, 0, 0);
+        }
+      }
+      if (more) store(nxt);
+      __syncthreads();
+    }
+    // FP32 term -> FP64 plane sum
+#pragma unroll
+    for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < LFN; ++fn)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[fm][fn][r] += (double)acc[fm][fn][r];
+  }
+
+  // the FP32/BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
+  const int64_t nv2 = (int64_t)nv * nv, nv3 = nv2 * nv;
+  double* dst = cubes + ((int64_t)z * 5 + plane) * nv3 + (int64_t)y * nv2;
+#pragma unroll
+  for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < LFN; ++fn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + (wm * LFM + fm) * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + (wn * LFN + fn) * 16 + (lane & 15);
+        if (m < nv && n < nv) dst[(int64_t)m * nv + n] = out[fm][fn][r];
+      }
+}
+
+void launch_wbuild_lp(const LpOperands& lp, const int* tri, int ntri, double* cubes, int no, int nv,
+                      bool all_terms, hipStream_t st) {
+  const int tm = (nv + LBM - 1) / LBM, tn = (nv + LBN - 1) / LBN;
+  const dim3 grid(nv * tm * tn, 3, ntri), block(LNT);
+  const char *a = (const char*)lp.t2, *b = (const char*)lp.t2N, *c = (const char*)lp.GwT,
+             *d = (const char*)lp.GoT;
+  const int at = all_terms ? 1 : 0;
+  if (lp.prec == CC3_FP32)
+    hipLaunchKernelGGL(k_wbuild_lp<EngF32>, grid, block, 0, st, a, b, c, d, tri, cubes, no, nv, tm, tn, at);
+  else if (lp.prec == CC3_BF16X3)
+    hipLaunchKernelGGL(k_wbuild_lp<EngBF16<2>>, grid, block, 0, st, a, b, c, d, tri, cubes, no, nv, tm, tn, at);
+  else
+    hipLaunchKernelGGL(k_wbuild_lp<EngBF16<3>>, grid, block, 0, st, a, b, c, d, tri, cubes, no, nv, tm, tn, at);
+}
+
+}  // namespace cc3
