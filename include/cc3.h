@@ -182,6 +182,107 @@ int cc3_profile_enable(cc3_ctx* ctx, int on);
  * CC3_E_INVAL, CC3_E_DEVICE. */
 int cc3_profile_get(cc3_ctx* ctx, cc3_kernel_stat* out, int max, int* count);
 
+/* ---------------------------------------------------------------------- */
+/* Serving: residual requests from many molecules, as solvers issue them    */
+/* ---------------------------------------------------------------------- */
+/* A server owns one caller-provided device buffer (the arena) and carves
+ * everything from it: the resident data of each registered molecule (eps, L,
+ * t1, t2, the T1-transformed integral blocks and the result) and, per request,
+ * the transient workspace of one residual evaluation.  A worker thread admits
+ * queued requests in arrival order whenever a slot (an independent set of
+ * streams, at most max_inflight) is free and the request's workspace fits in
+ * the arena (admission by HBM footprint); admitted requests run concurrently
+ * on the device, so new arrivals join work that is already in flight.  The
+ * arithmetic of a request is exactly that of cc3_triples_residual (Algorithm 1);
+ * the integral blocks are rebuilt only when a request brings new t1.
+ *
+ * Pointers passed to the serving calls may be host or device memory
+ * (detected per pointer); inputs are copied before the call returns, so the
+ * caller may reuse its buffers at once.  The library allocates no device
+ * memory here: everything lives in the arena (the server's streams and events
+ * are the only other device resources).  All calls are thread-safe.
+ * Clock: the timestamps of cc3_timing are seconds on a steady host clock
+ * whose zero is the server's creation. */
+typedef struct cc3_server cc3_server;
+
+typedef struct cc3_timing {
+  double arrival_s; /* the request was queued (inside cc3_submit, after its input copies) */
+  double admit_s;   /* workspace granted from the arena and the work enqueued on a slot */
+  double start_s;   /* the device began the request's first kernel (device clock mapped to host) */
+  double finish_s;  /* the server observed the request's completion */
+  double device_ms; /* device time from the first to the last kernel of the request */
+  int slot;         /* slot the request ran on */
+  int rebuilt;      /* 1 if the integral blocks were rebuilt (new t1) */
+} cc3_timing;
+
+typedef struct cc3_server_stats {
+  int64_t submitted, completed, failed, cancelled;
+  int queued, inflight, max_inflight_seen, molecules;
+  size_t arena_bytes, arena_used, arena_peak;
+} cc3_server_stats;
+
+/* Create a server on `device` over the arena [arena, arena + arena_bytes)
+ * (device memory of that GPU, 256-byte aligned, owned by the caller and kept
+ * alive until cc3_server_destroy returns).  1 <= max_inflight <= 8.
+ * Errors: CC3_E_INVAL, CC3_E_DEVICE. */
+int cc3_server_create(cc3_server** out, int device, void* arena, size_t arena_bytes,
+                      int max_inflight);
+
+/* Cancel queued requests, wait for the ones in flight, stop the worker and
+ * free the server (NULL accepted).  Uncollected results are dropped; no other
+ * call on this server may be in progress or follow. */
+int cc3_server_destroy(cc3_server* srv);
+
+/* Arena bytes of one molecule (*resident, held from register to release) and
+ * of one request's transient workspace (*transient, held from admission to
+ * completion) on this server.  Either pointer may be NULL.
+ * Errors: CC3_E_INVAL (sizes as for cc3_workspace_size, nchol >= 1). */
+int cc3_server_footprint(cc3_server* srv, int no, int nv, int nchol, int prec, size_t* resident,
+                         size_t* transient);
+
+/* Register a molecule: copies eps[no+nv] and L[nchol][nmo][nmo] (and t1[no][nv];
+ * NULL means t1 = 0) into its resident arena region; *mol receives its id.
+ * Blocks the caller until the copies are done.  Errors: CC3_E_INVAL,
+ * CC3_E_NOMEM (no hole in the arena large enough), CC3_E_DEVICE. */
+int cc3_molecule_register(cc3_server* srv, int no, int nv, int nchol, const double* eps,
+                          const double* L, const double* t1, uint64_t* mol);
+
+/* Free a molecule's arena region.  Errors: CC3_E_NOTFOUND, CC3_E_BUSY (it has
+ * a request that has not been collected by cc3_wait). */
+int cc3_molecule_release(cc3_server* srv, uint64_t mol);
+
+/* Queue one residual evaluation of molecule `mol`: copies t2[no][no][nv][nv]
+ * (and t1[no][nv] if not NULL; NULL keeps the molecule's current t1 and its
+ * integral blocks) into the molecule's region, then queues the request and
+ * returns its ticket.  prec as for cc3_triples_residual; flags: CC3_CHECK
+ * (checked here, blocking, before queueing) and CC3_ACCUMULATE (applied at
+ * cc3_wait).  A molecule has at most one unfinished request: submit again
+ * after cc3_wait.  Errors: CC3_E_INVAL, CC3_E_NOTFOUND, CC3_E_BUSY (the
+ * molecule has an unfinished request), CC3_E_NOMEM (the request's workspace
+ * exceeds the whole arena), CC3_E_PRECOND, CC3_E_DEVICE. */
+int cc3_submit(cc3_server* srv, uint64_t mol, const double* t1, const double* t2, int prec,
+               unsigned flags, uint64_t* ticket);
+
+/* *done = 1 once the request has finished (or failed or was cancelled), else 0.
+ * Errors: CC3_E_NOTFOUND (unknown or already collected ticket). */
+int cc3_poll(cc3_server* srv, uint64_t ticket, int* done);
+
+/* Block until the request has finished, then copy (or add, with
+ * CC3_ACCUMULATE; device outputs only) its covariant result into
+ * omega1[no][nv] and omega2[no][no][nv][nv] (either may be NULL to skip it)
+ * and fill *timing (may be NULL).  Collects the ticket.  Returns the request's
+ * own status: CC3_OK, CC3_E_CANCELLED, CC3_E_NOMEM (it could not be admitted
+ * with nothing in flight), CC3_E_DEVICE; CC3_E_NOTFOUND for an unknown ticket. */
+int cc3_wait(cc3_server* srv, uint64_t ticket, double* omega1, double* omega2,
+             cc3_timing* timing);
+
+/* Cancel a request that has not been admitted yet (cc3_wait then returns
+ * CC3_E_CANCELLED).  Errors: CC3_E_NOTFOUND; CC3_E_BUSY if it already runs. */
+int cc3_cancel(cc3_server* srv, uint64_t ticket);
+
+/* Counters of the server since creation.  Errors: CC3_E_INVAL. */
+int cc3_server_get_stats(cc3_server* srv, cc3_server_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

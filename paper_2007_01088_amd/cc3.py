@@ -62,9 +62,48 @@ _prof_enable = _sig("cc3_profile_enable", [_vp, _c_int])
 _prof_get = _sig("cc3_profile_get", [_vp, ctypes.POINTER(KernelStat), _c_int,
                                      ctypes.POINTER(_c_int)])
 
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("finish_s", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("slot", _c_int), ("rebuilt", _c_int)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("queued", _c_int), ("inflight", _c_int), ("max_inflight_seen", _c_int),
+                ("molecules", _c_int), ("arena_bytes", _c_size), ("arena_used", _c_size),
+                ("arena_peak", _c_size)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_u64 = ctypes.c_uint64
+_srv_create = _sig("cc3_server_create", [ctypes.POINTER(_vp), _c_int, _vp, _c_size, _c_int])
+_srv_destroy = _sig("cc3_server_destroy", [_vp])
+_srv_footprint = _sig("cc3_server_footprint", [_vp, _c_int, _c_int, _c_int, _c_int,
+                                               ctypes.POINTER(_c_size), ctypes.POINTER(_c_size)])
+_mol_register = _sig("cc3_molecule_register", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp,
+                                               ctypes.POINTER(_u64)])
+_mol_release = _sig("cc3_molecule_release", [_vp, _u64])
+_submit = _sig("cc3_submit", [_vp, _u64, _dp, _dp, _c_int, ctypes.c_uint, ctypes.POINTER(_u64)])
+_poll = _sig("cc3_poll", [_vp, _u64, ctypes.POINTER(_c_int)])
+_wait = _sig("cc3_wait", [_vp, _u64, _dp, _dp, ctypes.POINTER(Timing)])
+_cancel = _sig("cc3_cancel", [_vp, _u64])
+_srv_stats = _sig("cc3_server_get_stats", [_vp, ctypes.POINTER(ServerStats)])
+
 EXPORTED = ["cc3_create", "cc3_destroy", "cc3_last_error", "cc3_workspace_size",
             "cc3_triples_residual", "cc3_triples_residual_blocks", "cc3_triples_residual_subset",
-            "cc3_t3_block", "cc3_flops", "cc3_profile_enable", "cc3_profile_get"]
+            "cc3_t3_block", "cc3_flops", "cc3_profile_enable", "cc3_profile_get",
+            "cc3_server_create", "cc3_server_destroy", "cc3_server_footprint",
+            "cc3_molecule_register", "cc3_molecule_release", "cc3_submit", "cc3_poll",
+            "cc3_wait", "cc3_cancel", "cc3_server_get_stats"]
 
 
 class CC3Error(RuntimeError):
@@ -210,3 +249,108 @@ class Context:
         return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
                                        "flops": arr[i].flops, "bytes": arr[i].bytes}
                 for i in range(n.value)}
+
+
+class Server:
+    """A libcc3 serving loop over one arena tensor (uint8, on the server's GPU).
+
+    Inputs may be CUDA tensors or host (CPU) tensors; they are copied before
+    each call returns.  Results are copied out by `wait`.
+    """
+
+    def __init__(self, arena: torch.Tensor, max_inflight: int = 4, device: int = 0):
+        if not arena.is_cuda or arena.dtype != torch.uint8 or not arena.is_contiguous():
+            raise ValueError("arena must be a contiguous uint8 CUDA tensor")
+        h = _vp()
+        _check(_srv_create(ctypes.byref(h), device, arena.data_ptr(), arena.numel(),
+                           max_inflight), "cc3_server_create")
+        self._h = h
+        self._arena = arena  # kept alive as long as the server
+        self.device = device
+        self._shape = {}
+
+    def close(self) -> None:
+        if self._h:
+            _srv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self, no: int, nv: int, nchol: int, prec: int = FP64) -> tuple[int, int]:
+        r, t = _c_size(0), _c_size(0)
+        _check(_srv_footprint(self._h, no, nv, nchol, prec, ctypes.byref(r), ctypes.byref(t)),
+               "cc3_server_footprint")
+        return r.value, t.value
+
+    def register(self, no: int, nv: int, eps, L, t1=None) -> int:
+        """Copy a molecule's eps, L (and t1; None = zero) into the arena; returns its id."""
+        nchol = L.shape[0]
+        mol = _u64(0)
+        _check(_mol_register(self._h, no, nv, nchol, _any_ptr(eps, "eps"), _any_ptr(L, "L"),
+                             _any_ptr(t1, "t1"), ctypes.byref(mol)), "cc3_molecule_register")
+        self._shape[mol.value] = (no, nv)
+        return mol.value
+
+    def release(self, mol: int) -> None:
+        _check(_mol_release(self._h, mol), "cc3_molecule_release")
+        self._shape.pop(mol, None)
+
+    def submit(self, mol: int, t2, t1=None, prec: int = FP64, flags: int = 0) -> int:
+        tk = _u64(0)
+        _check(_submit(self._h, mol, _any_ptr(t1, "t1"), _any_ptr(t2, "t2"), prec, flags,
+                       ctypes.byref(tk)), "cc3_submit")
+        return tk.value
+
+    def try_submit(self, mol: int, t2, t1=None, prec: int = FP64, flags: int = 0):
+        """(ticket, 0) or (None, error code) without raising."""
+        tk = _u64(0)
+        rc = _submit(self._h, mol, _any_ptr(t1, "t1"), _any_ptr(t2, "t2"), prec, flags,
+                     ctypes.byref(tk))
+        return (tk.value, 0) if rc == OK else (None, rc)
+
+    def poll(self, ticket: int) -> bool:
+        d = _c_int(0)
+        _check(_poll(self._h, ticket, ctypes.byref(d)), "cc3_poll")
+        return bool(d.value)
+
+    def wait(self, ticket: int, omega1=None, omega2=None, mol: int | None = None,
+             want_result: bool = True):
+        """Block for `ticket`; returns (omega1, omega2, timing dict).  With
+        want_result and no output tensors given, device tensors are allocated
+        (the molecule id is needed for their shapes)."""
+        if want_result and omega1 is None and omega2 is None:
+            if mol is None:
+                raise ValueError("give output tensors or the molecule id")
+            no, nv = self._shape[mol]
+            dev = f"cuda:{self.device}"
+            omega1 = torch.empty((no, nv), dtype=torch.float64, device=dev)
+            omega2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=dev)
+        tm = Timing()
+        _check(_wait(self._h, ticket, _any_ptr(omega1, "omega1"), _any_ptr(omega2, "omega2"),
+                     ctypes.byref(tm)), "cc3_wait")
+        return omega1, omega2, tm.as_dict()
+
+    def wait_status(self, ticket: int) -> int:
+        """Collect a ticket without its result; returns the request's status code."""
+        return _wait(self._h, ticket, 0, 0, None)
+
+    def cancel(self, ticket: int) -> None:
+        _check(_cancel(self._h, ticket), "cc3_cancel")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_srv_stats(self._h, ctypes.byref(st)), "cc3_server_get_stats")
+        return st.as_dict()
+
+
+def _any_ptr(t, name: str) -> int:
+    """Pointer of a contiguous float64 tensor on the GPU or the host (None -> NULL)."""
+    if t is None:
+        return 0
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor")
+    return t.data_ptr()

@@ -1,0 +1,377 @@
+// Host-side core of libcc3: error reporting, kernel timing, the two-stream
+// runner, the workspace plan and the launch sequence of one residual
+// evaluation of Algorithm 1 (T1 transformation and integral blocks, the
+// batched restricted triple loop, the covariant back-transformation).
+#include "cc3_host.hpp"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+namespace cc3 {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+const char* last_error_str() { return g_err.c_str(); }
+
+int check_sizes(int no, int nv, int nchol, int prec) {
+  if (no < 1 || nv < 1) return fail(CC3_E_INVAL, "sizes must be positive (no=%d nv=%d)", no, nv);
+  if (nchol < 0) return fail(CC3_E_INVAL, "nchol must be >= 0 (got %d)", nchol);
+  if (no > 63 || nv > 1024)
+    return fail(CC3_E_INVAL, "sizes beyond the supported range no <= 63, nv <= 1024 (no=%d nv=%d)",
+                no, nv);
+  if (prec != CC3_FP64 && prec != CC3_FP32 && prec != CC3_BF16X3 && prec != CC3_BF16X6)
+    return fail(CC3_E_INVAL, "unknown precision %d", prec);
+  return CC3_OK;
+}
+
+int check_dev_ptr(const void* p, const char* what) {
+  if (!p) return fail(CC3_E_INVAL, "%s is NULL", what);
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CC3_E_INVAL, "%s is not device memory", what);
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+    return fail(CC3_E_INVAL, "%s is not device memory", what);
+  return CC3_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+const char* kFamilies[NFAM] = {"t1_transform", "block_build", "w_build", "mix",
+                               "omega_contract", "reduce", "back_transform"};
+
+hipEvent_t Profiler::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::reset() {
+  for (auto& t : timed) { pool.push_back(t.start); pool.push_back(t.stop); }
+  timed.clear();
+}
+
+int Profiler::collect(cc3_kernel_stat* out, int max, int* count) {
+  cc3_kernel_stat st[NFAM];
+  memset(st, 0, sizeof st);
+  for (int f = 0; f < NFAM; ++f) snprintf(st[f].name, sizeof st[f].name, "%s", kFamilies[f]);
+  for (auto& t : timed) {
+    HIPCHK(hipEventSynchronize(t.stop));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t.start, t.stop));
+    st[t.family].launches += 1;
+    st[t.family].total_ms += ms;
+    st[t.family].flops += t.flops;
+    st[t.family].bytes += t.bytes;
+  }
+  int n = 0;
+  for (int f = 0; f < NFAM && n < max; ++f)
+    if (st[f].launches > 0) out[n++] = st[f];
+  *count = n;
+  return CC3_OK;
+}
+
+void Profiler::destroy() {
+  for (auto& t : timed) { hipEventDestroy(t.start); hipEventDestroy(t.stop); }
+  for (auto e : pool) hipEventDestroy(e);
+  timed.clear();
+  pool.clear();
+}
+
+Timer::Timer(Profiler* pf_, hipStream_t st_, int fam, double flops, double bytes)
+    : pf(pf_), st(st_) {
+  on = pf && pf->on;
+  if (!on) return;
+  tl.family = fam;
+  tl.flops = flops;
+  tl.bytes = bytes;
+  tl.start = pf->take();
+  tl.stop = pf->take();
+  if (!tl.start || !tl.stop) { on = false; return; }
+  hipEventRecord(tl.start, st);
+}
+
+Timer::~Timer() {
+  if (!on) return;
+  hipEventRecord(tl.stop, st);
+  pf->timed.push_back(tl);
+}
+
+// ---------------------------------------------------------------------------
+// runner
+// ---------------------------------------------------------------------------
+int Runner::init() {
+  if (ready) return CC3_OK;
+  for (int k = 0; k < NSTREAM; ++k) {
+    if (hipStreamCreateWithFlags(&s[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_done[k], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_red[k], hipEventDisableTiming) != hipSuccess)
+      return fail(CC3_E_DEVICE, "could not create the internal streams");
+  }
+  if (hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess)
+    return fail(CC3_E_DEVICE, "could not create the internal streams");
+  ready = true;
+  return CC3_OK;
+}
+
+void Runner::destroy() {
+  if (!ready) return;
+  for (int k = 0; k < NSTREAM; ++k) {
+    hipStreamDestroy(s[k]);
+    hipEventDestroy(ev_done[k]);
+    hipEventDestroy(ev_red[k]);
+  }
+  hipEventDestroy(ev_fork);
+  ready = false;
+}
+
+// ---------------------------------------------------------------------------
+// plan and workspace
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int env_int(const char* name, int dflt) {
+  const char* s = getenv(name);
+  if (!s || !*s) return dflt;
+  int v = atoi(s);
+  return v > 0 ? v : dflt;
+}
+
+size_t block_bytes(int no, int nv) {
+  const size_t o = no, v = nv;
+  return align256(o * v * v * v * 8) * 2 + align256(o * o * o * v * 8) * 2 +
+         align256(o * o * v * v * 8) + align256(o * v * 8);
+}
+
+Blocks carve_blocks(int no, int nv, void* base) {
+  const size_t o = no, v = nv;
+  char* b = (char*)base;
+  Blocks bl;
+  bl.Gw = (double*)b; b += align256(o * v * v * v * 8);
+  bl.Gv = (double*)b; b += align256(o * v * v * v * 8);
+  bl.Go = (double*)b; b += align256(o * o * o * v * 8);
+  bl.Hs = (double*)b; b += align256(o * o * o * v * 8);
+  bl.Jo = (double*)b; b += align256(o * o * v * v * 8);
+  bl.F = (double*)b;
+  return bl;
+}
+
+int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_blocks,
+                 size_t cube_budget, Plan* p) {
+  memset(p, 0, sizeof *p);
+  p->no = no; p->nv = nv; p->nchol = nchol; p->prec = prec; p->flags = flags;
+  const size_t o = no, v = nv, J = nchol;
+  p->ntri = (int)((size_t)no * (no + 1) * (no + 2) / 6 - no);
+  p->cube = v * v * v;
+  // triples per batch: enough W-build workgroups per launch to fill 256 CUs
+  // many times over, bounded by a cube-memory budget
+  const size_t wg_per_triple = 3 * v * ((v + 127) / 128) * ((v + 127) / 128);
+  int batch = (int)std::max<size_t>(1, (size_t)(12288 + wg_per_triple - 1) / wg_per_triple);
+  const size_t budget =
+      cube_budget ? cube_budget : ((size_t)env_int("CC3_CUBE_BUDGET_MB", 4096) << 20);
+  const size_t per_triple = 5 * p->cube * sizeof(double);
+  batch = (int)std::min<size_t>((size_t)batch, std::max<size_t>(1, budget / per_triple));
+  batch = env_int("CC3_BATCH", batch);
+  batch = std::min(batch, 160);  // the reduction lists at most 6 * 160 pairs per p
+  batch = std::max(1, std::min(batch, std::max(1, p->ntri)));
+  p->batch = batch;
+  // largest (triples x chunks) product over the batch sizes the loop can see
+  size_t tc = 1;
+  for (int nb = 1; nb <= batch; ++nb) tc = std::max(tc, (size_t)nb * omega_nbchunks(nv, nb));
+  p->pvv_entries = tc;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+  p->off_blocks = with_blocks ? take(block_bytes(no, nv)) : 0;
+  p->off_Ot1 = take(o * v * 8);
+  p->off_Ot2 = take(o * o * v * v * 8);
+  p->off_OtT = take(o * o * v * v * 8);
+  p->off_t2N = take(o * o * v * v * 8);
+  p->off_lp = take(lp_operand_bytes(prec, no, nv));
+  p->pvv_bytes = align256(tc * 6 * v * (v + 1) * 8);
+  p->soo_bytes = align256((size_t)batch * 6 * o * v * v * 8);
+  p->off_Pvv = take(2 * p->pvv_bytes);
+  p->off_Soo = take(2 * p->soo_bytes);
+  p->off_tri = take((size_t)std::max(1, p->ntri) * 3 * sizeof(int) + 64);
+  p->off_flag = take(64);
+  // the Cholesky scratch is dead once the blocks are built: it shares the cube region
+  p->chol_bytes = J ? align256(J * v * v * 8) * 2 + align256(J * o * o * 8) * 2 +
+                          align256(J * o * v * 8) * 2 + align256(J * 8) + align256(J * o * o * 8)
+                    : 0;
+  p->cube_bytes = align256((size_t)batch * 5 * p->cube * 8);
+  p->off_cubes = take(std::max(p->chol_bytes, 2 * p->cube_bytes));
+  p->off_chol = p->off_cubes;
+  p->total = off;
+  return CC3_OK;
+}
+
+Ws carve(const Plan& p, void* ws, const Blocks* external_blocks) {
+  char* base = (char*)ws;
+  Ws w;
+  w.b = external_blocks ? *external_blocks : carve_blocks(p.no, p.nv, base + p.off_blocks);
+  w.Ot1 = (double*)(base + p.off_Ot1);
+  w.Ot2 = (double*)(base + p.off_Ot2);
+  w.OtT = (double*)(base + p.off_OtT);
+  w.t2N = (double*)(base + p.off_t2N);
+  lp_operand_ptrs(p.prec, p.no, p.nv, base + p.off_lp, w.lp);
+  for (int k = 0; k < 2; ++k) {
+    w.Pvv[k] = (double*)(base + p.off_Pvv + k * p.pvv_bytes);
+    w.Soo[k] = (double*)(base + p.off_Soo + k * p.soo_bytes);
+    w.cubes[k] = (double*)(base + p.off_cubes + k * p.cube_bytes);
+  }
+  w.tri = (int*)(base + p.off_tri);
+  w.flag = (int*)(base + p.off_flag);
+  const size_t J = p.nchol, o = p.no, v = p.nv;
+  char* c = base + p.off_chol;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* at = c + off; off = align256(off + bytes); return (double*)at; };
+  w.cs.Lvv = take(J * v * v * 8);
+  w.cs.LvvT = take(J * v * v * 8);
+  w.cs.Loo = take(J * o * o * 8);
+  w.cs.LooT = take(J * o * o * 8);
+  w.cs.LvoT = take(J * o * v * 8);
+  w.cs.Lov = take(J * o * v * 8);
+  w.cs.s = take(J * 8);
+  w.cs.M = take(J * o * o * 8);
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// launch sequences
+// ---------------------------------------------------------------------------
+static void host_triples(int no, std::vector<int>& t) {
+  t.clear();
+  for (int i = 0; i < no; ++i)
+    for (int j = 0; j <= i; ++j)
+      for (int k = 0; k <= j; ++k)
+        if (!(i == j && j == k)) { t.push_back(i); t.push_back(j); t.push_back(k); }
+}
+
+static int kind_of(int i, int j, int k) { return (i == j) ? 1 : (j == k) ? 2 : 0; }
+
+int prepare_cholesky(Profiler* pf, const Plan& p, const Ws& w, const double* L, const double* t1,
+                     hipStream_t st) {
+  {
+    Timer tm(pf, st, FAM_T1, 0.0, 0.0);
+    launch_t1_transform(L, t1, w.cs, p.no, p.nv, p.nchol, st);
+    launch_fock(t1, w.cs, w.b.F, p.no, p.nv, p.nchol, st);
+  }
+  {
+    const double v = p.nv, o = p.no, J = p.nchol;
+    const double fl = 2.0 * J * (2.0 * v * v * v * o + o * o * v * v + 2.0 * o * o * o * v);
+    Timer tm(pf, st, FAM_BUILD, fl, 0.0);
+    launch_build_blocks(w.cs, w.b, p.no, p.nv, p.nchol, st);
+  }
+  HIPCHK(hipGetLastError());
+  return CC3_OK;
+}
+
+// The batched triple loop over a device triple table `tri` of n entries whose
+// host copy is `ht` (for FLOP accounting only).  Batch b runs on runner
+// stream b % 2 with buffer set b % 2; reduction b waits for reduction b - 1.
+// Forks from and joins back to `st`.
+int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const double* eps,
+                const double* t2, const int* tri, const int* ht, int n, hipStream_t st) {
+  int rc = rn.init();
+  if (rc) return rc;
+  std::vector<int> kinds;
+  launch_t2N(t2, w.t2N, p.no, p.nv, st);
+  if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, p.no, p.nv, w.lp, st);
+  HIPCHK(hipEventRecord(rn.ev_fork, st));
+  for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
+  int nbatch = 0;
+  for (int t0 = 0; t0 < n; t0 += p.batch, ++nbatch) {
+    const int nb = std::min(p.batch, n - t0);
+    const int k = nbatch % NSTREAM;
+    hipStream_t sk = rn.s[k];
+    kinds.resize(nb);
+    for (int t = 0; t < nb; ++t)
+      kinds[t] = kind_of(ht[3 * (t0 + t)], ht[3 * (t0 + t) + 1], ht[3 * (t0 + t) + 2]);
+    const int* tb = tri + 3 * t0;
+    {
+      Timer tm(pf, sk, FAM_W, wbuild_flops(p.no, p.nv, kinds.data(), nb), 0.0);
+      if (p.prec == CC3_FP64)
+        launch_wbuild(t2, w.t2N, w.b, tb, nb, w.cubes[k], p.no, p.nv, false, sk);
+      else
+        launch_wbuild_lp(w.lp, tb, nb, w.cubes[k], p.no, p.nv, false, sk);
+    }
+    {
+      Timer tm(pf, sk, FAM_MIX, 0.0, 0.0);
+      launch_mix(eps, tb, nb, w.cubes[k], p.no, p.nv, sk);
+    }
+    {
+      Timer tm(pf, sk, FAM_OMEGA, omega_flops(p.no, p.nv, kinds.data(), nb), 0.0);
+      launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], w.Soo[k], p.no, p.nv, sk);
+    }
+    if (nbatch > 0) HIPCHK(hipStreamWaitEvent(sk, rn.ev_red[(nbatch - 1) % NSTREAM], 0));
+    {
+      Timer tm(pf, sk, FAM_REDUCE, 0.0, 0.0);
+      launch_reduce(tb, nb, w.Pvv[k], w.Soo[k], w.Ot1, w.Ot2, w.OtT, p.no, p.nv, sk);
+    }
+    HIPCHK(hipEventRecord(rn.ev_red[k], sk));
+  }
+  for (int k = 0; k < NSTREAM; ++k) {
+    HIPCHK(hipEventRecord(rn.ev_done[k], rn.s[k]));
+    HIPCHK(hipStreamWaitEvent(st, rn.ev_done[k], 0));
+  }
+  HIPCHK(hipGetLastError());
+  return CC3_OK;
+}
+
+int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const double* eps,
+                         const double* t2, double* omega1, double* omega2, bool accumulate,
+                         hipStream_t st) {
+  const int no = p.no, nv = p.nv;
+  launch_fill(w.Ot1, (int64_t)no * nv, 0.0, st);
+  launch_fill(w.Ot2, (int64_t)no * no * nv * nv, 0.0, st);
+  launch_fill(w.OtT, (int64_t)no * no * nv * nv, 0.0, st);
+  launch_triple_table(w.tri, no, st);
+  std::vector<int> ht;
+  host_triples(no, ht);
+  int rc = triple_loop(rn, pf, p, w, eps, t2, w.tri, ht.data(), p.ntri, st);
+  if (rc) return rc;
+  {
+    Timer tm(pf, st, FAM_BACK, 0.0, 0.0);
+    launch_back_transform(w.Ot1, w.Ot2, w.OtT, omega1, omega2, no, nv, accumulate, st);
+  }
+  HIPCHK(hipGetLastError());
+  return CC3_OK;
+}
+
+// CC3_CHECK: blocks the host until the input check has run.
+int run_input_check(const Plan& p, const Ws& w, const double* eps, const double* L,
+                    const double* t2, hipStream_t st) {
+  launch_check(eps, L, t2, p.no, p.nv, p.nchol, w.flag, st);
+  int bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, w.flag, sizeof bits, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bits & 1) return fail(CC3_E_PRECOND, "t2 violates t2[i][j][a][b] == t2[j][i][b][a]");
+  if (bits & 2) return fail(CC3_E_PRECOND, "L violates L[J][p][q] == L[J][q][p]");
+  if (bits & 4) return fail(CC3_E_PRECOND, "a denominator eps^{abc}_{ijk} is not positive");
+  return CC3_OK;
+}
+
+}  // namespace cc3

@@ -1,4 +1,4 @@
-// Host-side declarations shared by the C ABI (cc3_api.cpp) and the kernel
+// Host-side declarations shared by the host core (cc3_core.cpp) and the kernel
 // translation units: the workspace plan and the kernel launchers.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -39,7 +39,7 @@ struct Plan {
   size_t pvv_entries;  // max (triples x b-chunks) of one Omega launch
   size_t cube;  // doubles per nv^3 cube
   // byte offsets into the workspace
-  size_t off_Gw, off_Go, off_Gv, off_Jo, off_Hs, off_F;
+  size_t off_blocks;  // integral blocks (when the workspace holds them)
   size_t off_Ot1, off_Ot2, off_OtT, off_lp, off_t2N, off_Pvv, off_Soo, off_tri, off_flag, off_cubes;
   size_t off_chol;  // Cholesky scratch (aliases the cube region)
   size_t chol_bytes, cube_bytes, pvv_bytes, soo_bytes;  // per buffer set (two sets)
@@ -58,10 +58,9 @@ void launch_lp_convert(const double* t2, const Blocks& b, int no, int nv, const 
 void launch_wbuild_lp(const LpOperands& lp, const int* tri, int ntri, double* cubes, int no, int nv,
                       bool all_terms, hipStream_t st);
 
-int make_plan(int no, int nv, int nchol, int prec, unsigned flags, Plan* p, int batch_override);
-
 // ---- launchers (all enqueue on `st`) ----
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+void launch_add(double* y, const double* x, int64_t n, hipStream_t st);  // y += x
 void launch_t1_transform(const double* L, const double* t1, const CholeskyScratch& cs, int no,
                          int nv, int nJ, hipStream_t st);
 void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no, int nv, int nJ,

@@ -23,6 +23,19 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(g), dim3(256), 0, st, p, n, v);
 }
 
+__global__ void k_add(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) y[i] += x[i];
+}
+
+void launch_add(double* y, const double* x, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  unsigned g = nblk(n, 256);
+  if (g > 65536u) g = 65536u;
+  hipLaunchKernelGGL(k_add, dim3(g), dim3(256), 0, st, y, x, n);
+}
+
 // ---------------------------------------------------------------------------
 // T1 transformation (exp(-T1) H exp(T1)):  Lt = (1 - t) L (1 + t), t[no+a][i] = t1[i][a].
 //   Lt_bd = L_bd - sum_l t1[l][b] L_ld        Lt_lj = L_lj + sum_d L_ld t1[j][d]

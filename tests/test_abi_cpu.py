@@ -91,3 +91,32 @@ def test_product_never_touches_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "cc3_oracle" not in text and "bruteforce" not in text, fn
+
+
+def test_serving_calls_validate_without_a_device(lib):
+    """Null server handles and null out-pointers are rejected before any HIP call."""
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.cc3_server_create.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_int]
+    assert lib.cc3_server_create(None, 0, None, 0, 1) == -1
+    h = ctypes.c_void_p()
+    assert lib.cc3_server_create(ctypes.byref(h), 0, None, 1 << 20, 0) == -1  # max_inflight
+    assert lib.cc3_server_create(ctypes.byref(h), 0, None, 1 << 20, 9) == -1
+    lib.cc3_server_footprint.argtypes = [ctypes.c_void_p] + [ctypes.c_int] * 4 + [
+        ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.cc3_server_footprint(None, 4, 20, 60, 0, None, None) == -1
+    lib.cc3_submit.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, u64p]
+    assert lib.cc3_submit(None, 1, None, None, 0, 0, None) == -1
+    lib.cc3_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+    assert lib.cc3_poll(None, 1, None) == -1
+    lib.cc3_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64] + [ctypes.c_void_p] * 3
+    assert lib.cc3_wait(None, 1, None, None, None) == -1
+    lib.cc3_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    assert lib.cc3_cancel(None, 1) == -1
+    lib.cc3_molecule_release.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    assert lib.cc3_molecule_release(None, 1) == -1
+    lib.cc3_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.cc3_server_get_stats(None, None) == -1
+    lib.cc3_server_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.cc3_server_destroy(None) == 0
