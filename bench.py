@@ -103,6 +103,167 @@ def cpu_baseline(no: int, nv: int, nchol: int, budget_s: float) -> dict:
             "seconds_per_call": t_call}
 
 
+PREC_NAMES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+
+
+def _pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def serve(n_mol: int, n_calls: int, prec_name: str, slots: int, load: float,
+          small_arena_gb: float, seed: int = 5) -> dict:
+    """Serving mix: molecules with no ~ U[5,20], nv ~ U[60,250], Cholesky rank
+    3(no+nv), each issuing `n_calls` closed-loop residual calls (the next call
+    goes out when the previous result is back, with t2 perturbed as by a solver
+    iteration); first calls arrive as a Poisson process at `load` times the
+    capacity measured in a saturating run.  Everything goes through the
+    library's serving loop (arena admission, concurrent slots)."""
+    import torch
+
+    from paper_2007_01088_amd import cc3
+    from paper_2007_01088_amd.synth import (make_inputs_device, perturb_t2_device,
+                                            poisson_arrivals, serving_mix)
+    prec = PREC_NAMES[prec_name]
+    mix = serving_mix(n_mol, seed)
+    nominal = [cc3.flops(no, nv)[0] for no, nv, _ in mix]
+    dev = "cuda:0"
+    free, _ = torch.cuda.mem_get_info()
+    t2_bytes = sum(no * no * nv * nv * 8 for no, nv, _ in mix)
+    arena_bytes = int((free - 2 * t2_bytes - (24 << 30)) * 0.9) & ~255
+    log(f"serving: {n_mol} molecules x {n_calls} calls, prec {prec_name}, {slots} slots, "
+        f"arena {arena_bytes / 2**30:.1f} GiB")
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    srv = cc3.Server(arena, max_inflight=slots)
+    mols, t2s = [], []
+    resident = 0
+    for m, (no, nv, nJ) in enumerate(mix):
+        d = make_inputs_device(no, nv, nJ, tag=1000 + m, device=dev)
+        mols.append(srv.register(no, nv, d["eps"], d["L"], d["t1"]))
+        t2s.append(d["t2"])
+        resident += srv.footprint(no, nv, nJ, prec)[0]
+        del d
+    torch.cuda.synchronize()
+    log(f"serving: registered {n_mol} molecules, {resident / 2**30:.1f} GiB resident")
+    # warm-up call: loads the code objects and creates the slot streams
+    srv.wait(srv.submit(mols[0], t2s[0], prec=prec), want_result=False)
+
+    def finish_all(tickets):
+        out = {}
+        for t, m in tickets.items():
+            _, _, tm = srv.wait(t, want_result=False)
+            out[m] = tm
+        return out
+
+    # capacity: every molecule submits one call at once
+    tks = {srv.submit(mols[m], t2s[m], prec=prec): m for m in range(n_mol)}
+    tms = finish_all(tks)
+    t_first = min(tm["arrival_s"] for tm in tms.values())
+    t_last = max(tm["finish_s"] for tm in tms.values())
+    cap_rps = n_mol / (t_last - t_first)
+    cap_tflops = sum(nominal) / (t_last - t_first) / 1e12
+    log(f"serving: saturated capacity {cap_rps:.2f} requests/s, {cap_tflops:.2f} TFLOP/s")
+
+    # Poisson arrivals of first calls at `load` x capacity, then closed loops
+    lam = load * cap_rps / n_calls
+    arr = poisson_arrivals(n_mol, lam, seed)
+    calls_left = [n_calls] * n_mol
+    pending = {}
+    lat, lat_host, qwait, dev_ms, fin, arr_s, flop_done = [], [], [], [], [], [], 0.0
+    t0 = time.perf_counter()
+    nxt = 0
+    done = 0
+    last_log = t0
+    it_seed = 0
+    while done < n_mol * n_calls:
+        now = time.perf_counter() - t0
+        while nxt < n_mol and arr[nxt] <= now:
+            t = srv.submit(mols[nxt], t2s[nxt], prec=prec)
+            pending[t] = (nxt, time.perf_counter())
+            nxt += 1
+        for t in [t for t in pending if srv.poll(t)]:
+            m, t_issue = pending.pop(t)
+            _, _, tm = srv.wait(t, want_result=False)
+            lat_host.append(time.perf_counter() - t_issue)
+            lat.append(tm["finish_s"] - tm["arrival_s"])
+            qwait.append(tm["admit_s"] - tm["arrival_s"])
+            dev_ms.append(tm["device_ms"])
+            fin.append(tm["finish_s"])
+            arr_s.append(tm["arrival_s"])
+            flop_done += nominal[m]
+            done += 1
+            calls_left[m] -= 1
+            if calls_left[m] > 0:
+                it_seed += 1
+                t2s[m] = perturb_t2_device(t2s[m], seed=it_seed)
+                t = srv.submit(mols[m], t2s[m], prec=prec)
+                pending[t] = (m, time.perf_counter())
+        if time.perf_counter() - last_log > 20:
+            last_log = time.perf_counter()
+            log(f"serving: {done}/{n_mol * n_calls} calls done")
+        time.sleep(0.0002)
+    makespan = max(fin) - min(arr_s)
+    st = srv.stats()
+    res = {
+        "molecules": n_mol, "calls_per_molecule": n_calls, "requests": n_mol * n_calls,
+        "reading": "closed loop per molecule (next call when the previous result is back, "
+                   "t2 perturbed by N(0,1e-4^2)), Poisson first arrivals",
+        "prec": prec_name, "slots": slots, "arena_gib": arena_bytes / 2**30,
+        "resident_gib": resident / 2**30,
+        "capacity_requests_per_s": cap_rps, "capacity_tflops": cap_tflops,
+        "arrival_rate_molecules_per_s": lam, "load": load,
+        "p50_ms": _pct(lat, 50) * 1e3, "p99_ms": _pct(lat, 99) * 1e3,
+        "p50_ms_host": _pct(lat_host, 50) * 1e3, "p99_ms_host": _pct(lat_host, 99) * 1e3,
+        "queue_wait_p50_ms": _pct(qwait, 50) * 1e3, "queue_wait_p99_ms": _pct(qwait, 99) * 1e3,
+        "device_ms_p50": _pct(dev_ms, 50), "device_ms_p99": _pct(dev_ms, 99),
+        "aggregate_tflops": flop_done / makespan / 1e12, "makespan_s": makespan,
+        "max_inflight_seen": st["max_inflight_seen"], "arena_peak_gib": st["arena_peak"] / 2**30,
+    }
+    log(f"serving: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms, "
+        f"{res['aggregate_tflops']:.2f} TFLOP/s aggregate")
+    srv.close()
+    del arena
+    torch.cuda.empty_cache()
+
+    if small_arena_gb > 0:
+        # admission under memory pressure: a small arena, molecules that fit, all at once
+        nbytes = int(small_arena_gb * 2**30) & ~255
+        arena = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        srv = cc3.Server(arena, max_inflight=slots)
+        sub, used, tr_max = [], 0, 0
+        for m, (no, nv, nJ) in enumerate(mix):
+            r, tr = srv.footprint(no, nv, nJ, prec)
+            if used + r + max(tr_max, tr) <= nbytes * 0.98:
+                sub.append(m)
+                used += r
+                tr_max = max(tr_max, tr)
+        ids = {}
+        for m in sub:
+            no, nv, nJ = mix[m]
+            d = make_inputs_device(no, nv, nJ, tag=1000 + m, device=dev)
+            ids[m] = srv.register(no, nv, d["eps"], d["L"], d["t1"])
+            del d
+        tks = {srv.submit(ids[m], t2s[m], prec=prec): m for m in sub}
+        tms = finish_all(tks)
+        st = srv.stats()
+        lat_s = [tm["finish_s"] - tm["arrival_s"] for tm in tms.values()]
+        q_s = [tm["admit_s"] - tm["arrival_s"] for tm in tms.values()]
+        span = max(tm["finish_s"] for tm in tms.values()) - min(tm["arrival_s"] for tm in tms.values())
+        res["small_arena"] = {
+            "arena_gib": nbytes / 2**30, "molecules": len(sub), "resident_gib": used / 2**30,
+            "largest_request_gib": tr_max / 2**30, "submitted_at_once": len(sub),
+            "max_inflight_seen": st["max_inflight_seen"], "arena_peak_gib": st["arena_peak"] / 2**30,
+            "p50_ms": _pct(lat_s, 50) * 1e3, "p99_ms": _pct(lat_s, 99) * 1e3,
+            "queue_wait_p50_ms": _pct(q_s, 50) * 1e3, "queue_wait_p99_ms": _pct(q_s, 99) * 1e3,
+            "aggregate_tflops": sum(nominal[m] for m in sub) / span / 1e12,
+        }
+        log(f"serving, small arena: {len(sub)} molecules, max in flight "
+            f"{st['max_inflight_seen']}, p99 {res['small_arena']['p99_ms']:.1f} ms")
+        srv.close()
+        del arena
+        torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +275,15 @@ def main() -> int:
                     help="skip timing the mixed-precision W contractions (FP32, BF16x3, BF16x6)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-molecules", type=int, default=16,
+                    help="serving mix size (0 skips the serving measurement)")
+    ap.add_argument("--serve-calls", type=int, default=2, help="closed-loop calls per molecule")
+    ap.add_argument("--serve-prec", default="fp32", choices=sorted(PREC_NAMES))
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-small-arena-gb", type=float, default=8.0)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="print the serving measurement as the JSON line (no residual timing)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, used to scale hardware byte counters)")
@@ -124,10 +294,29 @@ def main() -> int:
               "launch.", file=sys.stderr)
         return 2
 
+    if args.serve_molecules > 0 and "GPU_MAX_HW_QUEUES" not in os.environ:
+        # every serving slot uses two streams and the server one more for its copies;
+        # streams beyond the runtime's hardware-queue count would wait on each other
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, 2 * args.serve_slots + 4))
     import torch
 
     from paper_2007_01088_amd import cc3
     from paper_2007_01088_amd.synth import make_inputs
+
+    if args.serve_only:
+        res = serve(args.serve_molecules, args.serve_calls, args.serve_prec, args.serve_slots,
+                    args.serve_load, args.serve_small_arena_gb)
+        print(json.dumps({
+            "metric": "Serving p50/p99 latency (ms) and aggregate TFLOP/s (4nv^4no^3/call)",
+            "value": res["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": res["requests"],
+            "warmup": 1, "ms_per_step": res["makespan_s"] * 1e3 / res["requests"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": res["prec"], "data": "synthetic (seeded Cholesky-factored molecules)",
+            "config": {"workload": f"serving mix: {res['molecules']} molecules, no U[5,20], "
+                                   f"nv U[60,250], nchol 3(no+nv), {res['calls_per_molecule']} "
+                                   "closed-loop calls each, Poisson arrivals"},
+            "serving": res}), flush=True)
+        return 0
 
     no, nv, nchol = WORKLOADS[args.workload]
     log(f"workload {args.workload}: no={no} nv={nv} nchol={nchol} prec={args.prec}")
@@ -229,6 +418,12 @@ def main() -> int:
     }
     if mixed:
         out["mixed"] = mixed
+    if args.serve_molecules > 0:
+        ctx.close()
+        del g, o1, o2
+        torch.cuda.empty_cache()
+        out["serving"] = serve(args.serve_molecules, args.serve_calls, args.serve_prec,
+                               args.serve_slots, args.serve_load, args.serve_small_arena_gb)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(no, nv, nchol, args.cpu_budget)

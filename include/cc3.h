@@ -201,12 +201,17 @@ int cc3_profile_get(cc3_ctx* ctx, cc3_kernel_stat* out, int max, int* count);
  * caller may reuse its buffers at once.  The library allocates no device
  * memory here: everything lives in the arena (the server's streams and events
  * are the only other device resources).  All calls are thread-safe.
+ * Each slot uses two HIP streams and the server one more for its copies; the
+ * runtime multiplexes streams onto a fixed number of hardware queues
+ * (GPU_MAX_HW_QUEUES, 4 by default), and streams that share a queue wait for
+ * each other, so a process serving with max_inflight slots should allow at
+ * least 2 * max_inflight + 2 hardware queues.
  * Clock: the timestamps of cc3_timing are seconds on a steady host clock
  * whose zero is the server's creation. */
 typedef struct cc3_server cc3_server;
 
 typedef struct cc3_timing {
-  double arrival_s; /* the request was queued (inside cc3_submit, after its input copies) */
+  double arrival_s; /* cc3_submit was entered (before its input copies) */
   double admit_s;   /* workspace granted from the arena and the work enqueued on a slot */
   double start_s;   /* the device began the request's first kernel (device clock mapped to host) */
   double finish_s;  /* the server observed the request's completion */

@@ -286,8 +286,16 @@ class Server:
                "cc3_server_footprint")
         return r.value, t.value
 
+    @staticmethod
+    def _ready(*ts) -> None:
+        # the server copies on a stream of its own: work queued on torch's
+        # current stream that produces these inputs must be complete first
+        if any(t is not None and t.is_cuda for t in ts):
+            torch.cuda.current_stream().synchronize()
+
     def register(self, no: int, nv: int, eps, L, t1=None) -> int:
         """Copy a molecule's eps, L (and t1; None = zero) into the arena; returns its id."""
+        self._ready(eps, L, t1)
         nchol = L.shape[0]
         mol = _u64(0)
         _check(_mol_register(self._h, no, nv, nchol, _any_ptr(eps, "eps"), _any_ptr(L, "L"),
@@ -300,6 +308,7 @@ class Server:
         self._shape.pop(mol, None)
 
     def submit(self, mol: int, t2, t1=None, prec: int = FP64, flags: int = 0) -> int:
+        self._ready(t2, t1)
         tk = _u64(0)
         _check(_submit(self._h, mol, _any_ptr(t1, "t1"), _any_ptr(t2, "t2"), prec, flags,
                        ctypes.byref(tk)), "cc3_submit")
@@ -307,6 +316,7 @@ class Server:
 
     def try_submit(self, mol: int, t2, t1=None, prec: int = FP64, flags: int = 0):
         """(ticket, 0) or (None, error code) without raising."""
+        self._ready(t2, t1)
         tk = _u64(0)
         rc = _submit(self._h, mol, _any_ptr(t1, "t1"), _any_ptr(t2, "t2"), prec, flags,
                      ctypes.byref(tk))
@@ -329,6 +339,7 @@ class Server:
             dev = f"cuda:{self.device}"
             omega1 = torch.empty((no, nv), dtype=torch.float64, device=dev)
             omega2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=dev)
+        self._ready(omega1, omega2)  # CC3_ACCUMULATE adds into their current contents
         tm = Timing()
         _check(_wait(self._h, ticket, _any_ptr(omega1, "omega1"), _any_ptr(omega2, "omega2"),
                      ctypes.byref(tm)), "cc3_wait")

@@ -124,11 +124,14 @@ Timer::~Timer() {
 // ---------------------------------------------------------------------------
 // runner
 // ---------------------------------------------------------------------------
-int Runner::init() {
+int Runner::init(hipStream_t s0) {
   if (ready) return CC3_OK;
+  own0 = (s0 == nullptr);
+  if (!own0) s[0] = s0;
   for (int k = 0; k < NSTREAM; ++k) {
-    if (hipStreamCreateWithFlags(&s[k], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ev_done[k], hipEventDisableTiming) != hipSuccess ||
+    if ((k > 0 || own0) && hipStreamCreateWithFlags(&s[k], hipStreamNonBlocking) != hipSuccess)
+      return fail(CC3_E_DEVICE, "could not create the internal streams");
+    if (hipEventCreateWithFlags(&ev_done[k], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ev_red[k], hipEventDisableTiming) != hipSuccess)
       return fail(CC3_E_DEVICE, "could not create the internal streams");
   }
@@ -141,7 +144,7 @@ int Runner::init() {
 void Runner::destroy() {
   if (!ready) return;
   for (int k = 0; k < NSTREAM; ++k) {
-    hipStreamDestroy(s[k]);
+    if (k > 0 || own0) hipStreamDestroy(s[k]);
     hipEventDestroy(ev_done[k]);
     hipEventDestroy(ev_red[k]);
   }
@@ -302,10 +305,12 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
   if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, p.no, p.nv, w.lp, st);
   HIPCHK(hipEventRecord(rn.ev_fork, st));
   for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
+  // CC3_SERIAL=1 keeps every batch on one stream (kernel durations without overlap)
+  static const int nstream = env_int("CC3_SERIAL", 0) ? 1 : NSTREAM;
   int nbatch = 0;
   for (int t0 = 0; t0 < n; t0 += p.batch, ++nbatch) {
     const int nb = std::min(p.batch, n - t0);
-    const int k = nbatch % NSTREAM;
+    const int k = nbatch % nstream;
     hipStream_t sk = rn.s[k];
     kinds.resize(nb);
     for (int t = 0; t < nb; ++t)
@@ -326,7 +331,7 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
       Timer tm(pf, sk, FAM_OMEGA, omega_flops(p.no, p.nv, kinds.data(), nb), 0.0);
       launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], w.Soo[k], p.no, p.nv, sk);
     }
-    if (nbatch > 0) HIPCHK(hipStreamWaitEvent(sk, rn.ev_red[(nbatch - 1) % NSTREAM], 0));
+    if (nbatch > 0) HIPCHK(hipStreamWaitEvent(sk, rn.ev_red[(nbatch - 1) % nstream], 0));
     {
       Timer tm(pf, sk, FAM_REDUCE, 0.0, 0.0);
       launch_reduce(tb, nb, w.Pvv[k], w.Soo[k], w.Ot1, w.Ot2, w.OtT, p.no, p.nv, sk);

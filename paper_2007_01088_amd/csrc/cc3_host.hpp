@@ -65,9 +65,12 @@ struct Timer {
 enum { NSTREAM = 2 };
 struct Runner {
   bool ready = false;
+  bool own0 = true;  // false: s[0] is the caller's stream
   hipStream_t s[NSTREAM];
   hipEvent_t ev_fork, ev_done[NSTREAM], ev_red[NSTREAM];
-  int init();
+  // Creates the streams; with `s0` given, batches alternate between s0 and
+  // one stream of the runner's own (fewer streams per concurrent request).
+  int init(hipStream_t s0 = nullptr);
   void destroy();
 };
 

@@ -208,6 +208,8 @@ int cc3_server::launch(uint64_t, Request& r, Molecule& m, Slot& s) {
     HIPCHK(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
     HIPCHK(hipEventCreate(&s.ev0));
     HIPCHK(hipEventCreate(&s.ev1));
+    int rc0 = s.rn.init(s.st);  // the slot's stream carries every other batch
+    if (rc0) return rc0;
   }
   const Plan& p = r.plan;
   Ws w = carve(p, arena + r.off, &m.b);
@@ -495,6 +497,7 @@ extern "C" int cc3_submit(cc3_server* s, uint64_t mol, const double* t1, const d
   const size_t o = m->no, v = m->nv;
   int rc = check_span(t2, o * o * v * v * 8, "t2");
   if (!rc && t1) rc = check_span(t1, o * v * 8, "t1");
+  const double arrival = now_s(s->t0);
   if (!rc) {
     std::lock_guard<std::mutex> g(s->up_mu);
     hipError_t e = hipSetDevice(s->device);
@@ -522,7 +525,7 @@ extern "C" int cc3_submit(cc3_server* s, uint64_t mol, const double* t1, const d
   r.flags = flags;
   r.rebuild = (t1 != nullptr) || !m->blocks_valid;
   r.plan = p;
-  r.tm.arrival_s = now_s(s->t0);
+  r.tm.arrival_s = arrival;
   r.tm.slot = -1;
   m->blocks_valid = true;  // once this request has run (reset if it fails)
   s->reqs.emplace(t, r);

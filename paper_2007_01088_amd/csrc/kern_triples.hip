@@ -415,7 +415,7 @@ template <int FNO>
 __global__ __launch_bounds__(OCfg::NT) void k_omega(
     const double* __restrict__ cubes, const double* __restrict__ Gv, const double* __restrict__ Jo,
     const double* __restrict__ Hs, const int* __restrict__ tri, double* __restrict__ Pvv,
-    double* __restrict__ Soo, int no, int nv, int bchunk, int nbchunks, int tiles_n) {
+    double* __restrict__ Soo, int no, int nv, int nbchunks, int tiles_n) {
   typedef OCfg T;
   constexpr int BO = 16 * FNO;  // oo rows per tile (no of them used, plus the Omega1 row)
   constexpr int EO = (BO * T::BK + T::NT - 1) / T::NT;
@@ -432,8 +432,9 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
   const int tile = blockIdx.x / nbchunks;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
   const bool do_oo = (tile % tiles_n) == 0;
-  const int bb0 = bc * bchunk;
-  const int bb1 = min(nv, bb0 + bchunk);
+  // balanced b chunks [bb0, bb1); nbchunks <= nv, so none is empty
+  const int bb0 = (int)((int64_t)bc * nv / nbchunks);
+  const int bb1 = (int)((int64_t)(bc + 1) * nv / nbchunks);
   if (bb0 >= bb1) return;
 
   const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
@@ -638,14 +639,24 @@ __global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int
 
 // Number of b chunks the Omega GEMM of one (triple, permutation) is split into:
 // enough workgroups for 256 CUs at two per CU, no more.
+// Split-K chunks of the b index per (triple, permutation, tile): enough
+// workgroups for several rounds over the chip (two resident per CU), as a
+// multiple of 8 so that the tiles of one (triple, permutation, chunk) -- which
+// share their A or B operand rows -- are dispatched to the same XCD (workgroups
+// go round-robin over the 8 XCDs in linear order, and tiles of one chunk are
+// nbchunks apart) and meet in its L2.
 int omega_nbchunks(int nv, int ntri) {
+  static const int target = [] {
+    const char* e = getenv("CC3_OMEGA_WG");
+    const int v = e ? atoi(e) : 0;
+    return v > 0 ? v : 2048;
+  }();
   const int tm = (nv + OCfg::BM - 1) / OCfg::BM, tn = (nv + OCfg::BN - 1) / OCfg::BN;
   const int per = 6 * tm * tn * (ntri > 0 ? ntri : 1);
-  int nbc = (640 + per - 1) / per;
-  if (nbc < 1) nbc = 1;
+  int nbc = (target + per - 1) / per;
+  if (nbc > 8) nbc = (nbc + 7) / 8 * 8;
   if (nbc > nv) nbc = nv;
-  const int bchunk = (nv + nbc - 1) / nbc;
-  return (nv + bchunk - 1) / bchunk;
+  return nbc < 1 ? 1 : nbc;
 }
 
 void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pvv,
@@ -653,16 +664,15 @@ void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri
   typedef OCfg T;
   const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + T::BN - 1) / T::BN;
   const int nbc = omega_nbchunks(nv, ntri);
-  const int bchunk = (nv + nbc - 1) / nbc;
   const dim3 grid(nbc * tm * tn, 6, ntri), block(T::NT);
   if (no + 1 <= 16)
-    hipLaunchKernelGGL(k_omega<1>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, bchunk, nbc, tn);
+    hipLaunchKernelGGL(k_omega<1>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, nbc, tn);
   else if (no + 1 <= 32)
-    hipLaunchKernelGGL(k_omega<2>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, bchunk, nbc, tn);
+    hipLaunchKernelGGL(k_omega<2>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, nbc, tn);
   else if (no + 1 <= 48)
-    hipLaunchKernelGGL(k_omega<3>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, bchunk, nbc, tn);
+    hipLaunchKernelGGL(k_omega<3>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, nbc, tn);
   else
-    hipLaunchKernelGGL(k_omega<4>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, bchunk, nbc, tn);
+    hipLaunchKernelGGL(k_omega<4>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, nbc, tn);
 }
 
 void launch_reduce(const int* tri, int ntri, const double* Pvv, const double* Soo, double* Ot1,

@@ -77,3 +77,68 @@ def sample_triples(no: int, count: int, seed: int = 0) -> np.ndarray:
     count = min(count, len(allt))
     idx = np.sort(g.choice(len(allt), size=count, replace=False))
     return np.ascontiguousarray(np.array([allt[t] for t in idx], dtype=np.int32).reshape(-1, 3))
+
+
+def _torch_gen(device, *key):
+    import torch
+    h = np.random.SeedSequence([SEED_BASE, *[int(k) for k in key]]).generate_state(1, np.uint64)[0]
+    g = torch.Generator(device=device)
+    g.manual_seed(int(h) & ((1 << 63) - 1))
+    return g
+
+
+def mirror_pairs_torch(x):
+    """torch form of mirror_pairs (same element choice), on x's device."""
+    import torch
+    no, _, nv, _ = x.shape
+    i = torch.arange(no, device=x.device).view(no, 1, 1, 1)
+    j = torch.arange(no, device=x.device).view(1, no, 1, 1)
+    a = torch.arange(nv, device=x.device).view(1, 1, nv, 1)
+    b = torch.arange(nv, device=x.device).view(1, 1, 1, nv)
+    keep = (i < j) | ((i == j) & (a <= b))
+    return torch.where(keep, x, x.permute(1, 0, 3, 2)).contiguous()
+
+
+def make_inputs_device(no: int, nv: int, nchol: int, tag: int = 0, device="cuda:0") -> dict:
+    """The recipe of make_inputs drawn with torch's generator directly on `device`
+    (for large batches of molecules; values differ from make_inputs, the
+    distributions and symmetries are the same)."""
+    import torch
+    g = _torch_gen(device, 3, no, nv, nchol, tag)
+    f64 = dict(dtype=torch.float64, device=device)
+    eps_o = torch.sort(torch.rand(no, generator=g, **f64) * 1.5 - 2.0).values
+    eps_v = torch.sort(torch.rand(nv, generator=g, **f64) * 2.8 + 0.2).values
+    nmo = no + nv
+    x = torch.randn(nchol, nmo, nmo, generator=g, **f64) * 0.05
+    up = torch.triu(x)
+    L = (up + torch.triu(x, 1).transpose(1, 2)).contiguous()
+    t1 = (torch.randn(no, nv, generator=g, **f64) * 1e-3).contiguous()
+    t2 = mirror_pairs_torch(torch.randn(no, no, nv, nv, generator=g, **f64) * 1e-2)
+    return {"no": no, "nv": nv, "nchol": nchol, "eps": torch.cat([eps_o, eps_v]).contiguous(),
+            "L": L, "t1": t1, "t2": t2}
+
+
+def perturb_t2_device(t2, seed: int, scale: float = 1e-4):
+    """torch form of perturb_t2 on t2's device (a solver-iteration-like update)."""
+    import torch
+    g = _torch_gen(t2.device, 7, seed)
+    noise = torch.randn(t2.shape, generator=g, dtype=t2.dtype, device=t2.device) * scale
+    return mirror_pairs_torch(t2 + noise)
+
+
+def serving_mix(count: int = 64, seed: int = 5) -> list:
+    """(no, nv, nchol) of `count` molecules: no uniform in [5, 20], nv uniform in
+    [60, 250] (integers), Cholesky rank round(3 (no + nv))."""
+    g = np.random.default_rng([SEED_BASE, 5, int(seed)])
+    out = []
+    for _ in range(count):
+        no = int(g.integers(5, 21))
+        nv = int(g.integers(60, 251))
+        out.append((no, nv, int(round(3 * (no + nv)))))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 5) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    g = np.random.default_rng([SEED_BASE, 6, int(seed)])
+    return np.cumsum(g.exponential(1.0 / rate, size=count)) - 0.0
