@@ -47,12 +47,16 @@ struct TileCfg {
 
 // LDS position of tile element (k, x) of a stage with BK rows: row k, with the
 // low four bits of x XOR-ed by a k-dependent pattern that spreads the BK rows
-// over the 16 slots of a 128-byte group (k for BK = 16, 2k for BK = 8).  A
+// over the 16 slots of a 128-byte group (k for BK = 16, 2k for BK = 8, k mod 16
+// for BK = 32).  A
 // fragment read (16 consecutive x of one row) stays a permutation of one
 // 128-byte group; a k-fast store (16 lanes covering BK rows and 16/BK adjacent
 // x) lands on 16 different 8-byte bank pairs instead of one.
 template <int BK>
-__device__ inline int lds_swz(int k) { return (k & (BK - 1)) * (16 / BK); }
+__device__ inline int lds_swz(int k) {
+  if constexpr (BK >= 16) return k & 15;  // BK = 32: rows k and k + 16 share a pattern
+  else return (k & (BK - 1)) * (16 / BK);
+}
 template <int BK>
 __device__ inline int lds_idx(int k, int x, int ld) { return k * ld + (x ^ lds_swz<BK>(k)); }
 
@@ -61,7 +65,7 @@ __device__ inline int lds_idx(int k, int x, int ld) { return k * ld + (x ^ lds_s
 template <int X, int BK, int NT>
 struct StageMap {
   static_assert(NT % BK == 0, "BK must divide the thread count");
-  static_assert(BK == 4 || BK == 8 || BK == 16, "BK must be 4, 8 or 16");
+  static_assert(BK == 4 || BK == 8 || BK == 16 || BK == 32, "BK must be 4, 8, 16 or 32");
   static constexpr bool XF_OK = (NT % X == 0);  // x-fast mapping keeps x fixed per thread
   int x_t, k_t, dx, dk;
   __device__ StageMap(bool xfast, int tid) {
@@ -93,6 +97,42 @@ __device__ inline void load_stage(const Opnd& o, int x0, int k0, double (&r)[E],
     }
   }
 }
+
+// Global -> registers for the stages of one operand view, with the per-thread
+// part of the addressing computed once (init) and only a uniform origin per
+// stage.  Rows x >= xlim repeat row xlim - 1 (their products only reach
+// outputs that are never stored); elements with k >= klim read as 0, which
+// zeroes their products whatever the other operand holds there (finite data).
+// Per-thread byte offsets from the stage origin stay below 4 GiB for every
+// supported size (rows < 128 of stride <= nv^2, k < 32 of stride <= nv^2).
+template <int X, int BK, int E, int NT>
+struct StageLoader {
+  unsigned xo[E];  // byte offset of element e's row from the tile origin
+  int k_t, dk;     // element e lies at k = k_t + e * dk within the stage
+  __device__ void init(const Opnd& o, int x0, int tid) {
+    const StageMap<X, BK, NT> mp(o.xfast, tid);
+    k_t = mp.k_t;
+    dk = mp.dk;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = min(x0 + mp.x_t + e * mp.dx, o.xlim - 1) - x0;
+      xo[e] = (unsigned)x * (unsigned)o.sx * 8u;
+    }
+  }
+  __device__ void load(const Opnd& o, int x0, int k0, double (&r)[E]) const {
+    const char* org = (const char*)(o.p + ((int64_t)x0 * o.sx + (int64_t)k0 * o.sk));
+    const bool full = k0 + BK <= o.klim;
+    const int kmax = o.klim - 1 - k0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = k_t + e * dk;
+      const bool in = full || k <= kmax;
+      const int kc = in ? k : kmax;
+      const double v = *(const double*)(org + (xo[e] + (unsigned)kc * (unsigned)o.sk * 8u));
+      r[e] = in ? v : 0.0;
+    }
+  }
+};
 
 // Registers -> swizzled k-major LDS tile (same element mapping as load_stage).
 template <int X, int BK, int E, int NT, int LD>
@@ -160,9 +200,12 @@ __device__ inline void k_loop(int nsteps, int m0, int n0, Ops ops, d4v (&acc)[T:
   Opnd A, B;
   int k0;
   if (nsteps <= 0) return;
-  ops(0, A, B, k0);
-  load_stage<T::BM, T::BK, T::EA, T::NT>(A, m0, k0, ra, tid);
-  load_stage<T::BN, T::BK, T::EB, T::NT>(B, n0, k0, rb, tid);
+  auto fetch = [&](int s) {
+    ops(s, A, B, k0);
+    load_stage<T::BM, T::BK, T::EA, T::NT>(A, m0, k0, ra, tid);
+    load_stage<T::BN, T::BK, T::EB, T::NT>(B, n0, k0, rb, tid);
+  };
+  fetch(0);
   store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(A.xfast, ra, lds, tid);
   store_stage<T::BN, T::BK, T::EB, T::NT, T::LDB>(B.xfast, rb, lds + T::BK * T::LDA, tid);
   __syncthreads();
@@ -170,11 +213,7 @@ __device__ inline void k_loop(int nsteps, int m0, int n0, Ops ops, d4v (&acc)[T:
     double* cur = lds + (s & 1) * T::STAGE;
     double* nxt = lds + ((s + 1) & 1) * T::STAGE;
     const bool more = (s + 1 < nsteps);
-    if (more) {
-      ops(s + 1, A, B, k0);
-      load_stage<T::BM, T::BK, T::EA, T::NT>(A, m0, k0, ra, tid);
-      load_stage<T::BN, T::BK, T::EB, T::NT>(B, n0, k0, rb, tid);
-    }
+    if (more) fetch(s + 1);
     mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
     if (more) {
       store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(A.xfast, ra, nxt, tid);

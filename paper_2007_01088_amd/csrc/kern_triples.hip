@@ -409,16 +409,35 @@ void launch_tau_export(const double* eps, const int* tri, const double* cubes, d
 //                                (summed over the chunk's b in registers)
 // Partial results: Pvv[z][pi][chunk][a][n] (n < nv: d columns, n == nv: Omega1),
 // SooT[z][pi][l][b][a].
-typedef TileCfg<4, 2, 2, 4, 16> OCfg;  // 128 x 128 vv tile, 8 wavefronts
+// 128 x 128 vv tile, 16 wavefronts of 32 x 32: at most 128 VGPRs, so four
+// wavefronts share each SIMD.  32 k per LDS stage where two stages fit the
+// LDS (oo rows up to 48), else 16.
+template <int BK>
+using OCfgK = TileCfg<4, 4, 2, 2, BK>;
+typedef OCfgK<16> OCfg;  // tile geometry (independent of BK)
+template <int FNO>
+struct OmegaBK {
+  static constexpr int BK = FNO <= 3 ? 32 : 16;
+};
+
+// The oo product (rows l, columns a) is split over the wavefronts in 16 x 16
+// blocks: wavefront (wm, wn) takes column block am = 2 wm + (wn & 1) -- one of
+// the two a blocks whose A fragments it already holds for the vv product --
+// and row blocks f = (wn >> 1) + 2 j < FNO.
+template <int FNO>
+struct OoSplit {
+  static constexpr int NF = (FNO + 1) / 2;  // row blocks per wavefront (upper bound)
+};
 
 template <int FNO>
 __global__ __launch_bounds__(OCfg::NT) void k_omega(
     const double* __restrict__ cubes, const double* __restrict__ Gv, const double* __restrict__ Jo,
     const double* __restrict__ Hs, const int* __restrict__ tri, double* __restrict__ Pvv,
     double* __restrict__ Soo, int no, int nv, int nbchunks, int tiles_n) {
-  typedef OCfg T;
+  typedef OCfgK<OmegaBK<FNO>::BK> T;
   constexpr int BO = 16 * FNO;  // oo rows per tile (no of them used, plus the Omega1 row)
   constexpr int EO = (BO * T::BK + T::NT - 1) / T::NT;
+  constexpr int NF = OoSplit<FNO>::NF;
   constexpr int STAGE = T::BK * (T::LDA + T::LDB + BO);
   __shared__ double lds[2 * STAGE];
   const int pi = blockIdx.y;
@@ -461,39 +480,46 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
+  const int am = wm * T::FM + (wn & 1);  // this wavefront's oo column block
+  const int f0 = wn >> 1;                // and its first oo row block
   d4v acc[T::FM][T::FN];
-  d4v aco[FNO][T::FM];  // rows l = f*16 + lane/16 + 4r, columns a = m0 + (wm*FM + fm)*16 + lane%16
+  d4v aco[NF];  // oo rows l = (f0 + 2 t) * 16 + lane/16 + 4 r, columns a = m0 + am * 16 + lane%16
   zero_acc<T>(acc);
 #pragma unroll
-  for (int f = 0; f < FNO; ++f)
-#pragma unroll
-    for (int fm = 0; fm < T::FM; ++fm) aco[f][fm] = d4v{0.0, 0.0, 0.0, 0.0};
-  double om1[T::FM];  // Omega1 partial for this lane's a columns (held by the lanes of row no)
-#pragma unroll
-  for (int fm = 0; fm < T::FM; ++fm) om1[fm] = 0.0;
+  for (int t = 0; t < NF; ++t) aco[t] = d4v{0.0, 0.0, 0.0, 0.0};
+  double om1 = 0.0;  // Omega1 partial of column a (lanes holding row l == no)
   double ra[T::EA], rb[T::EB], ro[EO];
-  // oo rows: thread -> (c = k_t, l = x_t + e * NT/BK), the same mapping store_stage uses
+  // vv operands: A = U_pi[a, b, c] (rows a, k = c) at fixed b, B = Gv[r][b][d][c] (rows d)
+  StageLoader<T::BM, T::BK, T::EA, T::NT> la;
+  StageLoader<T::BN, T::BK, T::EB, T::NT> lb;
+  la.init(make_opnd(ub, sm, sk, nv, nv, afast), m0, tid);
+  lb.init(make_opnd(Gr, nv, 1, nv, nv, false), n0, tid);
+  // oo rows: thread -> (c = k_t, l = x_t + e * NT/BK), the same mapping store_stage uses;
+  // rows l < no come from Hs, row no from Jo (at the stage's b), rows beyond read as 0
   const int ok_t = tid % T::BK, ox_t = tid / T::BK;
   constexpr int ODX = T::NT / T::BK;
 
-  auto load = [&](int s) {
-    const int b = bb0 + s / cs, c0 = (s % cs) * T::BK;
-    const Opnd A = make_opnd(ub + (int64_t)b * sbb, sm, sk, nv, nv, afast);
-    load_stage<T::BM, T::BK, T::EA, T::NT>(A, m0, c0, ra, tid);
-    const Opnd B = make_opnd(Gr + (int64_t)b * nv2, nv, 1, nv, nv, false);
-    load_stage<T::BN, T::BK, T::EB, T::NT>(B, n0, c0, rb, tid);
+  // position of the next stage to load (b, c0) and of the stage being computed
+  int ld_b = bb0, ld_c0 = 0;
+  auto load = [&]() {
+    const int b = ld_b, c0 = ld_c0;
+    la.load(make_opnd(ub + (int64_t)b * sbb, sm, sk, nv, nv, afast), m0, c0, ra);
+    lb.load(make_opnd(Gr + (int64_t)b * nv2, nv, 1, nv, nv, false), n0, c0, rb);
     if (do_oo) {
       const int c = c0 + ok_t;
+      const int cc = min(c, nv - 1);
+      const double* jrow = Jqr + (int64_t)b * nvl;
 #pragma unroll
       for (int e = 0; e < EO; ++e) {
         const int l = ox_t + e * ODX;
-        const double* src = (l < no) ? Hqr + (int64_t)l * nvl : Jqr + (int64_t)b * nvl;
+        const double* row = (l < no) ? Hqr + (int64_t)l * nvl : jrow;
         const bool in = (e * T::NT + tid) < BO * T::BK && c < nv && l <= no;
-        double v = 0.0;
-        if (in) v = src[c];
-        ro[e] = v;
+        const double v = row[cc];
+        ro[e] = in ? v : 0.0;
       }
     }
+    ld_c0 += T::BK;
+    if (ld_c0 >= nv) { ld_c0 = 0; ++ld_b; }
   };
   auto store = [&](double* st) {
     store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(afast, ra, st, tid);
@@ -502,48 +528,61 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
   };
 
   double* soo = Soo + ((int64_t)z * 6 + pi) * no * nv2;
-  load(0);
+  load();
   store(lds);
   __syncthreads();
+  int cp_b = bb0, cp_cs = 0;  // stage being computed: b and its c step
   for (int s = 0; s < nsteps; ++s) {
     double* cur = lds + (s & 1) * STAGE;
     double* nxt = lds + ((s + 1) & 1) * STAGE;
     const bool more = (s + 1 < nsteps);
-    if (more) load(s + 1);
-    mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
-    if (do_oo && wn == 0) {  // the oo product: one wavefront per row block of a
-      const double* so = cur + T::BK * (T::LDA + T::LDB);
+    if (more) load();
+    const double* so = cur + T::BK * (T::LDA + T::LDB);
 #pragma unroll
-      for (int kk = 0; kk < T::BK / 4; ++kk) {
-        const int kr = kk * 4 + (lane >> 4);
-        const int sw = (lane & 15) ^ lds_swz<T::BK>(kr);
-        double a[T::FM], bo[FNO];
+    for (int kk = 0; kk < T::BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      const int sw = (lane & 15) ^ lds_swz<T::BK>(kr);
+      double a[T::FM], bf[T::FN];
 #pragma unroll
-        for (int fm = 0; fm < T::FM; ++fm) a[fm] = cur[kr * T::LDA + (wm * T::FM + fm) * 16 + sw];
+      for (int fm = 0; fm < T::FM; ++fm) a[fm] = cur[kr * T::LDA + (wm * T::FM + fm) * 16 + sw];
 #pragma unroll
-        for (int f = 0; f < FNO; ++f) bo[f] = so[kr * BO + f * 16 + sw];
+      for (int fn = 0; fn < T::FN; ++fn)
+        bf[fn] = cur[T::BK * T::LDA + kr * T::LDB + (wn * T::FN + fn) * 16 + sw];
 #pragma unroll
-        for (int f = 0; f < FNO; ++f)
+      for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
-          for (int fm = 0; fm < T::FM; ++fm)
-            aco[f][fm] = __builtin_amdgcn_mfma_f64_16x16x4f64(bo[f], a[fm], aco[f][fm], 0, 0, 0);
+        for (int fn = 0; fn < T::FN; ++fn)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fm], bf[fn], acc[fm][fn], 0, 0, 0);
+      if (do_oo) {  // uniform per workgroup
+#pragma unroll
+        for (int t = 0; t < NF; ++t) {
+          const int f = f0 + 2 * t;
+          if (f < FNO) {
+            const double bo = so[kr * BO + f * 16 + sw];
+            aco[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(bo, (wn & 1) ? a[1] : a[0], aco[t], 0, 0, 0);
+          }
+        }
       }
-      if ((s % cs) == cs - 1) {  // b complete: SooT[l][b][a] = aco(l, a); row no -> Omega1
-        const int b = bb0 + s / cs;
+    }
+    if (++cp_cs == cs) {  // b complete
+      if (do_oo) {  // SooT[l][b][a] = aco(l, a); row no -> Omega1
+        const int a = m0 + am * 16 + (lane & 15);
 #pragma unroll
-        for (int f = 0; f < FNO; ++f)
-#pragma unroll
-          for (int fm = 0; fm < T::FM; ++fm) {
+        for (int t = 0; t < NF; ++t) {
+          const int f = f0 + 2 * t;
+          if (f < FNO) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
               const int l = f * 16 + (lane >> 4) + 4 * rr;
-              const int a = m0 + (wm * T::FM + fm) * 16 + (lane & 15);
-              if (a < nv && l < no) soo[((int64_t)l * nvl + b) * nvl + a] = aco[f][fm][rr];
-              if (l == no) om1[fm] += aco[f][fm][rr];
+              if (a < nv && l < no) soo[((int64_t)l * nvl + cp_b) * nvl + a] = aco[t][rr];
+              if (l == no) om1 += aco[t][rr];
             }
-            aco[f][fm] = d4v{0.0, 0.0, 0.0, 0.0};
           }
+          aco[t] = d4v{0.0, 0.0, 0.0, 0.0};
+        }
       }
+      cp_cs = 0;
+      ++cp_b;
     }
     if (more) store(nxt);
     __syncthreads();
@@ -560,17 +599,16 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
         const int n = n0 + acc_col<T>(wn, fn, lane);
         if (a < nv && n < nv) pvv[(int64_t)a * NV1 + n] = acc[fm][fn][rr];
       }
-  if (do_oo && wn == 0) {  // Omega1 column, held by the lanes whose oo row is l == no
+  if (do_oo) {  // Omega1 column, held by the lanes whose oo row is l == no
+    const int a = m0 + am * 16 + (lane & 15);
+    bool mine = false;
 #pragma unroll
-    for (int fm = 0; fm < T::FM; ++fm) {
-      const int a = m0 + (wm * T::FM + fm) * 16 + (lane & 15);
-      bool mine = false;
+    for (int t = 0; t < NF; ++t) {
+      const int f = f0 + 2 * t;
 #pragma unroll
-      for (int f = 0; f < FNO; ++f)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) mine |= (f * 16 + (lane >> 4) + 4 * rr == no);
-      if (mine && a < nv) pvv[(int64_t)a * NV1 + nv] = om1[fm];
+      for (int rr = 0; rr < 4; ++rr) mine |= (f < FNO) && (f * 16 + (lane >> 4) + 4 * rr == no);
     }
+    if (mine && a < nv) pvv[(int64_t)a * NV1 + nv] = om1;
   }
 }
 

@@ -29,6 +29,7 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));  // a 16-byte chunk (kept in registers)
 
 __host__ __device__ inline int kpad(int k) { return (k + 31) / 32 * 32; }
 
@@ -150,10 +151,11 @@ constexpr int LNT = 64 * LWM * LWN;
 constexpr int LBM = 16 * LWM * LFM, LBN = 16 * LWN * LFN;  // 128 x 128
 
 // Engine traits.  An LDS tile is row-major [x][k] with rows of BK elements plus
-// 16 bytes of padding (rows of 80 bytes: the 16 rows read by one fragment load
-// land on distinct banks).  One 16-byte chunk per thread per piece per operand.
+// 16 bytes of padding (rows of 80 or 144 bytes: the 16 rows read by one
+// fragment load spread over the banks).  Tiles load as 16-byte chunks, CH per
+// thread per piece per operand.
 struct EngF32 {
-  static constexpr int BK = 16, P = 1, NPROD = 1, ESZ = 4;
+  static constexpr int BK = 32, P = 1, NPROD = 1, ESZ = 4;
   static constexpr int ROWB = BK * ESZ + 16;  // bytes per LDS row
 };
 template <int P_>
@@ -211,59 +213,62 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
   const int64_t ps_t2 = o * o * v * dk, ps_t2N = o * v * v * lk, ps_Gw = o * v * v * dk,
                 ps_Go = o * o * v * lk;
   // segments: term 1 vv, term 1 oo, term 2 vv, term 2 oo (rows m for A, n for B)
-  LpSeg seg[4];
-  seg[0] = {t2L + ((p1 * o + q1) * v) * dk * ESZ, GwTL + ((r1 * v + y) * v) * dk * ESZ,
+  const LpSeg seg0 = {t2L + ((p1 * o + q1) * v) * dk * ESZ, GwTL + ((r1 * v + y) * v) * dk * ESZ,
             dk * ESZ, dk * ESZ, ps_t2 * ESZ, ps_Gw * ESZ, (int)(dk / BK)};
-  seg[1] = {t2NL + ((p1 * v + y) * v) * lk * ESZ, GoTL + ((q1 * o + r1) * v) * lk * ESZ,
+  const LpSeg seg1 = {t2NL + ((p1 * v + y) * v) * lk * ESZ, GoTL + ((q1 * o + r1) * v) * lk * ESZ,
             lk * ESZ, lk * ESZ, ps_t2N * ESZ, ps_Go * ESZ, (int)(lk / BK)};
-  seg[2] = {GwTL + ((r2 * v + y) * v) * dk * ESZ, t2L + ((p2 * o + q2) * v) * dk * ESZ,
+  const LpSeg seg2 = {GwTL + ((r2 * v + y) * v) * dk * ESZ, t2L + ((p2 * o + q2) * v) * dk * ESZ,
             dk * ESZ, dk * ESZ, ps_Gw * ESZ, ps_t2 * ESZ, (int)(dk / BK)};
-  seg[3] = {GoTL + ((q2 * o + r2) * v) * lk * ESZ, t2NL + ((p2 * v + y) * v) * lk * ESZ,
+  const LpSeg seg3 = {GoTL + ((q2 * o + r2) * v) * lk * ESZ, t2NL + ((p2 * v + y) * v) * lk * ESZ,
             lk * ESZ, lk * ESZ, ps_Go * ESZ, ps_t2N * ESZ, (int)(lk / BK)};
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % LWM, wn = wave / LWM;
-  // this thread's 16-byte chunk of a tile: row cr, chunk cc within the row
-  constexpr int CPR = BK * ESZ / 16;  // chunks per row (4)
+  // this thread's 16-byte chunks of a tile: rows cr + c * RPP, chunk cc within the row
+  constexpr int CPR = BK * ESZ / 16;       // chunks per row
+  constexpr int RPP = LNT / CPR;           // rows per pass of the workgroup
+  constexpr int CH = LBM / RPP;            // chunks per thread
   const int cr = tid / CPR, cc = tid % CPR;
-  const bool rowA_ok = (m0 + cr) < nv, rowB_ok = (n0 + cr) < nv;
 
-  double out[LFM][LFN][4];
-#pragma unroll
-  for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-    for (int fn = 0; fn < LFN; ++fn)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) out[fm][fn][r] = 0.0;
-
-  for (int term = 0; term < (two ? 2 : 1); ++term) {
-    f4v acc[LFM][LFN];
+  u4v ra[P][CH], rb[P][CH];  // one stage of both operands in flight
+  // one term: acc[m][n] = sum over K of segment sa (K = nv) then sb (K = no)
+  auto run_term = [&](const LpSeg& sa, const LpSeg& sb, f4v (&acc)[LFM][LFN]) __attribute__((always_inline)) {
 #pragma unroll
     for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < LFN; ++fn) acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
-    const LpSeg& s0 = seg[2 * term];
-    const LpSeg& s1 = seg[2 * term + 1];
-    const int nsteps = s0.ksteps + s1.ksteps;
-    uint4 ra[P], rb[P];
-    auto load = [&](int s) {
-      const LpSeg& g = (s < s0.ksteps) ? s0 : s1;
-      const int ks = (s < s0.ksteps) ? s : s - s0.ksteps;
+    const int nsteps = sa.ksteps + sb.ksteps;
+    auto load = [&](int s) __attribute__((always_inline)) {
+      const bool first = s < sa.ksteps;
+      const char* ga = first ? sa.a : sb.a;
+      const char* gb = first ? sa.b : sb.b;
+      const int64_t ars = first ? sa.a_rs : sb.a_rs, brs = first ? sa.b_rs : sb.b_rs;
+      const int64_t aps = first ? sa.a_ps : sb.a_ps, bps = first ? sa.b_ps : sb.b_ps;
+      const int ks = first ? s : s - sa.ksteps;
       const int64_t koff = (int64_t)ks * BK * ESZ + cc * 16;
-      const char* pa = g.a + (int64_t)(m0 + cr) * g.a_rs + koff;
-      const char* pb = g.b + (int64_t)(n0 + cr) * g.b_rs + koff;
 #pragma unroll
-      for (int pc = 0; pc < P; ++pc) {
-        ra[pc] = rowA_ok ? *(const uint4*)(pa + pc * g.a_ps) : make_uint4(0, 0, 0, 0);
-        rb[pc] = rowB_ok ? *(const uint4*)(pb + pc * g.b_ps) : make_uint4(0, 0, 0, 0);
+      for (int c = 0; c < CH; ++c) {
+        const int row = cr + c * RPP;
+        // rows past nv repeat row nv - 1 (their outputs are never stored)
+        const char* pa = ga + (int64_t)min(m0 + row, nv - 1) * ars + koff;
+        const char* pb = gb + (int64_t)min(n0 + row, nv - 1) * brs + koff;
+#pragma unroll
+        for (int pc = 0; pc < P; ++pc) {
+          ra[pc][c] = *(const u4v*)(pa + pc * aps);
+          rb[pc][c] = *(const u4v*)(pb + pc * bps);
+        }
       }
     };
-    auto store = [&](char* st) {
+    auto store = [&](char* st) __attribute__((always_inline)) {
 #pragma unroll
-      for (int pc = 0; pc < P; ++pc) {
-        *(uint4*)(st + pc * TILEB + cr * ROWB + cc * 16) = ra[pc];
-        *(uint4*)(st + (P + pc) * TILEB + cr * ROWB + cc * 16) = rb[pc];
+      for (int c = 0; c < CH; ++c) {
+        const int row = cr + c * RPP;
+#pragma unroll
+        for (int pc = 0; pc < P; ++pc) {
+          *(u4v*)(st + pc * TILEB + row * ROWB + cc * 16) = ra[pc][c];
+          *(u4v*)(st + (P + pc) * TILEB + row * ROWB + cc * 16) = rb[pc][c];
+        }
       }
     };
     load(0);
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
       const bool more = s + 1 < nsteps;
       if (more) load(s + 1);
       if constexpr (P == 1) {
-        // FP32: four k=4 MFMA steps; lane supplies A[m = l%16][k = l/16], B[k = l/16][n = l%16]
+        // FP32: k=4 MFMA steps; lane supplies A[m = l%16][k = l/16], B[k = l/16][n = l%16]
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
           const int kc = kk * 4 + (lane >> 4);
@@ -319,13 +324,19 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
       if (more) store(nxt);
       __syncthreads();
     }
-    // FP32 term -> FP64 plane sum
+  };
+
+  // term 1 (and term 2 when the plane has two), each accumulated in FP32; the
+  // plane value is their FP64 sum (exact FP32 values, one FP64 rounding)
+  f4v acc1[LFM][LFN], acc2[LFM][LFN];
+  run_term(seg0, seg1, acc1);
+  if (two) {
+    run_term(seg2, seg3, acc2);
+  } else {
 #pragma unroll
     for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
-      for (int fn = 0; fn < LFN; ++fn)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) out[fm][fn][r] += (double)acc[fm][fn][r];
+      for (int fn = 0; fn < LFN; ++fn) acc2[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
   }
 
   // the FP32/BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
@@ -339,7 +350,7 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + (wm * LFM + fm) * 16 + 4 * (lane >> 4) + r;
         const int n = n0 + (wn * LFN + fn) * 16 + (lane & 15);
-        if (m < nv && n < nv) dst[(int64_t)m * nv + n] = out[fm][fn][r];
+        if (m < nv && n < nv) dst[(int64_t)m * nv + n] = (double)acc1[fm][fn][r] + (double)acc2[fm][fn][r];
       }
 }
 
