@@ -1,0 +1,129 @@
+"""Summaries of rocprofv3 output for the kernels of libcc3 (host-side tooling).
+
+    python -m paper_2007_01088_amd.profiling stats RUN_results.db [--out FILE.md] [--cmd "..."]
+        per-kernel launches, average and total duration from a --kernel-trace database
+    python -m paper_2007_01088_amd.profiling traffic --fetch F.csv --write W.csv --kernel REGEX
+        [--calib-bytes N] [--source-sha SHA] [--out FILE.json] [--cmd "..."]
+        HBM bytes per dispatch from two --pmc runs (FETCH_SIZE, WRITE_SIZE, in KiB),
+        scaled by what the same counters read for the device-to-device copy of a
+        known size (the largest __amd_rocclr_copyBuffer dispatch) when N is given
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import json
+import re
+import sqlite3
+import sys
+
+
+def _short(name: str) -> str:
+    return re.sub(r"\(.*", "", name).replace("void ", "").strip()
+
+
+def kernel_stats(db_path: str) -> list[dict]:
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, duration from kernels").fetchall()
+    con.close()
+    agg = collections.OrderedDict()
+    for name, dur in rows:
+        k = _short(name)
+        a = agg.setdefault(k, [0, 0.0])
+        a[0] += 1
+        a[1] += dur
+    total = sum(a[1] for a in agg.values()) or 1.0
+    out = [{"kernel": k, "launches": n, "avg_us": t / n / 1e3, "total_ms": t / 1e6,
+            "share": t / total} for k, (n, t) in agg.items()]
+    out.sort(key=lambda r: -r["total_ms"])
+    return out
+
+
+def stats_markdown(rows: list[dict], cmd: str | None) -> str:
+    lines = []
+    if cmd:
+        lines += ["Command:", "", "    " + cmd, ""]
+    lines += ["| kernel | launches | avg (us) | total (ms) | share |", "|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{r['kernel']}` | {r['launches']} | {r['avg_us']:.1f} | "
+                     f"{r['total_ms']:.2f} | {100 * r['share']:.1f}% |")
+    return "\n".join(lines) + "\n"
+
+
+def _counter(csv_path: str, counter: str) -> dict:
+    """{kernel short name: [per-dispatch values]} for one counter."""
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            per[_short(r["Kernel_Name"])][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    return {k: list(v.values()) for k, v in per.items()}
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel_re: str, calib_bytes: float | None) -> dict:
+    fetch = _counter(fetch_csv, "FETCH_SIZE")
+    write = _counter(write_csv, "WRITE_SIZE")
+    pat = re.compile(kernel_re)
+    names = [k for k in fetch if pat.search(k)]
+    if not names:
+        raise SystemExit(f"no kernel matching {kernel_re!r} in {fetch_csv}")
+    fvals = [v for k in names for v in fetch[k]]
+    wvals = [v for k in names for v in write.get(k, [])]
+    f_kib = sum(fvals) / len(fvals)
+    w_kib = sum(wvals) / len(wvals) if wvals else 0.0
+    scale_f = scale_w = 1.0
+    calib = None
+    if calib_bytes:
+        cf = max(fetch.get("__amd_rocclr_copyBuffer", [0.0]))
+        cw = max(write.get("__amd_rocclr_copyBuffer", [0.0]))
+        if cf > 0 and cw > 0:
+            scale_f = calib_bytes / (cf * 1024.0)
+            scale_w = calib_bytes / (cw * 1024.0)
+            calib = {"copy_bytes": calib_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+                     "fetch_scale": scale_f, "write_scale": scale_w}
+    fb = f_kib * 1024.0 * scale_f
+    wb = w_kib * 1024.0 * scale_w
+    return {"kernels": names, "dispatches": len(fvals), "fetch_bytes_per_launch": fb,
+            "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb, "calibration": calib}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(prog="python -m paper_2007_01088_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--out")
+    s.add_argument("--cmd")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--calib-bytes", type=float)
+    t.add_argument("--source-sha")
+    t.add_argument("--out")
+    t.add_argument("--cmd")
+    args = ap.parse_args(argv)
+    if args.cmd_name == "stats":
+        text = stats_markdown(kernel_stats(args.db), args.cmd)
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(text)
+        sys.stdout.write(text)
+        return 0
+    res = traffic(args.fetch, args.write, args.kernel, args.calib_bytes)
+    if args.source_sha:
+        res["source_sha"] = args.source_sha
+    if args.cmd:
+        res["commands"] = args.cmd
+    text = json.dumps(res, indent=1)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    print(text)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
