@@ -27,6 +27,17 @@ __device__ inline Opnd make_opnd(const double* p, int64_t sx, int64_t sk, int xl
   return o;
 }
 
+// Raw buffer access: a resource for a uniform base pointer (range 2 GiB, no
+// stride) and 64-bit loads at 32-bit per-lane byte offsets.
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+typedef unsigned u2v_ __attribute__((ext_vector_type(2)));
+__device__ inline BufRsrc buf_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+__device__ inline double buf_load_f64(BufRsrc r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
 // Tile geometry: WM x WN wavefronts, each owning FM x FN blocks of 16x16
 // outputs; BK (a multiple of 4) k values per LDS stage.
 template <int WM_, int WN_, int FM_, int FN_, int BK_ = 8>

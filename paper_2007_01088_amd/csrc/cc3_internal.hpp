@@ -8,8 +8,8 @@
 namespace cc3 {
 
 // Device-resident, internally laid out integral blocks (all float64):
-//   Gw[r][y][d][z] = g_{ydzr}         (vv|vo), the W contraction operand
-//   Go[q][r][l][z] = g_{lqzr}         (oo|vo)
+//   Gw[r][y][z][d] = g_{ydzr}         (vv|vo), the W contraction operand (d fastest)
+//   Go[q][r][z][l] = g_{lqzr}         (oo|vo) (l fastest)
 //   Gv[r][b][d][c] = g_{dbrc}         (vv|ov), the Omega contraction operand
 //   Jo[q][r][b][c] = g_{qbrc}         (ov|ov)
 //   Hs[q][r][l][c] = delta_{lq} F_rc - g_{qlrc}   (oo|ov) and the Fock ov block

@@ -169,7 +169,7 @@ void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no,
 // Integral-block build: C[m][n] = sum_J A(m, J) B(J, n) on FP64 MFMA, batched
 // over blockIdx.z, with an output map per block kind.
 // ---------------------------------------------------------------------------
-enum BuildKind { BUILD_PLAIN = 0, BUILD_JO = 1, BUILD_HS = 2, BUILD_GO = 3 };
+enum BuildKind { BUILD_PLAIN = 0, BUILD_JO = 1, BUILD_HS = 2, BUILD_GO = 3, BUILD_GW = 4 };
 
 typedef TileCfg<2, 2, 4, 4, 16> BuildCfg;
 
@@ -215,9 +215,12 @@ __global__ __launch_bounds__(BuildCfg::NT, 2) void k_build(
         } else if (kind == BUILD_HS) {  // m = q*no + l, n = r*nv + c -> Hs[q][r][l][c]
           const int q = m / no, l = m % no, rr = n / nv, c = n % nv;
           Cz[(((int64_t)q * no + rr) * no + l) * nv + c] = (l == q ? F[(int64_t)rr * nv + c] : 0.0) - v;
-        } else {  // BUILD_GO: m = q*no + l, n = r*nv + z -> Go[q][r][l][z]
+        } else if (kind == BUILD_GO) {  // m = q*no + l, n = r*nv + z -> Go[q][r][z][l]
           const int q = m / no, l = m % no, rr = n / nv, c = n % nv;
-          Cz[(((int64_t)q * no + rr) * no + l) * nv + c] = v;
+          Cz[(((int64_t)q * no + rr) * nv + c) * no + l] = v;
+        } else {  // BUILD_GW: m = z, n = y*nv + d -> Gw[r][y][z][d] (batch r)
+          const int y = n / nv, d = n % nv;
+          Cz[((int64_t)y * nv + m) * nv + d] = v;
         }
       }
 }
@@ -235,8 +238,8 @@ static void build(const double* A, int64_t a_sm, int64_t a_sk, int64_t a_bs, con
 void launch_build_blocks(const CholeskyScratch& cs, const Blocks& bl, int no, int nv, int nJ,
                          hipStream_t st) {
   const int64_t nv2 = (int64_t)nv * nv, nv3 = nv2 * nv, onv = (int64_t)no * nv;
-  // Gw[r][(y,d)][z] = sum_J Lvv[J][(y,d)] LvoT[J][r][z]
-  build(cs.Lvv, 1, nv2, 0, cs.LvoT, onv, 1, nv, (int)nv2, nv, nJ, bl.Gw, nv3, no, BUILD_PLAIN, no,
+  // Gw[r][y][z][d] = sum_J LvoT[J][r][z] Lvv[J][(y,d)]   (rows z, columns (y,d), batch r)
+  build(cs.LvoT, 1, onv, nv, cs.Lvv, nv2, 1, 0, nv, (int)nv2, nJ, bl.Gw, nv3, no, BUILD_GW, no,
         nv, nullptr, st);
   // Gv[r][(b,d)][c] = sum_J LvvT[J][(b,d)] Lov[J][r][c]
   build(cs.LvvT, 1, nv2, 0, cs.Lov, onv, 1, nv, (int)nv2, nv, nJ, bl.Gv, nv3, no, BUILD_PLAIN, no,
@@ -247,7 +250,7 @@ void launch_build_blocks(const CholeskyScratch& cs, const Blocks& bl, int no, in
   // Hs[q][r][l][c] = delta_lq F[r][c] - sum_J Loo[J][q][l] Lov[J][r][c]
   build(cs.Loo, 1, (int64_t)no * no, 0, cs.Lov, onv, 1, 0, no * no, (int)onv, nJ, bl.Hs, 0, 1,
         BUILD_HS, no, nv, bl.F, st);
-  // Go[q][r][l][z] = sum_J LooT[J][q][l] LvoT[J][r][z]   (LooT[J][q][l] = Lt_lq)
+  // Go[q][r][z][l] = sum_J LooT[J][q][l] LvoT[J][r][z]   (LooT[J][q][l] = Lt_lq)
   build(cs.LooT, 1, (int64_t)no * no, 0, cs.LvoT, onv, 1, 0, no * no, (int)onv, nJ, bl.Go, 0, 1,
         BUILD_GO, no, nv, nullptr, st);
 }
@@ -263,8 +266,8 @@ __global__ void k_relayout_vv(const double* __restrict__ g_vvvo, const double* _
   const int r = blockIdx.y;
   if (e >= nv3) return;
   const int y = (int)(e / ((int64_t)nv * nv)), d = (int)((e / nv) % nv), z = (int)(e % nv);
-  // Gw[r][y][d][z] = g_vvvo[y][d][z][r]
-  Gw[(int64_t)r * nv3 + e] = g_vvvo[(((int64_t)y * nv + d) * nv + z) * no + r];
+  // Gw[r][y][u][w] = g_vvvo[y][w][u][r]  (u = d, w = z: the contracted index w fastest)
+  Gw[(int64_t)r * nv3 + e] = g_vvvo[(((int64_t)y * nv + z) * nv + d) * no + r];
   // Gv[r][b=y][d][c=z] = g_vvov[d][b][r][c]
   Gv[(int64_t)r * nv3 + e] = g_vvov[(((int64_t)d * nv + y) * no + r) * nv + z];
 }
@@ -280,8 +283,8 @@ __global__ void k_relayout_small(const double* __restrict__ g_oovo, const double
   }
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < no * nv; e += gridDim.x * blockDim.x) {
     const int l = e / nv, c = e % nv;
-    // Go[q][r][l][z] = g_oovo[l][q][z][r]
-    Go[(((int64_t)q * no + r) * no + l) * nv + c] = g_oovo[(((int64_t)l * no + q) * nv + c) * no + r];
+    // Go[q][r][z][l] = g_oovo[l][q][z][r]
+    Go[(((int64_t)q * no + r) * nv + c) * no + l] = g_oovo[(((int64_t)l * no + q) * nv + c) * no + r];
     // Hs[q][r][l][c] = delta_lq F[r][c] - g_ooov[q][l][r][c]
     Hs[(((int64_t)q * no + r) * no + l) * nv + c] =
         (l == q ? F_ov[(int64_t)r * nv + c] : 0.0) - g_ooov[(((int64_t)q * no + l) * no + r) * nv + c];

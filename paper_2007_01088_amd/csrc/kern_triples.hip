@@ -98,45 +98,85 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
   const int nvs = (nv + T::BK - 1) / T::BK, nos = (no + T::BK - 1) / T::BK;
   const int nsteps = two ? 2 * (nvs + nos) : (nvs + nos);
 
-  // term 1: Acc[m][n] += sum_d t2[p1][q1][m][d] Gw[r1][y][d][n] + sum_l t2N[p1][y][m][l] Go[q1][r1][l][n]
-  // term 2: Acc[m][n] += sum_d Gw[r2][y][d][m] t2[p2][q2][n][d] + sum_l Go[q2][r2][l][m] t2N[p2][y][n][l]
-  // with t2N[p][y][x][l] = -t2[p][l][x][y] (contiguous in l).
-  const double* a0 = t2 + ((int64_t)p1 * no + q1) * nv2;
-  const double* b0 = Gw + ((int64_t)r1 * nv + y) * nv2;
-  const double* a1 = t2N + ((int64_t)p1 * nv + y) * nv * no;
-  const double* b1 = Go + ((int64_t)q1 * no + r1) * no * nv;
-  const double* a2 = Gw + ((int64_t)r2 * nv + y) * nv2;
-  const double* b2 = t2 + ((int64_t)p2 * no + q2) * nv2;
-  const double* a3 = Go + ((int64_t)q2 * no + r2) * no * nv;
-  const double* b3 = t2N + ((int64_t)p2 * nv + y) * nv * no;
-
-  auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
-    int seg = 0, ls = s;
-    if (ls >= nvs) { ls -= nvs; seg = 1;
-      if (ls >= nos) { ls -= nos; seg = 2;
-        if (ls >= nvs) { ls -= nvs; seg = 3; } } }
-    k0 = ls * T::BK;
-    if (seg == 0) {
-      A = make_opnd(a0, nv, 1, nv, nv, false);
-      B = make_opnd(b0, 1, nv, nv, nv, true);
-    } else if (seg == 1) {
-      A = make_opnd(a1, no, 1, nv, no, false);
-      B = make_opnd(b1, 1, nv, nv, no, true);
-    } else if (seg == 2) {
-      A = make_opnd(a2, 1, nv, nv, nv, true);
-      B = make_opnd(b2, nv, 1, nv, nv, false);
-    } else {
-      A = make_opnd(a3, 1, nv, nv, no, true);
-      B = make_opnd(b3, no, 1, nv, no, false);
+  // Four K segments, each a product of two row-major (row, k) operands with k contiguous:
+  //   term 1: Acc[m][n] += sum_d t2[p1][q1][m][d] Gw[r1][y][n][d]       (K = nv)
+  //                      + sum_l t2N[p1][y][m][l] Go[q1][r1][n][l]      (K = no)
+  //   term 2: Acc[m][n] += sum_d Gw[r2][y][m][d] t2[p2][q2][n][d]       (K = nv)
+  //                      + sum_l Go[q2][r2][m][l] t2N[p2][y][n][l]      (K = no)
+  // with t2N[p][y][x][l] = -t2[p][l][x][y].  The row stride of a segment is its K.
+  // Tile origins (row m0 / n0, k = 0) of the eight operands, as byte pointers:
+  const char* A0 = (const char*)(t2 + ((int64_t)p1 * no + q1) * nv2 + (int64_t)m0 * nv);
+  const char* B0 = (const char*)(Gw + ((int64_t)r1 * nv + y) * nv2 + (int64_t)n0 * nv);
+  const char* A1 = (const char*)(t2N + ((int64_t)p1 * nv + y) * nv * no + (int64_t)m0 * no);
+  const char* B1 = (const char*)(Go + ((int64_t)q1 * no + r1) * nv * no + (int64_t)n0 * no);
+  const char* A2 = (const char*)(Gw + ((int64_t)r2 * nv + y) * nv2 + (int64_t)m0 * nv);
+  const char* B2 = (const char*)(t2 + ((int64_t)p2 * no + q2) * nv2 + (int64_t)n0 * nv);
+  const char* A3 = (const char*)(Go + ((int64_t)q2 * no + r2) * nv * no + (int64_t)m0 * no);
+  const char* B3 = (const char*)(t2N + ((int64_t)p2 * nv + y) * nv * no + (int64_t)n0 * no);
+  // This thread's part of every stage: k = kt and rows xt + e * RP of both tiles.  Rows
+  // past nv repeat row nv - 1 (their outputs are never stored).  Loads go through buffer
+  // resources built from the (uniform) stage origin with 32-bit byte offsets per lane.
+  const int tid = threadIdx.x;
+  constexpr int RP = T::NT / T::BK;
+  const int kt = tid % T::BK, xt = tid / T::BK;
+  int rowa[T::EA], rowb[T::EB];
+#pragma unroll
+  for (int e = 0; e < T::EA; ++e) rowa[e] = min(m0 + xt + e * RP, nv - 1) - m0;
+#pragma unroll
+  for (int e = 0; e < T::EB; ++e) rowb[e] = min(n0 + xt + e * RP, nv - 1) - n0;
+  // swizzled LDS slots of (kt, xt + e * RP): RP is a multiple of 16, so the XOR
+  // pattern of row kt only touches xt
+  const int lda = kt * T::LDA + (xt ^ lds_swz<T::BK>(kt));
+  const int ldb = T::BK * T::LDA + kt * T::LDB + (xt ^ lds_swz<T::BK>(kt));
+  double ra[T::EA], rb[T::EB];
+  int lseg = 0, lk0 = 0;  // the next stage to load
+  auto fetch = [&]() {
+    const char *pa, *pb;
+    if (lseg == 0) { pa = A0; pb = B0; }
+    else if (lseg == 1) { pa = A1; pb = B1; }
+    else if (lseg == 2) { pa = A2; pb = B2; }
+    else { pa = A3; pb = B3; }
+    const int ld = (lseg & 1) ? no : nv;
+    const BufRsrc sa = buf_rsrc(pa + lk0 * 8), sb = buf_rsrc(pb + lk0 * 8);
+    const bool in = lk0 + kt < ld;                    // the segment's last stage may be partial
+    const int kc = in ? kt : ld - 1 - lk0;           // k past K reads a valid element, then 0
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) {
+      const double v = buf_load_f64(sa, (unsigned)(rowa[e] * ld + kc) * 8u);
+      ra[e] = in ? v : 0.0;
     }
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) {
+      const double v = buf_load_f64(sb, (unsigned)(rowb[e] * ld + kc) * 8u);
+      rb[e] = in ? v : 0.0;
+    }
+    lk0 += T::BK;
+    if (lk0 >= ld) { lk0 = 0; ++lseg; }
+  };
+  auto store = [&](double* st) {
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) st[lda + e * RP] = ra[e];
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) st[ldb + e * RP] = rb[e];
   };
   d4v acc[T::FM][T::FN];
   zero_acc<T>(acc);
-  k_loop<T>(nsteps, m0, n0, ops, acc, lds);
-
-  double* out = cubes + ((int64_t)z * NSLOT + plane) * nv3 + (int64_t)y * nv2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
+  fetch();
+  store(lds);
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    double* cur = lds + (s & 1) * T::STAGE;
+    double* nxt = lds + ((s + 1) & 1) * T::STAGE;
+    const bool more = s + 1 < nsteps;
+    if (more) fetch();
+    mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
+    if (more) store(nxt);
+    __syncthreads();
+  }
+
+  double* out = cubes + ((int64_t)z * NSLOT + plane) * nv3 + (int64_t)y * nv2;
 #pragma unroll
   for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll

@@ -15,8 +15,8 @@
 // chunks into row-major LDS rows, and the K loop needs no bounds checks):
 //   t2L [piece][p][q][x][dk]  = t2[p][q][x][d]
 //   t2NL[piece][p][y][x][lk]  = -t2[p][l][x][y]
-//   GwTL[piece][r][y][z][dk]  = Gw[r][y][d][z]   (= g_{ydzr})
-//   GoTL[piece][q][r][z][lk]  = Go[q][r][l][z]   (= g_{lqzr})
+//   GwTL[piece][r][y][z][dk]  = Gw[r][y][z][d]   (= g_{ydzr})
+//   GoTL[piece][q][r][z][lk]  = Go[q][r][z][l]   (= g_{lqzr})
 #include <hip/hip_bf16.h>
 
 #include "cc3.h"
@@ -131,10 +131,10 @@ void launch_lp_convert(const double* t2, const Blocks& b, int no, int nv, const 
     for (int p = 0; p < no; ++p)
       lp_copy<M>(t2 + (int64_t)p * o * v * v, 1, v, v * v, -1.0, nv, nv, no,
                  (char*)lp.t2N + (size_t)p * v * v * lk * esz, o * v * v * lk, st);
-    // GwTL[r][y][z][d] = Gw[r][y][d][z]: outer = (r, y), x = z, k = d
-    lp_copy<M>(b.Gw, v * v, 1, v, 1.0, no * nv, nv, nv, lp.GwT, o * v * v * dk, st);
-    // GoTL[q][r][z][l] = Go[q][r][l][z]: outer = (q, r), x = z, k = l
-    lp_copy<M>(b.Go, o * v, 1, v, 1.0, no * no, nv, no, lp.GoT, o * o * v * lk, st);
+    // GwTL[r][y][z][d] = Gw[r][y][z][d]: outer = (r, y), x = z, k = d
+    lp_copy<M>(b.Gw, v * v, v, 1, 1.0, no * nv, nv, nv, lp.GwT, o * v * v * dk, st);
+    // GoTL[q][r][z][l] = Go[q][r][z][l]: outer = (q, r), x = z, k = l
+    lp_copy<M>(b.Go, o * v, o, 1, 1.0, no * no, nv, no, lp.GoT, o * o * v * lk, st);
   };
   const int m = mode_of(lp.prec);
   if (m == 0) run(std::integral_constant<int, 0>());
