@@ -1,4 +1,5 @@
-"""Brute-force evaluation of the CC3 triples residual over the full T3 tensor.
+"""Brute-force evaluation of the CC3 triples residual (and of the t3-dependent
+intermediates of the Jacobian preparation) over the full T3 tensor.
 
 TEST INFRASTRUCTURE ONLY (tiny sizes: it stores all nv^3 no^3 amplitudes).
 This is the plain definition the restricted loop of Algorithm 1 reaches up to
@@ -41,6 +42,28 @@ def transformed_hamiltonian(eps, L, t1):
 
 def residual_bruteforce(eps, L, t1, t2):
     """(Omega1, Omega2, tau_full) by the plain definition over all ordered triples."""
+    tt, tau, g_ovov, g_ooov, g_vvov, F = _full_contravariant(eps, L, t1, t2)
+    O1 = np.einsum("ijkabc,jbkc->ia", tt, g_ovov, optimize=True)
+    O2 = (np.einsum("ijkabc,kc->ijab", tt, F, optimize=True)
+          - np.einsum("ijkabc,jlkc->ilab", tt, g_ooov, optimize=True)
+          + np.einsum("ijkabc,dbkc->ijad", tt, g_vvov, optimize=True))
+    Y = 2.0 * O2 + O2.transpose(0, 1, 3, 2)
+    return O1, (Y + Y.transpose(1, 0, 3, 2)) / 3.0, tau
+
+
+def jacobian_prep_bruteforce(eps, L, t1, t2):
+    """The intermediates of the preparation for the Jacobian transformations by their
+    plain definition over all ordered triples (j, k summed freely):
+        Zv[a][b][i][d] = - sum_{jkc} tau~^{abc}_{ijk} g_{jdkc}
+        Zo[a][j][i][l] =   sum_{kbc} tau~^{abc}_{ijk} g_{lbkc}"""
+    tt, _, g_ovov, _, _, _ = _full_contravariant(eps, L, t1, t2)
+    Zv = -np.einsum("ijkabc,jdkc->abid", tt, g_ovov, optimize=True)
+    Zo = np.einsum("ijkabc,lbkc->ajil", tt, g_ovov, optimize=True)
+    return Zv, Zo
+
+
+def _full_contravariant(eps, L, t1, t2):
+    """tau~ and tau over all ordered triples, with the blocks their contractions use."""
     no, _, nv, _ = t2.shape
     gt, Ft = transformed_hamiltonian(eps, L, t1)
     o, v = slice(0, no), slice(no, None)
@@ -65,9 +88,4 @@ def residual_bruteforce(eps, L, t1, t2):
     tt = (4.0 * tau - 2.0 * np.einsum("ijkacb->ijkabc", tau) - 2.0 * np.einsum("ijkcba->ijkabc", tau)
           - 2.0 * np.einsum("ijkbac->ijkabc", tau) + np.einsum("ijkbca->ijkabc", tau)
           + np.einsum("ijkcab->ijkabc", tau))
-    O1 = np.einsum("ijkabc,jbkc->ia", tt, g_ovov, optimize=True)
-    O2 = (np.einsum("ijkabc,kc->ijab", tt, F, optimize=True)
-          - np.einsum("ijkabc,jlkc->ilab", tt, g_ooov, optimize=True)
-          + np.einsum("ijkabc,dbkc->ijad", tt, g_vvov, optimize=True))
-    Y = 2.0 * O2 + O2.transpose(0, 1, 3, 2)
-    return O1, (Y + Y.transpose(1, 0, 3, 2)) / 3.0, tau
+    return tt, tau, g_ovov, g_ooov, g_vvov, F

@@ -7,7 +7,9 @@ library and its Python binding) never calls it and shares no code with it.
 It follows Paul, Myhre & Koch, "A new and efficient implementation of CC3"
 (arXiv 2007.01088): Section "Implementation", Algorithm 1 (CC3 ground-state
 equations), the permutation operator P^{abc}_{ijk}, the orbital-energy
-difference, the contravariant amplitudes and the covariant back-transformation.
+difference, the contravariant amplitudes and the covariant back-transformation;
+and Algorithm 2 (the t3-dependent intermediates of the preparation for the
+Jacobian transformations).
 Every step is a numpy einsum over float64 arrays, taken in the order the
 algorithm states; no blocking, fusion or reordering beyond it.
 
@@ -45,7 +47,8 @@ __all__ = [
     "t1_transform", "IntegralBlocks", "fock_ov", "w_term", "t3_amplitudes",
     "contravariant", "occupied_permutations", "unordered_triples", "omega_tilde",
     "back_transform", "triples_residual", "triples_residual_blocks",
-    "omega_tilde_subset", "nominal_flops", "FlopCounter",
+    "omega_tilde_subset", "nominal_flops", "FlopCounter", "jacobian_prep_tilde",
+    "jacobian_prep",
 ]
 
 
@@ -303,3 +306,42 @@ def omega_tilde_subset(eps, L, t1, t2, triples):
 def nominal_flops(no: int, nv: int) -> float:
     """The paper's asymptotic ground-state cost per residual call: 4 nv^4 no^3 FLOP (abstract)."""
     return 4.0 * float(nv) ** 4 * float(no) ** 3
+
+
+# --------------------------------------------------------------------------
+# Preparation for the Jacobian transformations (Algorithm 2).
+# --------------------------------------------------------------------------
+
+def jacobian_prep_tilde(eps: np.ndarray, t2: np.ndarray, blk: IntegralBlocks, triples=None,
+                        flops: FlopCounter | None = None):
+    """The intermediates of Algorithm 2 from the given unordered triples.
+
+    The same restricted loop, t3 and contravariant t3 as Algorithm 1; then for each
+    distinct permutation (p,q,r) of (i,j,k), with U = tau~_{pqr}:
+        Zv^{ab}_{pd} -= sum_c    U^{abc} g_{qdrc}
+        Zo^{a}_{qpl} += sum_{bc} U^{abc} g_{lbrc}
+    Arrays (row-major): Zv[a][b][i][d] = Z~^v_{abid}, Zo[a][j][i][l] = Z~^o_{ajil}.
+    """
+    no, _, nv, _ = t2.shape
+    Zv = np.zeros((nv, nv, no, nv))
+    Zo = np.zeros((nv, no, no, no))
+    if triples is None:
+        triples = unordered_triples(no)
+    for (i, j, k) in triples:
+        i, j, k = int(i), int(j), int(k)
+        if i == j == k:
+            continue
+        tau = t3_amplitudes(i, j, k, eps, t2, blk, flops)
+        tt = contravariant(tau)
+        for (p, q, r), U in occupied_permutations(i, j, k, tt):
+            Zv[:, :, p, :] -= _e("abc,dc->abd", U, blk.g_ovov[q, :, r, :], flops=flops)
+            Zo[:, q, p, :] += _e("abc,lbc->al", U, blk.g_ovov[:, :, r, :], flops=flops)
+    return Zv, Zo
+
+
+def jacobian_prep(eps, L, t1, t2, flops: FlopCounter | None = None):
+    """Algorithm 2 from Cholesky vectors: (Zv, Zo) as in jacobian_prep_tilde, all triples."""
+    no = t1.shape[0]
+    Lt = t1_transform(L, t1)
+    blk = IntegralBlocks(Lt, no)
+    return jacobian_prep_tilde(eps, t2, blk, flops=flops)

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from oracle import cc3_oracle as O
+from oracle import bruteforce as B
 from oracle.bruteforce import residual_bruteforce, transformed_hamiltonian
 from paper_2007_01088_amd.synth import make_inputs
 
@@ -237,3 +238,47 @@ def test_flop_convention_reproduces_paper_efficiencies():
     D, E = comb(no, 3), no * (no - 1)
     lead = (D + E) * 6 * 2 * nv**4 + (6 * D + 3 * E) * 2 * nv**4
     assert abs(lead / O.nominal_flops(no, nv) - 1.0) < 0.03
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2: t3-dependent intermediates of the preparation for the Jacobian
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("no,nv,nJ,t1z", [(3, 4, 6, True), (3, 4, 6, False), (4, 5, 8, False),
+                                          (4, 6, 9, False), (2, 3, 5, False)])
+def test_jacobian_prep_equals_bruteforce(no, nv, nJ, t1z):
+    """The restricted loop of Algorithm 2 (6/3 distinct permutations, i = j = k skipped)
+    against the plain definition over every ordered triple."""
+    d = make_inputs(no, nv, nJ, t1_zero=t1z)
+    zv, zo = O.jacobian_prep(d["eps"], d["L"], d["t1"], d["t2"])
+    bv, bo = B.jacobian_prep_bruteforce(d["eps"], d["L"], d["t1"], d["t2"])
+    assert np.abs(bv).max() > 0 and np.abs(bo).max() > 0
+    assert np.abs(zv - bv).max() <= 1e-13 * np.abs(bv).max()
+    assert np.abs(zo - bo).max() <= 1e-13 * np.abs(bo).max()
+
+
+def test_jacobian_prep_trace_is_omega1():
+    """sum_j Z~^o_{ajij} = sum_{jkbc} tau~^{abc}_{ijk} g_{jbkc}, the Omega1 contraction of
+    Algorithm 1 (computed here by the other routine)."""
+    d = make_inputs(5, 9, 14)
+    zv, zo = O.jacobian_prep(d["eps"], d["L"], d["t1"], d["t2"])
+    o1, _ = O.omega_tilde_subset(d["eps"], d["L"], d["t1"], d["t2"], O.unordered_triples(5))
+    tr = np.einsum("ajij->ia", zo)
+    assert np.abs(tr - o1).max() <= 1e-13 * np.abs(o1).max()
+
+
+def test_jacobian_prep_homogeneity_and_special_cases():
+    """Linear in t2; L -> s L scales both intermediates by s^4; t2 = 0 and no = 1 give 0."""
+    d = make_inputs(4, 6, 9)
+    zv, zo = O.jacobian_prep(d["eps"], d["L"], d["t1"], d["t2"])
+    zv2, zo2 = O.jacobian_prep(d["eps"], d["L"], d["t1"], 2.0 * d["t2"])
+    assert np.abs(zv2 - 2.0 * zv).max() <= 1e-14 * np.abs(zv).max()
+    assert np.abs(zo2 - 2.0 * zo).max() <= 1e-14 * np.abs(zo).max()
+    zv3, zo3 = O.jacobian_prep(d["eps"], 1.5 * d["L"], d["t1"], d["t2"])
+    assert np.abs(zv3 - 1.5 ** 4 * zv).max() <= 1e-13 * np.abs(zv3).max()
+    assert np.abs(zo3 - 1.5 ** 4 * zo).max() <= 1e-13 * np.abs(zo3).max()
+    zv0, zo0 = O.jacobian_prep(d["eps"], d["L"], d["t1"], 0.0 * d["t2"])
+    assert not zv0.any() and not zo0.any()
+    e = make_inputs(1, 5, 7)
+    zv1, zo1 = O.jacobian_prep(e["eps"], e["L"], e["t1"], e["t2"])
+    assert not zv1.any() and not zo1.any()
