@@ -273,6 +273,8 @@ def main() -> int:
     ap.add_argument("--prec", default="fp64", choices=["fp64"])
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip timing the mixed-precision W contractions (FP32, BF16x3, BF16x6)")
+    ap.add_argument("--no-jacobian-prep", action="store_true",
+                    help="skip timing the Jacobian-preparation intermediates (Algorithm 2)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-molecules", type=int, default=16,
@@ -418,6 +420,31 @@ def main() -> int:
     }
     if mixed:
         out["mixed"] = mixed
+    if not args.no_jacobian_prep:
+        # Algorithm 2 (the t3-dependent intermediates of the Jacobian preparation) on the
+        # same inputs; nominal cost as one ground-state call, 4 nv^4 no^3
+        zv = torch.empty((nv, nv, no, nv), dtype=torch.float64, device=dev)
+        zo = torch.empty((nv, no, no, no), dtype=torch.float64, device=dev)
+        ctx.jacobian_prep(g["eps"], g["L"], g["t1"], g["t2"], zv, zo)
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.jacobian_prep(g["eps"], g["L"], g["t1"], g["t2"], zv, zo)
+        torch.cuda.synchronize()
+        dtj = (time.perf_counter() - t0) / args.steps
+        stj = ctx.profile_get()
+        ctx.profile_enable(False)
+        out["jacobian_prep"] = {
+            "what": "Z~v_{abid} and Z~o_{ajil} of the preparation for the Jacobian transformations",
+            "value": nominal / dtj / 1e12, "unit": "TFLOP/s", "ms_per_step": dtj * 1e3,
+            "kernels": {k: {"launches": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
+                            "tflops": (v["flops"] / (v["total_ms"] * 1e-3) / 1e12)
+                            if v["flops"] and v["total_ms"] else None}
+                        for k, v in stj.items()},
+        }
+        log(f"jacobian prep: {out['jacobian_prep']['value']:.2f} TFLOP/s, {dtj * 1e3:.1f} ms per call")
+        del zv, zo
     if args.serve_molecules > 0:
         ctx.close()
         del g, o1, o2

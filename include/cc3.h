@@ -157,6 +157,21 @@ int cc3_t3_block(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps, con
                  const double* t1, const double* t2, int i, int j, int k, double* tau, int prec,
                  void* workspace, size_t workspace_bytes, cc3_stream_t stream);
 
+/* The t3-dependent intermediates of the preparation for the Jacobian
+ * transformations (Sec. "Implementation", Algorithm 2): the same restricted loop,
+ * t3 and contravariant t3 as cc3_triples_residual, then for each distinct
+ * occupied permutation (p,q,r) of a triple, with U = tau~_{pqr},
+ *   Z~v_{abpd} -= sum_c U^{abc} g_{qdrc},   Z~o_{aqpl} += sum_{bc} U^{abc} g_{lbrc}.
+ * Outputs (device, row-major, overwritten or added with CC3_ACCUMULATE):
+ *   zv[nv][nv][no][nv] = Z~v_{abid},  zo[nv][no][no][no] = Z~o_{ajil}.
+ * Inputs, precision (of the W contractions) and workspace as for
+ * cc3_triples_residual (same cc3_workspace_size).  Supported sizes additionally
+ * need no^2 nv^2 < 2^31.  Errors: CC3_E_INVAL, CC3_E_NOMEM, CC3_E_DEVICE,
+ * CC3_E_PRECOND (with CC3_CHECK). */
+int cc3_jacobian_prep(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps, const double* L,
+                      const double* t1, const double* t2, double* zv, double* zo, int prec,
+                      unsigned flags, void* workspace, size_t workspace_bytes, cc3_stream_t stream);
+
 /* FLOP per residual call: *nominal = 4 nv^4 no^3 (the paper's asymptotic count,
  * abstract); *executed = the multiply-adds (x2) this library's triple loop
  * issues for the dominant contractions and their small companions, padding

@@ -56,6 +56,8 @@ _residual_subset = _sig("cc3_triples_residual_subset",
                          _c_int, ctypes.c_uint, _vp, _c_size, _vp])
 _t3_block = _sig("cc3_t3_block", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _c_int, _c_int,
                                   _c_int, _dp, _c_int, _vp, _c_size, _vp])
+_jprep = _sig("cc3_jacobian_prep", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp, _dp,
+                                     _c_int, ctypes.c_uint, _vp, _c_size, _vp])
 _flops = _sig("cc3_flops", [_c_int, _c_int, ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double)])
 _prof_enable = _sig("cc3_profile_enable", [_vp, _c_int])
@@ -101,7 +103,7 @@ _srv_stats = _sig("cc3_server_get_stats", [_vp, ctypes.POINTER(ServerStats)])
 EXPORTED = ["cc3_create", "cc3_destroy", "cc3_last_error", "cc3_workspace_size",
             "cc3_triples_residual", "cc3_triples_residual_blocks", "cc3_triples_residual_subset",
             "cc3_t3_block", "cc3_flops", "cc3_profile_enable", "cc3_profile_get",
-            "cc3_server_create", "cc3_server_destroy", "cc3_server_footprint",
+            "cc3_jacobian_prep", "cc3_server_create", "cc3_server_destroy", "cc3_server_footprint",
             "cc3_molecule_register", "cc3_molecule_release", "cc3_submit", "cc3_poll",
             "cc3_wait", "cc3_cancel", "cc3_server_get_stats"]
 
@@ -237,6 +239,21 @@ class Context:
                          _ptr(t2, "t2"), i, j, k, _ptr(tau, "tau"), prec, ws.data_ptr(),
                          ws.numel(), _stream(stream)), "cc3_t3_block")
         return tau
+
+    def jacobian_prep(self, eps, L, t1, t2, zv=None, zo=None, prec=FP64, flags=0, stream=None):
+        """Algorithm 2 intermediates: zv[a][b][i][d] = Z~v_{abid}, zo[a][j][i][l] = Z~o_{ajil}."""
+        no, nv = t1.shape
+        nchol = L.shape[0]
+        if zv is None:
+            zv = torch.empty((nv, nv, no, nv), dtype=torch.float64, device=t2.device)
+        if zo is None:
+            zo = torch.empty((nv, no, no, no), dtype=torch.float64, device=t2.device)
+        nbytes = workspace_size(no, nv, nchol, prec, flags)
+        ws = self.workspace(nbytes)
+        _check(_jprep(self._h, no, nv, nchol, _ptr(eps, "eps"), _ptr(L, "L"), _ptr(t1, "t1"),
+                      _ptr(t2, "t2"), _ptr(zv, "zv"), _ptr(zo, "zo"), prec, flags, ws.data_ptr(),
+                      ws.numel(), _stream(stream)), "cc3_jacobian_prep")
+        return zv, zo
 
     # ---- kernel timing ---------------------------------------------------
     def profile_enable(self, on: bool = True) -> None:

@@ -217,3 +217,27 @@ extern "C" int cc3_t3_block(cc3_ctx* c, int no, int nv, int nchol, const double*
   HIPCHK(hipStreamSynchronize(st));
   return CC3_OK;
 }
+
+extern "C" int cc3_jacobian_prep(cc3_ctx* c, int no, int nv, int nchol, const double* eps,
+                                 const double* L, const double* t1, const double* t2, double* zv,
+                                 double* zo, int prec, unsigned flags, void* ws, size_t ws_bytes,
+                                 cc3_stream_t stream) {
+  Plan p;
+  int rc = common_checks(c, no, nv, nchol, prec, flags, ws, ws_bytes, &p);
+  if (rc) return rc;
+  if (nchol < 1) return fail(CC3_E_INVAL, "nchol must be >= 1 for the Cholesky form");
+  if ((int64_t)no * no * nv * nv >= ((int64_t)1 << 31))
+    return fail(CC3_E_INVAL, "no^2 nv^2 must stay below 2^31 for the Jacobian preparation "
+                "(no=%d nv=%d)", no, nv);
+  const void* ptrs[] = {eps, L, t1, t2, zv, zo};
+  const char* names[] = {"eps", "L", "t1", "t2", "zv", "zo"};
+  for (int i = 0; i < 6; ++i)
+    if ((rc = check_dev_ptr(ptrs[i], names[i]))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Ws w = carve(p, ws, nullptr);
+  std::lock_guard<std::mutex> g(c->mu);
+  if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, L, t2, st))) return rc;
+  if ((rc = prepare_cholesky(&c->prof, p, w, L, t1, st))) return rc;
+  return jacobian_prep_from_blocks(c->run, &c->prof, p, w, eps, t2, zv, zo,
+                                   (flags & CC3_ACCUMULATE) != 0, st);
+}

@@ -57,7 +57,7 @@ int check_dev_ptr(const void* p, const char* what) {
 // kernel timing
 // ---------------------------------------------------------------------------
 const char* kFamilies[NFAM] = {"t1_transform", "block_build", "w_build", "mix",
-                               "omega_contract", "reduce", "back_transform"};
+                               "omega_contract", "reduce", "back_transform", "jacobian_prep"};
 
 hipEvent_t Profiler::take() {
   if (!pool.empty()) {
@@ -214,7 +214,8 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   p->off_OtT = take(o * o * v * v * 8);
   p->off_t2N = take(o * o * v * v * 8);
   p->off_lp = take(lp_operand_bytes(prec, no, nv));
-  p->pvv_bytes = align256(tc * 6 * v * (v + 1) * 8);
+  // partial slabs: Omega chunks of nv x (nv + 1), or Jacobian-preparation chunks of nv x no
+  p->pvv_bytes = align256(tc * 6 * v * std::max(v + 1, o) * 8);
   p->soo_bytes = align256((size_t)batch * 6 * o * v * v * 8);
   p->off_Pvv = take(2 * p->pvv_bytes);
   p->off_Soo = take(2 * p->soo_bytes);
@@ -361,6 +362,71 @@ int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, c
   {
     Timer tm(pf, st, FAM_BACK, 0.0, 0.0);
     launch_back_transform(w.Ot1, w.Ot2, w.OtT, omega1, omega2, no, nv, accumulate, st);
+  }
+  HIPCHK(hipGetLastError());
+  return CC3_OK;
+}
+
+// Algorithm 2 over every unordered triple: the same batched W build and mix as the
+// residual, then per batch the Zo partials on the batch's stream and, chained in
+// batch order, the Zo reduction and the output-stationary Zv contraction.
+int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w,
+                              const double* eps, const double* t2, double* zv, double* zo,
+                              bool accumulate, hipStream_t st) {
+  const int no = p.no, nv = p.nv;
+  int rc = rn.init();
+  if (rc) return rc;
+  if (!accumulate) {
+    launch_fill(zv, (int64_t)nv * nv * nv * no, 0.0, st);
+    launch_fill(zo, (int64_t)nv * no * no * no, 0.0, st);
+  }
+  launch_triple_table(w.tri, no, st);
+  std::vector<int> ht, kinds;
+  host_triples(no, ht);
+  launch_t2N(t2, w.t2N, no, nv, st);
+  if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, no, nv, w.lp, st);
+  HIPCHK(hipEventRecord(rn.ev_fork, st));
+  for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
+  static const int nstream = env_int("CC3_SERIAL", 0) ? 1 : NSTREAM;
+  const int n = p.ntri;
+  int nbatch = 0;
+  for (int t0 = 0; t0 < n; t0 += p.batch, ++nbatch) {
+    const int nb = std::min(p.batch, n - t0);
+    const int k = nbatch % nstream;
+    hipStream_t sk = rn.s[k];
+    kinds.resize(nb);
+    for (int t = 0; t < nb; ++t)
+      kinds[t] = kind_of(ht[3 * (t0 + t)], ht[3 * (t0 + t) + 1], ht[3 * (t0 + t) + 2]);
+    const int* tb = w.tri + 3 * t0;
+    {
+      Timer tm(pf, sk, FAM_W, wbuild_flops(no, nv, kinds.data(), nb), 0.0);
+      if (p.prec == CC3_FP64)
+        launch_wbuild(t2, w.t2N, w.b, tb, nb, w.cubes[k], no, nv, false, sk);
+      else
+        launch_wbuild_lp(w.lp, tb, nb, w.cubes[k], no, nv, false, sk);
+    }
+    {
+      Timer tm(pf, sk, FAM_MIX, 0.0, 0.0);
+      launch_mix(eps, tb, nb, w.cubes[k], no, nv, sk);
+    }
+    {
+      Timer tm(pf, sk, FAM_ZPREP, zprep_flops(no, nv, kinds.data(), nb) * ((double)no / (nv + no)), 0.0);
+      launch_zo(w.cubes[k], w.b, tb, nb, w.Pvv[k], nullptr, no, nv, sk, false);
+    }
+    if (nbatch > 0) HIPCHK(hipStreamWaitEvent(sk, rn.ev_red[(nbatch - 1) % nstream], 0));
+    {
+      Timer tm(pf, sk, FAM_REDUCE, 0.0, 0.0);
+      launch_zo(w.cubes[k], w.b, tb, nb, w.Pvv[k], zo, no, nv, sk, true);
+    }
+    {
+      Timer tm(pf, sk, FAM_ZPREP, zprep_flops(no, nv, kinds.data(), nb) * ((double)nv / (nv + no)), 0.0);
+      launch_zv(w.cubes[k], w.b, tb, nb, zv, no, nv, sk);
+    }
+    HIPCHK(hipEventRecord(rn.ev_red[k], sk));
+  }
+  for (int k = 0; k < NSTREAM; ++k) {
+    HIPCHK(hipEventRecord(rn.ev_done[k], rn.s[k]));
+    HIPCHK(hipStreamWaitEvent(st, rn.ev_done[k], 0));
   }
   HIPCHK(hipGetLastError());
   return CC3_OK;

@@ -28,7 +28,7 @@ int check_sizes(int no, int nv, int nchol, int prec);
 int check_dev_ptr(const void* p, const char* what);
 
 // ---- kernel timing ------------------------------------------------------------
-enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_REDUCE, FAM_BACK, NFAM };
+enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_REDUCE, FAM_BACK, FAM_ZPREP, NFAM };
 extern const char* kFamilies[NFAM];
 
 struct TimedLaunch {
@@ -103,6 +103,11 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
 int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const double* eps,
                          const double* t2, double* omega1, double* omega2, bool accumulate,
                          hipStream_t st);
+// Algorithm 2: zv[a][b][i][d] = Z~v_{abid}, zo[a][j][i][l] = Z~o_{ajil} (zeroed first
+// unless accumulate), over every unordered triple.
+int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w,
+                              const double* eps, const double* t2, double* zv, double* zo,
+                              bool accumulate, hipStream_t st);
 int run_input_check(const Plan& p, const Ws& w, const double* eps, const double* L,
                     const double* t2, hipStream_t st);
 

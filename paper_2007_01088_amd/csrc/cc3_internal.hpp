@@ -94,6 +94,15 @@ void launch_set_triples(int* tri_dev, const int* host_tri, int n, hipStream_t st
 void launch_check(const double* eps, const double* L, const double* t2, int no, int nv, int nJ,
                   int* flag, hipStream_t st);
 
+// Preparation for the Jacobian transformations (Algorithm 2), per batch:
+// Zv -= (read-modify-write, output-stationary); Zo partials into Pzo (reduce = false),
+// then their fixed-order sum into Zo (reduce = true).
+void launch_zv(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Zv, int no,
+               int nv, hipStream_t st);
+void launch_zo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pzo,
+               double* Zo, int no, int nv, hipStream_t st, bool reduce);
+double zprep_flops(int no, int nv, const int* host_types, int n);
+
 // Algorithmic FLOP of one launch of the two dominant kernels (padding excluded).
 double wbuild_flops(int no, int nv, const int* host_types, int n);
 double omega_flops(int no, int nv, const int* host_types, int n);

@@ -717,6 +717,205 @@ __global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int
 
 // Number of b chunks the Omega GEMM of one (triple, permutation) is split into:
 // enough workgroups for 256 CUs at two per CU, no more.
+// ---------------------------------------------------------------------------
+// Preparation for the Jacobian transformations (Algorithm 2): for each distinct
+// occupied permutation (p,q,r) of a triple, with U = tau~_{pqr},
+//   Zv[a][b][p][d] -= sum_c    U[a,b,c] g_{qdrc}     (g_{qdrc} = Jo[q][r][d][c])
+//   Zo[a][q][p][l] += sum_{bc} U[a,b,c] g_{lbrc}     (g_{lbrc} = Jo[l][r][b][c])
+// ---------------------------------------------------------------------------
+// The view of U_pi[a, b, c] at fixed b as a strided (a, c) matrix: base + b * sbb, (sm, sk).
+__device__ inline void u_view(int pi, int nv, int& slot, int& sbb, int& sm, int& sk) {
+  switch (pi) {
+    case 0: slot = SLOT_TT; sbb = nv; sm = nv * nv; sk = 1; break;    // tau~[a][b][c]
+    case 1: slot = SLOT_TT; sbb = nv * nv; sm = nv; sk = 1; break;    // tau~[b][a][c]
+    case 2: slot = SLOT_TT; sbb = nv; sm = 1; sk = nv * nv; break;    // tau~[c][b][a]
+    case 3: slot = SLOT_TTT; sbb = nv; sm = nv * nv; sk = 1; break;   // tau~T[a][b][c]
+    case 4: slot = SLOT_TTT; sbb = nv; sm = 1; sk = nv * nv; break;   // tau~T[c][b][a]
+    default: slot = SLOT_TT; sbb = nv * nv; sm = 1; sk = nv; break;   // tau~[b][c][a]
+  }
+}
+
+#define ZLIST_MAX 160  // pairs of one batch with a given p (at most six per triple)
+
+// Zv, output-stationary: one workgroup per (p, b, 128 x 128 tile of (a, d)) sums the
+// batch's (triple, permutation) pairs with that p, in batch order, over c, and
+// subtracts the result from Zv (read-modify-write; the batches run in order).
+typedef TileCfg<4, 2, 2, 4, 16> ZvCfg;
+
+__global__ __launch_bounds__(ZvCfg::NT) void k_zv(const double* __restrict__ cubes,
+                                                  const double* __restrict__ Jo,
+                                                  const int* __restrict__ tri, int ntri,
+                                                  double* __restrict__ Zv, int no, int nv,
+                                                  int tiles_m, int tiles_n) {
+  typedef ZvCfg T;
+  __shared__ double lds[T::LDS_DOUBLES];
+  __shared__ int lz[ZLIST_MAX], lqr[ZLIST_MAX];
+  __shared__ int cnt;
+  const int p = blockIdx.y;
+  const int tpp = tiles_m * tiles_n;
+  const int b = blockIdx.x / tpp, tile = blockIdx.x % tpp;
+  const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int z = 0; z < ntri; ++z) {
+      const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+      const int kind = tri_kind(i, j, k);
+      for (int pi = 0; pi < 6; ++pi) {
+        if (!perm_active(kind, pi)) continue;
+        int pp, q, r;
+        perm_pqr(pi, i, j, k, pp, q, r);
+        if (pp == p && n < ZLIST_MAX) { lz[n] = z * 6 + pi; lqr[n] = q * no + r; ++n; }
+      }
+    }
+    cnt = n;
+  }
+  __syncthreads();
+  const int n = cnt;
+  if (n == 0) return;
+  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
+  const int cs = (nv + T::BK - 1) / T::BK;
+  auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
+    const int t = s / cs;
+    k0 = (s % cs) * T::BK;
+    const int zp = lz[t], z = zp / 6, pi = zp % 6;
+    int slot, sbb, sm, sk;
+    u_view(pi, nv, slot, sbb, sm, sk);
+    A = make_opnd(cubes + ((int64_t)z * NSLOT + slot) * nv3 + (int64_t)b * sbb, sm, sk, nv, nv,
+                  sm == 1);
+    B = make_opnd(Jo + (int64_t)lqr[t] * nv2, nv, 1, nv, nv, false);  // rows d, k = c
+  };
+  d4v acc[T::FM][T::FN];
+  zero_acc<T>(acc);
+  k_loop<T>(n * cs, m0, n0, ops, acc, lds);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % T::WM, wn = wave / T::WM;
+#pragma unroll
+  for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < T::FN; ++fn)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int a = m0 + acc_row<T>(wm, fm, lane, rr);
+        const int d = n0 + acc_col<T>(wn, fn, lane);
+        if (a < nv && d < nv) Zv[(((int64_t)a * nv + b) * no + p) * nv + d] -= acc[fm][fn][rr];
+      }
+}
+
+// Zo partials: per (triple, permutation, 128-row tile of a, b chunk)
+//   Pzo[z][pi][chunk][a][l] = sum_{b in chunk} sum_c U[a,b,c] Jo[l][r][b][c]   (l < no <= 64)
+typedef TileCfg<4, 2, 2, 2, 16> ZoCfg;
+
+__global__ __launch_bounds__(ZoCfg::NT) void k_zo(const double* __restrict__ cubes,
+                                                  const double* __restrict__ Jo,
+                                                  const int* __restrict__ tri,
+                                                  double* __restrict__ Pzo, int no, int nv,
+                                                  int nbchunks) {
+  typedef ZoCfg T;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int pi = blockIdx.y, z = blockIdx.z;
+  const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+  if (!perm_active(tri_kind(i, j, k), pi)) return;
+  int p, q, r;
+  perm_pqr(pi, i, j, k, p, q, r);
+  const int bc = blockIdx.x % nbchunks;
+  const int m0 = (blockIdx.x / nbchunks) * T::BM;
+  const int bb0 = (int)((int64_t)bc * nv / nbchunks);
+  const int bb1 = (int)((int64_t)(bc + 1) * nv / nbchunks);
+  if (bb0 >= bb1) return;
+  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
+  int slot, sbb, sm, sk;
+  u_view(pi, nv, slot, sbb, sm, sk);
+  const double* ub = cubes + ((int64_t)z * NSLOT + slot) * nv3;
+  const int cs = (nv + T::BK - 1) / T::BK;
+  auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
+    const int b = bb0 + s / cs;
+    k0 = (s % cs) * T::BK;
+    A = make_opnd(ub + (int64_t)b * sbb, sm, sk, nv, nv, sm == 1);
+    B = make_opnd(Jo + (int64_t)r * nv2 + (int64_t)b * nv, (int64_t)no * nv2, 1, no, nv, false);
+  };
+  d4v acc[T::FM][T::FN];
+  zero_acc<T>(acc);
+  k_loop<T>((bb1 - bb0) * cs, m0, 0, ops, acc, lds);
+  double* out = Pzo + (((int64_t)z * 6 + pi) * nbchunks + bc) * nvl * no;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % T::WM, wn = wave / T::WM;
+#pragma unroll
+  for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < T::FN; ++fn)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int a = m0 + acc_row<T>(wm, fm, lane, rr);
+        const int l = acc_col<T>(wn, fn, lane);
+        if (a < nv && l < no) out[(int64_t)a * no + l] = acc[fm][fn][rr];
+      }
+}
+
+// Zo[a][q][p][l] += the chunk sums of the batch's pairs with that (p, q), in batch order.
+__global__ __launch_bounds__(256) void k_zo_reduce(const int* __restrict__ tri, int ntri,
+                                                   const double* __restrict__ Pzo,
+                                                   double* __restrict__ Zo, int no, int nv,
+                                                   int nbchunks) {
+  __shared__ int lz[ZLIST_MAX];
+  __shared__ int cnt;
+  const int q = blockIdx.y, p = blockIdx.z;
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int z = 0; z < ntri; ++z) {
+      const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+      const int kind = tri_kind(i, j, k);
+      for (int pi = 0; pi < 6; ++pi) {
+        if (!perm_active(kind, pi)) continue;
+        int pp, qq, r;
+        perm_pqr(pi, i, j, k, pp, qq, r);
+        if (pp == p && qq == q && n < ZLIST_MAX) lz[n++] = z * 6 + pi;
+      }
+    }
+    cnt = n;
+  }
+  __syncthreads();
+  const int n = cnt;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n == 0 || e >= (int64_t)nv * no) return;
+  const int a = (int)(e / no), l = (int)(e % no);
+  const int64_t slab = (int64_t)nv * no;
+  double s = 0.0;
+  for (int t = 0; t < n; ++t) {
+    const double* pz = Pzo + (int64_t)lz[t] * nbchunks * slab + e;
+    for (int c = 0; c < nbchunks; ++c) s += pz[c * slab];
+  }
+  Zo[(((int64_t)a * no + q) * no + p) * no + l] += s;
+}
+
+void launch_zv(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Zv, int no,
+               int nv, hipStream_t st) {
+  typedef ZvCfg T;
+  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + T::BN - 1) / T::BN;
+  hipLaunchKernelGGL(k_zv, dim3(nv * tm * tn, no), dim3(T::NT), 0, st, cubes, b.Jo, tri, ntri, Zv,
+                     no, nv, tm, tn);
+}
+
+void launch_zo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pzo,
+               double* Zo, int no, int nv, hipStream_t st, bool reduce) {
+  typedef ZoCfg T;
+  const int nbc = omega_nbchunks(nv, ntri);
+  if (!reduce) {
+    const int tm = (nv + T::BM - 1) / T::BM;
+    hipLaunchKernelGGL(k_zo, dim3(nbc * tm, 6, ntri), dim3(T::NT), 0, st, cubes, b.Jo, tri, Pzo,
+                       no, nv, nbc);
+  } else {
+    hipLaunchKernelGGL(k_zo_reduce, dim3(nblk((int64_t)nv * no, 256), no, no), dim3(256), 0, st,
+                       tri, ntri, Pzo, Zo, no, nv, nbc);
+  }
+}
+
+double zprep_flops(int no, int nv, const int* kinds, int n) {
+  const double v = nv, o = no;
+  double perms = 0;
+  for (int t = 0; t < n; ++t) perms += (kinds[t] == 0) ? 6 : 3;
+  return perms * (2.0 * v * v * v * v + 2.0 * v * v * v * o);
+}
+
 // Split-K chunks of the b index per (triple, permutation, tile): enough
 // workgroups for several rounds over the chip (two resident per CU), as a
 // multiple of 8 so that the tiles of one (triple, permutation, chunk) -- which
