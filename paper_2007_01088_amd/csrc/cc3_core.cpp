@@ -56,8 +56,9 @@ int check_dev_ptr(const void* p, const char* what) {
 // ---------------------------------------------------------------------------
 // kernel timing
 // ---------------------------------------------------------------------------
-const char* kFamilies[NFAM] = {"t1_transform", "block_build", "w_build", "mix",
-                               "omega_contract", "reduce", "back_transform", "jacobian_prep"};
+const char* kFamilies[NFAM] = {"t1_transform", "block_build",    "w_build",       "mix",
+                               "omega_contract", "reduce",        "back_transform", "jacobian_prep",
+                               "omega_oo"};
 
 hipEvent_t Profiler::take() {
   if (!pool.empty()) {
@@ -166,8 +167,8 @@ static int env_int(const char* name, int dflt) {
 
 size_t block_bytes(int no, int nv) {
   const size_t o = no, v = nv;
-  return align256(o * v * v * v * 8) * 2 + align256(o * o * o * v * 8) * 2 +
-         align256(o * o * v * v * 8) + align256(o * v * 8);
+  return align256(o * v * v * v * 8) + align256(o * (v + o) * v * v * 8) * 2 +
+         align256(o * o * o * v * 8) * 2 + align256(o * o * v * v * 8) + align256(o * v * 8);
 }
 
 Blocks carve_blocks(int no, int nv, void* base) {
@@ -175,7 +176,8 @@ Blocks carve_blocks(int no, int nv, void* base) {
   char* b = (char*)base;
   Blocks bl;
   bl.Gw = (double*)b; b += align256(o * v * v * v * 8);
-  bl.Gv = (double*)b; b += align256(o * v * v * v * 8);
+  bl.Gbc = (double*)b; b += align256(o * (v + o) * v * v * 8);
+  bl.Gcb = (double*)b; b += align256(o * (v + o) * v * v * 8);
   bl.Go = (double*)b; b += align256(o * o * o * v * 8);
   bl.Hs = (double*)b; b += align256(o * o * o * v * 8);
   bl.Jo = (double*)b; b += align256(o * o * v * v * 8);
@@ -199,12 +201,13 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   const size_t per_triple = 5 * p->cube * sizeof(double);
   batch = (int)std::min<size_t>((size_t)batch, std::max<size_t>(1, budget / per_triple));
   batch = env_int("CC3_BATCH", batch);
-  batch = std::min(batch, 160);  // the reduction lists at most 6 * 160 pairs per p
+  batch = std::min(batch, MAX_BATCH);  // bounds the kernels' per-p pair lists
   batch = std::max(1, std::min(batch, std::max(1, p->ntri)));
   p->batch = batch;
   // largest (triples x chunks) product over the batch sizes the loop can see
   size_t tc = 1;
-  for (int nb = 1; nb <= batch; ++nb) tc = std::max(tc, (size_t)nb * omega_nbchunks(nv, nb));
+  for (int nb = 1; nb <= batch; ++nb)
+    tc = std::max(tc, (size_t)nb * std::max(omega_kchunks(nv, nb), zo_nbchunks(nv, nb)));
   p->pvv_entries = tc;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
@@ -216,13 +219,11 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   p->off_lp = take(lp_operand_bytes(prec, no, nv));
   // partial slabs: Omega chunks of nv x (nv + 1), or Jacobian-preparation chunks of nv x no
   p->pvv_bytes = align256(tc * 6 * v * std::max(v + 1, o) * 8);
-  p->soo_bytes = align256((size_t)batch * 6 * o * v * v * 8);
   p->off_Pvv = take(2 * p->pvv_bytes);
-  p->off_Soo = take(2 * p->soo_bytes);
   p->off_tri = take((size_t)std::max(1, p->ntri) * 3 * sizeof(int) + 64);
   p->off_flag = take(64);
   // the Cholesky scratch is dead once the blocks are built: it shares the cube region
-  p->chol_bytes = J ? align256(J * v * v * 8) * 2 + align256(J * o * o * 8) * 2 +
+  p->chol_bytes = J ? align256(J * v * v * 8) + align256(J * o * o * 8) * 2 +
                           align256(J * o * v * 8) * 2 + align256(J * 8) + align256(J * o * o * 8)
                     : 0;
   p->cube_bytes = align256((size_t)batch * 5 * p->cube * 8);
@@ -243,7 +244,6 @@ Ws carve(const Plan& p, void* ws, const Blocks* external_blocks) {
   lp_operand_ptrs(p.prec, p.no, p.nv, base + p.off_lp, w.lp);
   for (int k = 0; k < 2; ++k) {
     w.Pvv[k] = (double*)(base + p.off_Pvv + k * p.pvv_bytes);
-    w.Soo[k] = (double*)(base + p.off_Soo + k * p.soo_bytes);
     w.cubes[k] = (double*)(base + p.off_cubes + k * p.cube_bytes);
   }
   w.tri = (int*)(base + p.off_tri);
@@ -253,7 +253,6 @@ Ws carve(const Plan& p, void* ws, const Blocks* external_blocks) {
   size_t off = 0;
   auto take = [&](size_t bytes) { char* at = c + off; off = align256(off + bytes); return (double*)at; };
   w.cs.Lvv = take(J * v * v * 8);
-  w.cs.LvvT = take(J * v * v * 8);
   w.cs.Loo = take(J * o * o * 8);
   w.cs.LooT = take(J * o * o * 8);
   w.cs.LvoT = take(J * o * v * 8);
@@ -266,13 +265,25 @@ Ws carve(const Plan& p, void* ws, const Blocks* external_blocks) {
 // ---------------------------------------------------------------------------
 // launch sequences
 // ---------------------------------------------------------------------------
-static void host_triples(int no, std::vector<int>& t) {
-  t.clear();
+// Host copy of the device triple table (launch_triple_table): the restricted loop
+// in lexicographic order, dealt round-robin over nbatch batches.
+static void host_triples(int no, int nbatch, std::vector<int>& t) {
+  std::vector<int> lex;
   for (int i = 0; i < no; ++i)
     for (int j = 0; j <= i; ++j)
       for (int k = 0; k <= j; ++k)
-        if (!(i == j && j == k)) { t.push_back(i); t.push_back(j); t.push_back(k); }
+        if (!(i == j && j == k)) { lex.push_back(i); lex.push_back(j); lex.push_back(k); }
+  const int n = (int)lex.size() / 3;
+  nbatch = std::max(1, nbatch);
+  t.assign(lex.size(), 0);
+  for (int L = 0; L < n; ++L) {
+    const int g = L % nbatch;
+    const int pos = g * (n / nbatch) + std::min(g, n % nbatch) + L / nbatch;
+    for (int c = 0; c < 3; ++c) t[3 * pos + c] = lex[3 * L + c];
+  }
 }
+
+static int nbatches(const Plan& p) { return (p.ntri + p.batch - 1) / p.batch; }
 
 static int kind_of(int i, int j, int k) { return (i == j) ? 1 : (j == k) ? 2 : 0; }
 
@@ -330,12 +341,16 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
     }
     {
       Timer tm(pf, sk, FAM_OMEGA, omega_flops(p.no, p.nv, kinds.data(), nb), 0.0);
-      launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], w.Soo[k], p.no, p.nv, sk);
+      launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], p.no, p.nv, sk);
     }
     if (nbatch > 0) HIPCHK(hipStreamWaitEvent(sk, rn.ev_red[(nbatch - 1) % nstream], 0));
     {
+      Timer tm(pf, sk, FAM_OMEGA_OO, omega_oo_flops(p.no, p.nv, kinds.data(), nb), 0.0);
+      launch_omega_oo(w.cubes[k], w.b, tb, nb, w.OtT, p.no, p.nv, sk);
+    }
+    {
       Timer tm(pf, sk, FAM_REDUCE, 0.0, 0.0);
-      launch_reduce(tb, nb, w.Pvv[k], w.Soo[k], w.Ot1, w.Ot2, w.OtT, p.no, p.nv, sk);
+      launch_reduce(tb, nb, w.Pvv[k], w.Ot1, w.Ot2, p.no, p.nv, sk);
     }
     HIPCHK(hipEventRecord(rn.ev_red[k], sk));
   }
@@ -354,9 +369,9 @@ int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, c
   launch_fill(w.Ot1, (int64_t)no * nv, 0.0, st);
   launch_fill(w.Ot2, (int64_t)no * no * nv * nv, 0.0, st);
   launch_fill(w.OtT, (int64_t)no * no * nv * nv, 0.0, st);
-  launch_triple_table(w.tri, no, st);
+  launch_triple_table(w.tri, no, nbatches(p), st);
   std::vector<int> ht;
-  host_triples(no, ht);
+  host_triples(no, nbatches(p), ht);
   int rc = triple_loop(rn, pf, p, w, eps, t2, w.tri, ht.data(), p.ntri, st);
   if (rc) return rc;
   {
@@ -380,9 +395,9 @@ int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws&
     launch_fill(zv, (int64_t)nv * nv * nv * no, 0.0, st);
     launch_fill(zo, (int64_t)nv * no * no * no, 0.0, st);
   }
-  launch_triple_table(w.tri, no, st);
+  launch_triple_table(w.tri, no, nbatches(p), st);
   std::vector<int> ht, kinds;
-  host_triples(no, ht);
+  host_triples(no, nbatches(p), ht);
   launch_t2N(t2, w.t2N, no, nv, st);
   if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, no, nv, w.lp, st);
   HIPCHK(hipEventRecord(rn.ev_fork, st));

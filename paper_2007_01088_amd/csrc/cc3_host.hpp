@@ -28,7 +28,7 @@ int check_sizes(int no, int nv, int nchol, int prec);
 int check_dev_ptr(const void* p, const char* what);
 
 // ---- kernel timing ------------------------------------------------------------
-enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_REDUCE, FAM_BACK, FAM_ZPREP, NFAM };
+enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_REDUCE, FAM_BACK, FAM_ZPREP, FAM_OMEGA_OO, NFAM };
 extern const char* kFamilies[NFAM];
 
 struct TimedLaunch {
@@ -79,7 +79,7 @@ struct Ws {
   Blocks b;
   CholeskyScratch cs;
   double *Ot1, *Ot2, *OtT, *t2N;
-  double *cubes[2], *Pvv[2], *Soo[2];
+  double *cubes[2], *Pvv[2];
   int* tri;
   int* flag;
   LpOperands lp;

@@ -7,28 +7,36 @@
 
 namespace cc3 {
 
+// Most triples per batch of the triple loop.  A batch holds at most two
+// (triple, permutation) pairs per triple with a given first occupied index, so
+// the per-p pair lists of the kernels hold 2 * MAX_BATCH entries.
+constexpr int MAX_BATCH = 160;
+
 // Device-resident, internally laid out integral blocks (all float64):
 //   Gw[r][y][z][d] = g_{ydzr}         (vv|vo), the W contraction operand (d fastest)
 //   Go[q][r][z][l] = g_{lqzr}         (oo|vo) (l fastest)
-//   Gv[r][b][d][c] = g_{dbrc}         (vv|ov), the Omega contraction operand
+//   Gbc[r][n][b][c] = g_{nbrc} for n < nv (vv|ov), g_{lbrc} for n = nv + l (ov|ov):
+//                     the Omega contraction operand, K = (b, c) contiguous
+//   Gcb[r][n][c][b] = the same values with K = (c, b) contiguous
 //   Jo[q][r][b][c] = g_{qbrc}         (ov|ov)
-//   Hs[q][r][l][c] = delta_{lq} F_rc - g_{qlrc}   (oo|ov) and the Fock ov block
+//   Hs[q][r][c][l] = delta_{lq} F_rc - g_{qlrc}   (oo|ov) and the Fock ov block (l fastest)
 //   F[k][c]
 struct Blocks {
   double* Gw;
   double* Go;
-  double* Gv;
+  double* Gbc;
+  double* Gcb;
   double* Jo;
   double* Hs;
   double* F;
 };
 
 // Intermediates of the T1 transformation (Cholesky form only):
-//   Lvv[J][b][d] = Lt_{bd}, LvvT[J][d][b] = Lt_{bd}, Loo[J][q][l] = Lt_{ql},
+//   Lvv[J][b][d] = Lt_{bd}, Loo[J][q][l] = Lt_{ql},
 //   LooT[J][l][q] = Lt_{ql}, LvoT[J][k][c] = Lt_{ck}, Lov[J][k][c] = L_{kc},
 //   s[J], M[J][k][l]: partial sums of the Fock ov block.
 struct CholeskyScratch {
-  double *Lvv, *LvvT, *Loo, *LooT, *LvoT, *Lov, *s, *M;
+  double *Lvv, *Loo, *LooT, *LvoT, *Lov, *s, *M;
 };
 
 struct Plan {
@@ -36,13 +44,13 @@ struct Plan {
   unsigned flags;
   int ntri;     // unordered triples i >= j >= k, not all equal
   int batch;    // triples per batch of the triple loop
-  size_t pvv_entries;  // max (triples x b-chunks) of one Omega launch
+  size_t pvv_entries;  // max (triples x chunks) of one Omega or Zo launch
   size_t cube;  // doubles per nv^3 cube
   // byte offsets into the workspace
   size_t off_blocks;  // integral blocks (when the workspace holds them)
-  size_t off_Ot1, off_Ot2, off_OtT, off_lp, off_t2N, off_Pvv, off_Soo, off_tri, off_flag, off_cubes;
+  size_t off_Ot1, off_Ot2, off_OtT, off_lp, off_t2N, off_Pvv, off_tri, off_flag, off_cubes;
   size_t off_chol;  // Cholesky scratch (aliases the cube region)
-  size_t chol_bytes, cube_bytes, pvv_bytes, soo_bytes;  // per buffer set (two sets)
+  size_t chol_bytes, cube_bytes, pvv_bytes;  // per buffer set (two sets)
   size_t total;
 };
 
@@ -70,7 +78,8 @@ void launch_build_blocks(const CholeskyScratch& cs, const Blocks& b, int no, int
 void launch_relayout_blocks(const double* g_vvvo, const double* g_oovo, const double* g_ovov,
                             const double* g_ooov, const double* g_vvov, const double* F_ov,
                             const Blocks& b, int no, int nv, hipStream_t st);
-void launch_triple_table(int* tri, int no, hipStream_t st);
+// The full triple table, the restricted loop dealt round-robin over nbatch batches.
+void launch_triple_table(int* tri, int no, int nbatch, hipStream_t st);
 void launch_t2N(const double* t2, double* t2N, int no, int nv, hipStream_t st);
 void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
                    double* cubes, int no, int nv, bool all_terms, hipStream_t st);
@@ -78,16 +87,22 @@ void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, int 
                 hipStream_t st);
 void launch_tau_export(const double* eps, const int* tri, const double* cubes, double* tau, int no,
                        int nv, hipStream_t st);
-// Omega contraction of a batch into per-(triple, permutation) partial slabs Pvv
-// and Soo; then their fixed-order reduction into Ot1/Ot2/OtT (added, not overwritten).
+// Omega contraction of a batch: the vv term and Omega1 into per-(triple,
+// permutation, chunk) partial slabs Pvv, then their fixed-order reduction into
+// Ot1/Ot2 (added, not overwritten); the oo and Fock terms added into OtT
+// (output-stationary).  The reduction and the OtT update of successive batches
+// must run in batch order.
 void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pvv,
-                  double* Soo, int no, int nv, hipStream_t st);
-void launch_reduce(const int* tri, int ntri, const double* Pvv, const double* Soo, double* Ot1,
-                   double* Ot2, double* OtT, int no, int nv, hipStream_t st);
+                  int no, int nv, hipStream_t st);
+void launch_reduce(const int* tri, int ntri, const double* Pvv, double* Ot1, double* Ot2, int no,
+                   int nv, hipStream_t st);
+void launch_omega_oo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* OtT,
+                     int no, int nv, hipStream_t st);
 // Ot~2[p][q][a][b] = Ot2[p][q][a][b] + OtT[p][q][b][a]  (contravariant doubles residual)
 void launch_combine(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
                     double* O2, int no, int nv, hipStream_t st);
-int omega_nbchunks(int nv, int ntri);
+int omega_kchunks(int nv, int ntri);  // K chunks of one Omega GEMM
+int zo_nbchunks(int nv, int ntri);    // b chunks of one Zo product
 void launch_back_transform(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
                            double* O2, int no, int nv, bool accumulate, hipStream_t st);
 void launch_set_triples(int* tri_dev, const int* host_tri, int n, hipStream_t st);
@@ -106,5 +121,6 @@ double zprep_flops(int no, int nv, const int* host_types, int n);
 // Algorithmic FLOP of one launch of the two dominant kernels (padding excluded).
 double wbuild_flops(int no, int nv, const int* host_types, int n);
 double omega_flops(int no, int nv, const int* host_types, int n);
+double omega_oo_flops(int no, int nv, const int* host_types, int n);
 
 }  // namespace cc3

@@ -42,7 +42,7 @@ void launch_add(double* y, const double* x, int64_t n, hipStream_t st) {
 //   Lt_ck = L_ck + sum_d L_cd t1[k][d] - sum_l t1[l][c] Lt_lk      Lt_kc = L_kc
 // ---------------------------------------------------------------------------
 __global__ void k_t1_vv(const double* __restrict__ L, const double* __restrict__ t1,
-                        double* __restrict__ Lvv, double* __restrict__ LvvT, int no, int nv) {
+                        double* __restrict__ Lvv, int no, int nv) {
   const int J = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)nv * nv) return;
@@ -53,7 +53,6 @@ __global__ void k_t1_vv(const double* __restrict__ L, const double* __restrict__
   for (int l = 0; l < no; ++l) v -= t1[(int64_t)l * nv + b] * LJ[(int64_t)l * nmo + no + d];
   const int64_t base = (int64_t)J * nv * nv;
   Lvv[base + (int64_t)b * nv + d] = v;
-  LvvT[base + (int64_t)d * nv + b] = v;
 }
 
 __global__ void k_t1_oo(const double* __restrict__ L, const double* __restrict__ t1,
@@ -95,7 +94,7 @@ __global__ void k_t1_vo(const double* __restrict__ L, const double* __restrict__
 void launch_t1_transform(const double* L, const double* t1, const CholeskyScratch& cs, int no,
                          int nv, int nJ, hipStream_t st) {
   hipLaunchKernelGGL(k_t1_vv, dim3(nblk((int64_t)nv * nv, 256), nJ), dim3(256), 0, st, L, t1,
-                     cs.Lvv, cs.LvvT, no, nv);
+                     cs.Lvv, no, nv);
   int m = no * no > no * nv ? no * no : no * nv;
   hipLaunchKernelGGL(k_t1_oo, dim3(nblk(m, 256), nJ), dim3(256), 0, st, L, t1, cs.Loo, cs.LooT,
                      cs.Lov, no, nv);
@@ -212,9 +211,9 @@ __global__ __launch_bounds__(BuildCfg::NT, 2) void k_build(
         } else if (kind == BUILD_JO) {  // m = q*nv + b, n = r*nv + c -> Jo[q][r][b][c]
           const int q = m / nv, b = m % nv, rr = n / nv, c = n % nv;
           Cz[(((int64_t)q * no + rr) * nv + b) * nv + c] = v;
-        } else if (kind == BUILD_HS) {  // m = q*no + l, n = r*nv + c -> Hs[q][r][l][c]
+        } else if (kind == BUILD_HS) {  // m = q*no + l, n = r*nv + c -> Hs[q][r][c][l]
           const int q = m / no, l = m % no, rr = n / nv, c = n % nv;
-          Cz[(((int64_t)q * no + rr) * no + l) * nv + c] = (l == q ? F[(int64_t)rr * nv + c] : 0.0) - v;
+          Cz[(((int64_t)q * no + rr) * nv + c) * no + l] = (l == q ? F[(int64_t)rr * nv + c] : 0.0) - v;
         } else if (kind == BUILD_GO) {  // m = q*no + l, n = r*nv + z -> Go[q][r][z][l]
           const int q = m / no, l = m % no, rr = n / nv, c = n % nv;
           Cz[(((int64_t)q * no + rr) * nv + c) * no + l] = v;
@@ -235,19 +234,53 @@ static void build(const double* A, int64_t a_sm, int64_t a_sk, int64_t a_bs, con
                      b_sk, b_sn, b_bs, M, N, K, C, c_bs, kind, no, nv, F);
 }
 
+// Gcb[r][n][c][b] = Gbc[r][n][b][c]: nv x nv transposes, one per (r, n), through
+// padded 32 x 32 LDS tiles.
+__global__ __launch_bounds__(256) void k_gcb(const double* __restrict__ Gbc,
+                                             double* __restrict__ Gcb, int nv) {
+  __shared__ double t[32][33];
+  const int tn = (nv + 31) / 32;
+  const int64_t slab = blockIdx.x / (tn * tn);  // r * (nv + no) + n
+  const int tile = blockIdx.x % (tn * tn);
+  const int b0 = (tile / tn) * 32, c0 = (tile % tn) * 32;
+  const int64_t nv2 = (int64_t)nv * nv;
+  const double* src = Gbc + slab * nv2;
+  double* dst = Gcb + slab * nv2;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int b = b0 + y, c = c0 + tx;
+    if (b < nv && c < nv) t[y][tx] = src[(int64_t)b * nv + c];
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int c = c0 + y, b = b0 + tx;
+    if (b < nv && c < nv) dst[(int64_t)c * nv + b] = t[tx][y];
+  }
+}
+
+static void launch_gcb(const Blocks& bl, int no, int nv, hipStream_t st) {
+  const unsigned t = nblk(nv, 32);
+  hipLaunchKernelGGL(k_gcb, dim3(t * t * no * (nv + no)), dim3(256), 0, st, bl.Gbc, bl.Gcb, nv);
+}
+
 void launch_build_blocks(const CholeskyScratch& cs, const Blocks& bl, int no, int nv, int nJ,
                          hipStream_t st) {
   const int64_t nv2 = (int64_t)nv * nv, nv3 = nv2 * nv, onv = (int64_t)no * nv;
+  const int64_t gs = (int64_t)(nv + no) * nv2;  // one r slab of Gbc / Gcb
   // Gw[r][y][z][d] = sum_J LvoT[J][r][z] Lvv[J][(y,d)]   (rows z, columns (y,d), batch r)
   build(cs.LvoT, 1, onv, nv, cs.Lvv, nv2, 1, 0, nv, (int)nv2, nJ, bl.Gw, nv3, no, BUILD_GW, no,
         nv, nullptr, st);
-  // Gv[r][(b,d)][c] = sum_J LvvT[J][(b,d)] Lov[J][r][c]
-  build(cs.LvvT, 1, nv2, 0, cs.Lov, onv, 1, nv, (int)nv2, nv, nJ, bl.Gv, nv3, no, BUILD_PLAIN, no,
+  // Gbc[r][(d,b)][c] = sum_J Lvv[J][(d,b)] Lov[J][r][c]            (rows n = d < nv)
+  build(cs.Lvv, 1, nv2, 0, cs.Lov, onv, 1, nv, (int)nv2, nv, nJ, bl.Gbc, gs, no, BUILD_PLAIN, no,
         nv, nullptr, st);
+  // Gbc[r][nv + (l,b)][c] = sum_J Lov[J][(l,b)] Lov[J][r][c]      (rows n = nv + l)
+  build(cs.Lov, 1, onv, 0, cs.Lov, onv, 1, nv, (int)onv, nv, nJ, bl.Gbc + nv3, gs, no,
+        BUILD_PLAIN, no, nv, nullptr, st);
+  launch_gcb(bl, no, nv, st);
   // Jo[q][r][b][c] = sum_J Lov[J][q][b] Lov[J][r][c]
   build(cs.Lov, 1, onv, 0, cs.Lov, onv, 1, 0, (int)onv, (int)onv, nJ, bl.Jo, 0, 1, BUILD_JO, no,
         nv, nullptr, st);
-  // Hs[q][r][l][c] = delta_lq F[r][c] - sum_J Loo[J][q][l] Lov[J][r][c]
+  // Hs[q][r][c][l] = delta_lq F[r][c] - sum_J Loo[J][q][l] Lov[J][r][c]
   build(cs.Loo, 1, (int64_t)no * no, 0, cs.Lov, onv, 1, 0, no * no, (int)onv, nJ, bl.Hs, 0, 1,
         BUILD_HS, no, nv, bl.F, st);
   // Go[q][r][z][l] = sum_J LooT[J][q][l] LvoT[J][r][z]   (LooT[J][q][l] = Lt_lq)
@@ -259,7 +292,7 @@ void launch_build_blocks(const CholeskyScratch& cs, const Blocks& bl, int no, in
 // Integral blocks given in the paper's index order -> internal layouts.
 // ---------------------------------------------------------------------------
 __global__ void k_relayout_vv(const double* __restrict__ g_vvvo, const double* __restrict__ g_vvov,
-                              double* __restrict__ Gw, double* __restrict__ Gv, int no, int nv) {
+                              double* __restrict__ Gw, double* __restrict__ Gbc, int no, int nv) {
   // output index (r, y, d, z) of an nv^3 slab; z fastest
   const int64_t nv3 = (int64_t)nv * nv * nv;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,25 +301,29 @@ __global__ void k_relayout_vv(const double* __restrict__ g_vvvo, const double* _
   const int y = (int)(e / ((int64_t)nv * nv)), d = (int)((e / nv) % nv), z = (int)(e % nv);
   // Gw[r][y][u][w] = g_vvvo[y][w][u][r]  (u = d, w = z: the contracted index w fastest)
   Gw[(int64_t)r * nv3 + e] = g_vvvo[(((int64_t)y * nv + z) * nv + d) * no + r];
-  // Gv[r][b=y][d][c=z] = g_vvov[d][b][r][c]
-  Gv[(int64_t)r * nv3 + e] = g_vvov[(((int64_t)d * nv + y) * no + r) * nv + z];
+  // Gbc[r][n=y][b=d][c=z] = g_vvov[n][b][r][c]
+  Gbc[(int64_t)r * (nv + no) * nv * nv + e] = g_vvov[(((int64_t)y * nv + d) * no + r) * nv + z];
 }
 
 __global__ void k_relayout_small(const double* __restrict__ g_oovo, const double* __restrict__ g_ovov,
                                  const double* __restrict__ g_ooov, const double* __restrict__ F_ov,
                                  double* __restrict__ Go, double* __restrict__ Jo,
-                                 double* __restrict__ Hs, double* __restrict__ F, int no, int nv) {
+                                 double* __restrict__ Gbc, double* __restrict__ Hs,
+                                 double* __restrict__ F, int no, int nv) {
   const int q = blockIdx.y / no, r = blockIdx.y % no;
+  const int64_t nv2 = (int64_t)nv * nv;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nv * nv; e += gridDim.x * blockDim.x) {
-    const int b = e / nv, c = e % nv;  // Jo[q][r][b][c] = g_ovov[q][b][r][c]
-    Jo[(((int64_t)q * no + r) * nv + b) * nv + c] = g_ovov[(((int64_t)q * nv + b) * no + r) * nv + c];
+    const int b = e / nv, c = e % nv;  // Jo[q][r][b][c] = Gbc[r][nv + q][b][c] = g_ovov[q][b][r][c]
+    const double g = g_ovov[(((int64_t)q * nv + b) * no + r) * nv + c];
+    Jo[((int64_t)q * no + r) * nv2 + e] = g;
+    Gbc[((int64_t)r * (nv + no) + nv + q) * nv2 + e] = g;
   }
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < no * nv; e += gridDim.x * blockDim.x) {
     const int l = e / nv, c = e % nv;
     // Go[q][r][z][l] = g_oovo[l][q][z][r]
     Go[(((int64_t)q * no + r) * nv + c) * no + l] = g_oovo[(((int64_t)l * no + q) * nv + c) * no + r];
-    // Hs[q][r][l][c] = delta_lq F[r][c] - g_ooov[q][l][r][c]
-    Hs[(((int64_t)q * no + r) * no + l) * nv + c] =
+    // Hs[q][r][c][l] = delta_lq F[r][c] - g_ooov[q][l][r][c]
+    Hs[(((int64_t)q * no + r) * nv + c) * no + l] =
         (l == q ? F_ov[(int64_t)r * nv + c] : 0.0) - g_ooov[(((int64_t)q * no + l) * no + r) * nv + c];
   }
   if (blockIdx.y == 0)
@@ -299,30 +336,39 @@ void launch_relayout_blocks(const double* g_vvvo, const double* g_oovo, const do
                             const Blocks& b, int no, int nv, hipStream_t st) {
   const int64_t nv3 = (int64_t)nv * nv * nv;
   hipLaunchKernelGGL(k_relayout_vv, dim3(nblk(nv3, 256), no), dim3(256), 0, st, g_vvvo, g_vvov,
-                     b.Gw, b.Gv, no, nv);
+                     b.Gw, b.Gbc, no, nv);
   unsigned gx = nblk((int64_t)nv * nv, 256);
   if (gx > 64) gx = 64;
   hipLaunchKernelGGL(k_relayout_small, dim3(gx, no * no), dim3(256), 0, st, g_oovo, g_ovov,
-                     g_ooov, F_ov, b.Go, b.Jo, b.Hs, b.F, no, nv);
+                     g_ooov, F_ov, b.Go, b.Jo, b.Gbc, b.Hs, b.F, no, nv);
+  launch_gcb(b, no, nv, st);
 }
 
 // ---------------------------------------------------------------------------
-// Triple table: the restricted loop i >= j >= k in lexicographic order without
-// the i == j == k triples; rank = C(i+2,3) + j(j+1)/2 + k - i.
+// Triple table: the restricted loop i >= j >= k without the i == j == k triples,
+// lexicographic rank L = C(i+2,3) + j(j+1)/2 + k - i, dealt round-robin over the
+// nbatch batches: position = start of group L mod nbatch + L / nbatch.  Each
+// batch then samples the whole loop, so that the (triple, permutation) pairs of
+// a batch spread evenly over the first occupied index, which the
+// output-stationary kernels are parallel over.
 // ---------------------------------------------------------------------------
-__global__ void k_triples(int* __restrict__ tri, int no) {
+__global__ void k_triples(int* __restrict__ tri, int no, int nbatch) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= no * no * no) return;
   const int i = e / (no * no), j = (e / no) % no, k = e % no;
   if (!(i >= j && j >= k) || (i == j && j == k)) return;
-  const int rank = i * (i + 1) * (i + 2) / 6 + j * (j + 1) / 2 + k - i;
-  tri[3 * rank + 0] = i;
-  tri[3 * rank + 1] = j;
-  tri[3 * rank + 2] = k;
+  const int n = no * (no + 1) * (no + 2) / 6 - no;
+  const int L = i * (i + 1) * (i + 2) / 6 + j * (j + 1) / 2 + k - i;
+  const int g = L % nbatch;
+  const int pos = g * (n / nbatch) + min(g, n % nbatch) + L / nbatch;
+  tri[3 * pos + 0] = i;
+  tri[3 * pos + 1] = j;
+  tri[3 * pos + 2] = k;
 }
 
-void launch_triple_table(int* tri, int no, hipStream_t st) {
-  hipLaunchKernelGGL(k_triples, dim3(nblk((int64_t)no * no * no, 256)), dim3(256), 0, st, tri, no);
+void launch_triple_table(int* tri, int no, int nbatch, hipStream_t st) {
+  hipLaunchKernelGGL(k_triples, dim3(nblk((int64_t)no * no * no, 256)), dim3(256), 0, st, tri, no,
+                     nbatch < 1 ? 1 : nbatch);
 }
 
 void launch_set_triples(int* tri_dev, const int* host_tri, int n, hipStream_t st) {

@@ -16,15 +16,14 @@
 //            tau~ = 4 tau^{abc} - 2 tau^{acb} - 2 tau^{cba} - 2 tau^{bac} + tau^{bca} + tau^{cab},
 //            written as tau~[a][b][c] and its transpose tau~T[a][c][b].
 //  k_omega   (FP64 MFMA)  for each distinct occupied permutation (p,q,r), with
-//            U = tau~_{pqr} read from tau~ or tau~T, one GEMM over K = (b, c):
+//            U = tau~_{pqr} read from tau~ or tau~T, one long-K GEMM over K = (b, c):
 //              Ot2[p][q][a][d] += sum_bc U[a,b,c] g_{dbrc}    (columns d < nv)
 //              Ot1[p][a]       += sum_bc U[a,b,c] g_{qbrc}    (column nv)
-//              Ot2[p][l][a][b] += sum_c  U[a,b,c] (delta_lq F_rc - g_{qlrc})  (separate
-//                                 accumulator blocks, stored after every b)
-//            written as per-(triple, permutation) partial slabs with plain stores;
-//            the last term is kept transposed, OtT[p][l][b][a], so that its
-//            stores run along a;
-//  k_reduce  adds the slabs into Ot1/Ot2/OtT in a fixed order (deterministic, no atomics).
+//            split over K into per-(triple, permutation, chunk) partial slabs;
+//  k_reduce  adds the slabs into Ot1/Ot2 in a fixed order (deterministic, no atomics);
+//  k_omega_oo (FP64 MFMA, output-stationary)  the oo and Fock terms
+//              Ot2[p][l][a][b] += sum_c U[a,b,c] (delta_lq F_rc - g_{qlrc}),
+//            kept transposed, OtT[p][l][b][a], so that its stores run along a.
 #include "cc3_device.hpp"
 #include "cc3_internal.hpp"
 
@@ -438,197 +437,138 @@ void launch_tau_export(const double* eps, const int* tri, const double* cubes, d
 }
 
 // ---------------------------------------------------------------------------
-// Omega contraction
+// Omega contraction: the vv term and Omega1
 // ---------------------------------------------------------------------------
-// One (triple, permutation) GEMM over K = (b, c), rows a:
-//   vv columns d < nv          : Ot2[p][q][a][d] += sum_bc U[a,b,c] Gv[r][b][d][c]
-// and a second, transposed product (rows l, columns a) owned by the first N tile:
-//   rows l < no                : Ot2[p][l][a][b] += sum_c U[a,b,c] Hs[q][r][l][c]
-//                                (complete after each b, stored as SooT[z][pi][l][b][a])
-//   row l == no                : Ot1[p][a] += sum_bc U[a,b,c] Jo[q][r][b][c]
-//                                (summed over the chunk's b in registers)
-// Partial results: Pvv[z][pi][chunk][a][n] (n < nv: d columns, n == nv: Omega1),
-// SooT[z][pi][l][b][a].
-// 128 x 128 vv tile, 16 wavefronts of 32 x 32: at most 128 VGPRs, so four
-// wavefronts share each SIMD.  32 k per LDS stage where two stages fit the
-// LDS (oo rows up to 48), else 16.
-template <int BK>
-using OCfgK = TileCfg<4, 4, 2, 2, BK>;
-typedef OCfgK<16> OCfg;  // tile geometry (independent of BK)
-template <int FNO>
-struct OmegaBK {
-  static constexpr int BK = FNO <= 3 ? 32 : 16;
-};
+// One (triple, permutation) GEMM over the flattened K = (b, c), K = nv^2:
+//   columns n < nv : Ot2[p][q][a][n] += sum_bc U[a,b,c] g_{nbrc}
+//   column  n = nv : Ot1[p][a]       += sum_bc U[a,b,c] g_{qbrc}
+// Both column kinds are rows of one block G[r][n'][.][.] (n' < nv: g_{n'brc};
+// n' = nv + l: g_{lbrc}), stored once with K in (b, c) order (Gbc) and once in
+// (c, b) order (Gcb).  Each of the six views U_pi of the contravariant cubes
+// (TT[x][y][z] = tau~[x][y][z], TTT[x][y][z] = tau~[x][z][y]) is affine in K in
+// one of the two orders:
+//   pi 0: tau~[a][b][c] = TT[a][(b,c)]      k contiguous, row stride nv^2
+//   pi 3: tau~[a][c][b] = TTT[a][(b,c)]
+//   pi 1: tau~[b][a][c] = TTT[(b,c)][a]     a contiguous, k stride nv
+//   pi 5: tau~[b][c][a] = TT[(b,c)][a]
+//   pi 2: tau~[c][b][a] = TT[(c,b)][a]      the same, K in (c, b) order
+//   pi 4: tau~[c][a][b] = TTT[(c,b)][a]
+// so every permutation is a plain long-K GEMM.  K is split into chunks of whole
+// LDS stages; each chunk writes a partial slab Pvv[z][pi][chunk][a][n] (n <= nv)
+// that k_reduce sums in a fixed order.  128 x 128 tiles on 8 wavefronts of
+// 32 x 64, 16 k per LDS stage, two workgroups per CU.
+typedef TileCfg<4, 2, 2, 4, 16> OCfg;
 
-// The oo product (rows l, columns a) is split over the wavefronts in 16 x 16
-// blocks: wavefront (wm, wn) takes column block am = 2 wm + (wn & 1) -- one of
-// the two a blocks whose A fragments it already holds for the vv product --
-// and row blocks f = (wn >> 1) + 2 j < FNO.
-template <int FNO>
-struct OoSplit {
-  static constexpr int NF = (FNO + 1) / 2;  // row blocks per wavefront (upper bound)
-};
-
-template <int FNO>
-__global__ __launch_bounds__(OCfg::NT) void k_omega(
-    const double* __restrict__ cubes, const double* __restrict__ Gv, const double* __restrict__ Jo,
-    const double* __restrict__ Hs, const int* __restrict__ tri, double* __restrict__ Pvv,
-    double* __restrict__ Soo, int no, int nv, int nbchunks, int tiles_n) {
-  typedef OCfgK<OmegaBK<FNO>::BK> T;
-  constexpr int BO = 16 * FNO;  // oo rows per tile (no of them used, plus the Omega1 row)
-  constexpr int EO = (BO * T::BK + T::NT - 1) / T::NT;
-  constexpr int NF = OoSplit<FNO>::NF;
-  constexpr int STAGE = T::BK * (T::LDA + T::LDB + BO);
-  __shared__ double lds[2 * STAGE];
-  const int pi = blockIdx.y;
-  const int z = blockIdx.z;
+__global__ __launch_bounds__(OCfg::NT) void k_omega(const double* __restrict__ cubes,
+                                                    const double* __restrict__ Gbc,
+                                                    const double* __restrict__ Gcb,
+                                                    const int* __restrict__ tri,
+                                                    double* __restrict__ Pvv, int no, int nv,
+                                                    int nchunks, int tiles_n) {
+  typedef OCfg T;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int pi = blockIdx.y, z = blockIdx.z;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
-  const int kind = tri_kind(i, j, k);
-  if (!perm_active(kind, pi)) return;
+  if (!perm_active(tri_kind(i, j, k), pi)) return;
   int p, q, r;
   perm_pqr(pi, i, j, k, p, q, r);
-  const int bc = blockIdx.x % nbchunks;
-  const int tile = blockIdx.x / nbchunks;
+  const int ch = blockIdx.x % nchunks, tile = blockIdx.x / nchunks;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
-  const bool do_oo = (tile % tiles_n) == 0;
-  // balanced b chunks [bb0, bb1); nbchunks <= nv, so none is empty
-  const int bb0 = (int)((int64_t)bc * nv / nbchunks);
-  const int bb1 = (int)((int64_t)(bc + 1) * nv / nbchunks);
-  if (bb0 >= bb1) return;
-
   const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
-  const int NV1 = nv + 1;
-  const double* cz = cubes + (int64_t)z * NSLOT * nv3;
-  // U_pi[a, b, c] at fixed b as a strided (a, c) view: base + b * sbb, (sm, sk)
-  int slot, sbb, sm, sk;
-  switch (pi) {
-    case 0: slot = SLOT_TT; sbb = nv; sm = nv * nv; sk = 1; break;    // tau~[a][b][c]
-    case 1: slot = SLOT_TT; sbb = nv * nv; sm = nv; sk = 1; break;    // tau~[b][a][c]
-    case 2: slot = SLOT_TT; sbb = nv; sm = 1; sk = nv * nv; break;    // tau~[c][b][a]
-    case 3: slot = SLOT_TTT; sbb = nv; sm = nv * nv; sk = 1; break;   // tau~[a][c][b] = tau~T[a][b][c]
-    case 4: slot = SLOT_TTT; sbb = nv; sm = 1; sk = nv * nv; break;   // tau~[c][a][b] = tau~T[c][b][a]
-    default: slot = SLOT_TT; sbb = nv * nv; sm = 1; sk = nv; break;   // tau~[b][c][a]
-  }
-  const double* ub = cz + slot * nv3;
-  const bool afast = (sm == 1);
-  const int cs = (nv + T::BK - 1) / T::BK;  // c steps per b
-  const int nsteps = (bb1 - bb0) * cs;
-  const double* Gr = Gv + (int64_t)r * nv3;
-  const double* Jqr = Jo + ((int64_t)q * no + r) * nv2;
-  const double* Hqr = Hs + ((int64_t)q * no + r) * no * nvl;
+  const int K = nv * nv;
+  const int S = (K + T::BK - 1) / T::BK;
+  const int s0 = (int)((int64_t)ch * S / nchunks), s1 = (int)((int64_t)(ch + 1) * S / nchunks);
+  if (s0 >= s1) return;  // nchunks <= S, so never taken
+  const bool cb = (pi == 2 || pi == 4);
+  const bool amaj = !(pi == 0 || pi == 3);  // a contiguous, k stride nv
+  const int slot = (pi == 1 || pi == 3 || pi == 4) ? SLOT_TTT : SLOT_TT;
+  const double* U = cubes + ((int64_t)z * NSLOT + slot) * nv3;
+  const double* G = (cb ? Gcb : Gbc) + (int64_t)r * (nv + no) * nv2;
+  const int ask = amaj ? nv : 1;  // k stride of A in doubles
+  // tile origins (k = 0) of the two operands
+  const double* A0 = amaj ? U + m0 : U + (int64_t)m0 * K;
+  const double* B0 = G + (int64_t)n0 * K;
 
+  // Per-thread part of every stage.  A: element e at (row/column x_e, k_e) of the
+  // stage, global byte offset aoff[e] + k_e * ask * 8 from the stage origin
+  // A0 + k0 * ask, LDS slot alds[e].  Rows past nv repeat row nv - 1 (their outputs
+  // are never stored).  B rows n < nv are G rows n; rows n >= nv (only in the last
+  // column tile) read the Omega1 row nv + q.  Offsets are relative to the tile
+  // origin: below 191 rows of stride nv^2 <= 2^20, so below 2^31 bytes.
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave % T::WM, wn = wave / T::WM;
-  const int am = wm * T::FM + (wn & 1);  // this wavefront's oo column block
-  const int f0 = wn >> 1;                // and its first oo row block
-  d4v acc[T::FM][T::FN];
-  d4v aco[NF];  // oo rows l = (f0 + 2 t) * 16 + lane/16 + 4 r, columns a = m0 + am * 16 + lane%16
-  zero_acc<T>(acc);
+  constexpr int RP = T::NT / T::BK;  // k-fast mapping: 32 rows per element step
+  constexpr int KP = T::NT / T::BM;  // a-fast mapping: 4 k per element step
+  unsigned aoff[T::EA], boff[T::EB];
+  int ak[T::EA], alds[T::EA], blds[T::EB];
+  const int kt = tid % T::BK, xt = tid / T::BK;
+  if (amaj) {
+    const int x = tid % T::BM, k0t = tid / T::BM;
+    const unsigned xc = (unsigned)(min(m0 + x, nv - 1) - m0);
 #pragma unroll
-  for (int t = 0; t < NF; ++t) aco[t] = d4v{0.0, 0.0, 0.0, 0.0};
-  double om1 = 0.0;  // Omega1 partial of column a (lanes holding row l == no)
-  double ra[T::EA], rb[T::EB], ro[EO];
-  // vv operands: A = U_pi[a, b, c] (rows a, k = c) at fixed b, B = Gv[r][b][d][c] (rows d)
-  StageLoader<T::BM, T::BK, T::EA, T::NT> la;
-  StageLoader<T::BN, T::BK, T::EB, T::NT> lb;
-  la.init(make_opnd(ub, sm, sk, nv, nv, afast), m0, tid);
-  lb.init(make_opnd(Gr, nv, 1, nv, nv, false), n0, tid);
-  // oo rows: thread -> (c = k_t, l = x_t + e * NT/BK), the same mapping store_stage uses;
-  // rows l < no come from Hs, row no from Jo (at the stage's b), rows beyond read as 0
-  const int ok_t = tid % T::BK, ox_t = tid / T::BK;
-  constexpr int ODX = T::NT / T::BK;
-
-  // position of the next stage to load (b, c0) and of the stage being computed
-  int ld_b = bb0, ld_c0 = 0;
-  auto load = [&]() {
-    const int b = ld_b, c0 = ld_c0;
-    la.load(make_opnd(ub + (int64_t)b * sbb, sm, sk, nv, nv, afast), m0, c0, ra);
-    lb.load(make_opnd(Gr + (int64_t)b * nv2, nv, 1, nv, nv, false), n0, c0, rb);
-    if (do_oo) {
-      const int c = c0 + ok_t;
-      const int cc = min(c, nv - 1);
-      const double* jrow = Jqr + (int64_t)b * nvl;
-#pragma unroll
-      for (int e = 0; e < EO; ++e) {
-        const int l = ox_t + e * ODX;
-        const double* row = (l < no) ? Hqr + (int64_t)l * nvl : jrow;
-        const bool in = (e * T::NT + tid) < BO * T::BK && c < nv && l <= no;
-        const double v = row[cc];
-        ro[e] = in ? v : 0.0;
-      }
+    for (int e = 0; e < T::EA; ++e) {
+      ak[e] = k0t + e * KP;
+      aoff[e] = xc * 8u;
+      alds[e] = lds_idx<T::BK>(ak[e], x, T::LDA);
     }
-    ld_c0 += T::BK;
-    if (ld_c0 >= nv) { ld_c0 = 0; ++ld_b; }
+  } else {
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) {
+      ak[e] = kt;
+      aoff[e] = (unsigned)(min(m0 + xt + e * RP, nv - 1) - m0) * (unsigned)K * 8u;
+      alds[e] = lds_idx<T::BK>(kt, xt + e * RP, T::LDA);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < T::EB; ++e) {
+    const int n = n0 + xt + e * RP;
+    boff[e] = (unsigned)((n < nv ? n : nv + q) - n0) * (unsigned)K * 8u;
+    blds[e] = T::BK * T::LDA + lds_idx<T::BK>(kt, xt + e * RP, T::LDB);
+  }
+  const unsigned ask8 = (unsigned)ask * 8u;
+  double ra[T::EA], rb[T::EB];
+  auto fetch = [&](int s) {
+    const int k0 = s * T::BK;
+    const BufRsrc sa = buf_rsrc(A0 + (int64_t)k0 * ask), sb = buf_rsrc(B0 + k0);
+    const int kl = K - 1 - k0;  // last valid k of this stage (only the last stage is partial)
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) {
+      const bool in = ak[e] <= kl;
+      const int kc = in ? ak[e] : kl;
+      const double v = buf_load_f64(sa, aoff[e] + (unsigned)kc * ask8);
+      ra[e] = in ? v : 0.0;
+    }
+    const bool inb = kt <= kl;
+    const unsigned kb = (unsigned)(inb ? kt : kl) * 8u;
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) {
+      const double v = buf_load_f64(sb, boff[e] + kb);
+      rb[e] = inb ? v : 0.0;
+    }
   };
   auto store = [&](double* st) {
-    store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(afast, ra, st, tid);
-    store_stage<T::BN, T::BK, T::EB, T::NT, T::LDB>(false, rb, st + T::BK * T::LDA, tid);
-    if (do_oo) store_stage<BO, T::BK, EO, T::NT, BO>(false, ro, st + T::BK * (T::LDA + T::LDB), tid);
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) st[alds[e]] = ra[e];
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) st[blds[e]] = rb[e];
   };
-
-  double* soo = Soo + ((int64_t)z * 6 + pi) * no * nv2;
-  load();
+  d4v acc[T::FM][T::FN];
+  zero_acc<T>(acc);
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % T::WM, wn = wave / T::WM;
+  fetch(s0);
   store(lds);
   __syncthreads();
-  int cp_b = bb0, cp_cs = 0;  // stage being computed: b and its c step
-  for (int s = 0; s < nsteps; ++s) {
-    double* cur = lds + (s & 1) * STAGE;
-    double* nxt = lds + ((s + 1) & 1) * STAGE;
-    const bool more = (s + 1 < nsteps);
-    if (more) load();
-    const double* so = cur + T::BK * (T::LDA + T::LDB);
-#pragma unroll
-    for (int kk = 0; kk < T::BK / 4; ++kk) {
-      const int kr = kk * 4 + (lane >> 4);
-      const int sw = (lane & 15) ^ lds_swz<T::BK>(kr);
-      double a[T::FM], bf[T::FN];
-#pragma unroll
-      for (int fm = 0; fm < T::FM; ++fm) a[fm] = cur[kr * T::LDA + (wm * T::FM + fm) * 16 + sw];
-#pragma unroll
-      for (int fn = 0; fn < T::FN; ++fn)
-        bf[fn] = cur[T::BK * T::LDA + kr * T::LDB + (wn * T::FN + fn) * 16 + sw];
-#pragma unroll
-      for (int fm = 0; fm < T::FM; ++fm)
-#pragma unroll
-        for (int fn = 0; fn < T::FN; ++fn)
-          acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fm], bf[fn], acc[fm][fn], 0, 0, 0);
-      if (do_oo) {  // uniform per workgroup
-#pragma unroll
-        for (int t = 0; t < NF; ++t) {
-          const int f = f0 + 2 * t;
-          if (f < FNO) {
-            const double bo = so[kr * BO + f * 16 + sw];
-            aco[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(bo, (wn & 1) ? a[1] : a[0], aco[t], 0, 0, 0);
-          }
-        }
-      }
-    }
-    if (++cp_cs == cs) {  // b complete
-      if (do_oo) {  // SooT[l][b][a] = aco(l, a); row no -> Omega1
-        const int a = m0 + am * 16 + (lane & 15);
-#pragma unroll
-        for (int t = 0; t < NF; ++t) {
-          const int f = f0 + 2 * t;
-          if (f < FNO) {
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-              const int l = f * 16 + (lane >> 4) + 4 * rr;
-              if (a < nv && l < no) soo[((int64_t)l * nvl + cp_b) * nvl + a] = aco[t][rr];
-              if (l == no) om1 += aco[t][rr];
-            }
-          }
-          aco[t] = d4v{0.0, 0.0, 0.0, 0.0};
-        }
-      }
-      cp_cs = 0;
-      ++cp_b;
-    }
+  for (int s = s0; s < s1; ++s) {
+    double* cur = lds + ((s - s0) & 1) * T::STAGE;
+    double* nxt = lds + ((s - s0 + 1) & 1) * T::STAGE;
+    const bool more = s + 1 < s1;
+    if (more) fetch(s + 1);
+    mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
     if (more) store(nxt);
     __syncthreads();
   }
-  double* pvv = Pvv + (((int64_t)z * 6 + pi) * nbchunks + bc) * nvl * NV1;
-  // d columns of this chunk
+  const int NV1 = nv + 1;
+  double* pvv = Pvv + (((int64_t)z * 6 + pi) * nchunks + ch) * nvl * NV1;
 #pragma unroll
   for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
@@ -637,92 +577,33 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(
       for (int rr = 0; rr < 4; ++rr) {
         const int a = m0 + acc_row<T>(wm, fm, lane, rr);
         const int n = n0 + acc_col<T>(wn, fn, lane);
-        if (a < nv && n < nv) pvv[(int64_t)a * NV1 + n] = acc[fm][fn][rr];
+        if (a < nv && n <= nv) pvv[(int64_t)a * NV1 + n] = acc[fm][fn][rr];
       }
-  if (do_oo) {  // Omega1 column, held by the lanes whose oo row is l == no
-    const int a = m0 + am * 16 + (lane & 15);
-    bool mine = false;
-#pragma unroll
-    for (int t = 0; t < NF; ++t) {
-      const int f = f0 + 2 * t;
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) mine |= (f < FNO) && (f * 16 + (lane >> 4) + 4 * rr == no);
-    }
-    if (mine && a < nv) pvv[(int64_t)a * NV1 + nv] = om1;
-  }
 }
 
-// For output block (p, x):
-//   Ot2[p][x][a][d] += sum of Pvv[z][pi][chunk][a][d] over the batch's (triple,
-//                      permutation) pairs with that p and q == x, and chunks;
-//   OtT[p][x][b][a] += sum of SooT[z][pi][x][b][a] over the pairs with that p;
-//   Ot1[p][a]       += column nv of Pvv (block x == 0).
-// Fixed summation order: triple, permutation, chunk.
-#define REDUCE_MAXL 1024
-__global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int ntri,
-                                                const double* __restrict__ Pvv,
-                                                const double* __restrict__ SooT,
-                                                double* __restrict__ Ot1, double* __restrict__ Ot2,
-                                                double* __restrict__ OtT, int no, int nv,
-                                                int nbchunks) {
-  __shared__ int lz[REDUCE_MAXL];  // (z * 6 + pi) of the pairs with this p, in order
-  __shared__ int lq[REDUCE_MAXL];
-  __shared__ int cnt;
-  const int p = blockIdx.z, x = blockIdx.y;
-  if (threadIdx.x == 0) {
-    int n = 0;
-    for (int z = 0; z < ntri; ++z) {
-      const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
-      const int kind = tri_kind(i, j, k);
-      for (int pi = 0; pi < 6; ++pi) {
-        if (!perm_active(kind, pi)) continue;
-        int pp, q, r;
-        perm_pqr(pi, i, j, k, pp, q, r);
-        if (pp == p && n < REDUCE_MAXL) { lz[n] = z * 6 + pi; lq[n] = q; ++n; }
+// The (triple, permutation) pairs of a batch whose first occupied index is p, in
+// batch order: at most two per triple, so at most 2 * MAX_BATCH.
+#define PLIST_MAX (2 * MAX_BATCH)
+__device__ inline int pairs_with_p(const int* __restrict__ tri, int ntri, int p, int no, int* lz,
+                                   int* lqr) {
+  int n = 0;
+  for (int z = 0; z < ntri; ++z) {
+    const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+    const int kind = tri_kind(i, j, k);
+    for (int pi = 0; pi < 6; ++pi) {
+      if (!perm_active(kind, pi)) continue;
+      int pp, q, r;
+      perm_pqr(pi, i, j, k, pp, q, r);
+      if (pp == p && n < PLIST_MAX) {
+        lz[n] = z * 6 + pi;
+        if (lqr) lqr[n] = q * no + r;
+        ++n;
       }
     }
-    cnt = n;
   }
-  __syncthreads();
-  const int64_t nvl = nv, nv2 = nvl * nvl;
-  const int NV1 = nv + 1;
-  const int64_t pvs = (int64_t)nvl * NV1;  // one chunk slab
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool o2 = e < nv2;
-  const bool o1 = (x == 0) && e < nv;  // Omega1 element a = e
-  if (!o2 && !o1) return;
-  const int a = (int)(e / nvl), d = (int)(e % nvl);
-  const int n = cnt;
-  double s2 = 0.0, st = 0.0, s1 = 0.0;
-  if (o2) {
-#pragma unroll 4
-    for (int t = 0; t < n; ++t) st += SooT[((int64_t)lz[t] * no + x) * nv2 + e];
-    for (int t = 0; t < n; ++t) {
-      if (lq[t] != x) continue;
-      const double* pv = Pvv + (int64_t)lz[t] * nbchunks * pvs + (int64_t)a * NV1 + d;
-#pragma unroll 4
-      for (int c = 0; c < nbchunks; ++c) s2 += pv[c * pvs];
-    }
-    Ot2[((int64_t)p * no + x) * nv2 + e] += s2;
-    OtT[((int64_t)p * no + x) * nv2 + e] += st;
-  }
-  if (o1) {
-    for (int t = 0; t < n; ++t) {
-      const double* pv = Pvv + (int64_t)lz[t] * nbchunks * pvs + (int64_t)e * NV1 + nv;
-      for (int c = 0; c < nbchunks; ++c) s1 += pv[c * pvs];
-    }
-    Ot1[(int64_t)p * nvl + e] += s1;
-  }
+  return n;
 }
 
-// Number of b chunks the Omega GEMM of one (triple, permutation) is split into:
-// enough workgroups for 256 CUs at two per CU, no more.
-// ---------------------------------------------------------------------------
-// Preparation for the Jacobian transformations (Algorithm 2): for each distinct
-// occupied permutation (p,q,r) of a triple, with U = tau~_{pqr},
-//   Zv[a][b][p][d] -= sum_c    U[a,b,c] g_{qdrc}     (g_{qdrc} = Jo[q][r][d][c])
-//   Zo[a][q][p][l] += sum_{bc} U[a,b,c] g_{lbrc}     (g_{lbrc} = Jo[l][r][b][c])
-// ---------------------------------------------------------------------------
 // The view of U_pi[a, b, c] at fixed b as a strided (a, c) matrix: base + b * sbb, (sm, sk).
 __device__ inline void u_view(int pi, int nv, int& slot, int& sbb, int& sm, int& sk) {
   switch (pi) {
@@ -735,7 +616,161 @@ __device__ inline void u_view(int pi, int nv, int& slot, int& sbb, int& sm, int&
   }
 }
 
-#define ZLIST_MAX 160  // pairs of one batch with a given p (at most six per triple)
+// ---------------------------------------------------------------------------
+// Omega contraction: the oo and Fock terms, output-stationary
+// ---------------------------------------------------------------------------
+// One workgroup of 4 wavefronts per (p, pair of b, 64-wide tile of a) sums, over
+// the batch's pairs with that p in batch order,
+//   OtT[p][l][b][a] += sum_c Hs[q][r][c][l] U[a,b,c]      (l < no)
+// (Hs[q][r][c][l] = delta_lq F_rc - g_{qlrc}) and adds the sum into OtT
+// (read-modify-write; successive batches are ordered by the caller).  Wavefront w
+// owns the 16 columns a0 = tile + 16 w of both b and every row l (FNO blocks of
+// 16), as D[l][a] of the FP64 MFMA with A = Hs, B = U.  The kernel streams U once
+// per pair and is bound by HBM latency, so nothing is staged in LDS and there
+// are no barriers in the loop: each lane loads its operands in the MFMA layout
+// directly, the next step's loads in flight during the current step's MFMAs,
+// and the Hs fragments serve both b.  Within a 16-c step, lane group
+// kq = lane / 16 feeds c = c0 + 4 kq + t to MFMA t (the same order on both
+// operands, which leaves the sum unchanged).
+template <int FNO>
+__global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cubes,
+                                                  const double* __restrict__ Hs,
+                                                  const int* __restrict__ tri, int ntri,
+                                                  double* __restrict__ OtT, int no, int nv,
+                                                  int tiles_a) {
+  constexpr int NB = 2;
+  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
+  __shared__ int cnt;
+  const int p = blockIdx.y;
+  const int bp = blockIdx.x / tiles_a;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int a0 = (blockIdx.x % tiles_a) * 64 + 16 * wave;
+  if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
+  __syncthreads();
+  const int n = cnt;
+  if (n == 0 || a0 >= nv) return;  // no barrier follows
+  const int m = lane & 15, kq = lane >> 4;
+  const int a = min(a0 + m, nv - 1);
+  int bb[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) bb[j] = min(NB * bp + j, nv - 1);
+  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
+  d4v acc[NB][FNO];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int f = 0; f < FNO; ++f) acc[j][f] = d4v{0.0, 0.0, 0.0, 0.0};
+  // flattened (pair, 16-c step) loop with the next step's loads issued before
+  // the current step's MFMAs
+  const int cs = (nv + 15) / 16;
+  const int nit = n * cs;
+  double u[2][NB][4], h[2][FNO][4];
+  auto load = [&](int it, double (&uu)[NB][4], double (&hh)[FNO][4]) {
+    const int t = it / cs, c0 = (it - t * cs) * 16;
+    const int zp = lz[t], zz = zp / 6, pi = zp % 6;
+    int slot, sbb, sm, sk;
+    u_view(pi, nv, slot, sbb, sm, sk);
+    const double* ua = cubes + ((int64_t)zz * NSLOT + slot) * nv3 + (int64_t)a * sm;
+    const double* hb = Hs + (int64_t)lqr[t] * no * nvl;
+    const int cb = c0 + 4 * kq;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const int c = cb + tt;
+      const int cc = min(c, nv - 1);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const double v = ua[(int64_t)bb[j] * sbb + (int64_t)cc * sk];
+        uu[j][tt] = c < nv ? v : 0.0;
+      }
+#pragma unroll
+      for (int f = 0; f < FNO; ++f) {
+        const int l = min(16 * f + m, no - 1);
+        hh[f][tt] = hb[(int64_t)cc * no + l];
+      }
+    }
+  };
+  auto mma = [&](const double (&uu)[NB][4], const double (&hh)[FNO][4]) {
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int f = 0; f < FNO; ++f)
+          acc[j][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(hh[f][tt], uu[j][tt], acc[j][f], 0, 0, 0);
+  };
+  load(0, u[0], h[0]);
+  for (int it = 0; it < nit; it += 2) {
+    if (it + 1 < nit) load(it + 1, u[1], h[1]);
+    mma(u[0], h[0]);
+    if (it + 1 < nit) {
+      if (it + 2 < nit) load(it + 2, u[0], h[0]);
+      mma(u[1], h[1]);
+    }
+  }
+  const int ac = a0 + m;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int b = NB * bp + j;
+#pragma unroll
+    for (int f = 0; f < FNO; ++f)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int l = 16 * f + kq + 4 * rr;
+        if (l < no && ac < nv && b < nv)
+          OtT[(((int64_t)p * no + l) * nvl + b) * nvl + ac] += acc[j][f][rr];
+      }
+  }
+}
+
+// For output block (p, x):
+//   Ot2[p][x][a][d] += sum of Pvv[z][pi][chunk][a][d] over the batch's (triple,
+//                      permutation) pairs with that p and q == x, and chunks;
+//   Ot1[p][a]       += column nv of Pvv (block x == 0).
+// Fixed summation order: triple, permutation, chunk.
+__global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int ntri,
+                                                const double* __restrict__ Pvv,
+                                                double* __restrict__ Ot1, double* __restrict__ Ot2,
+                                                int no, int nv, int nchunks) {
+  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
+  __shared__ int cnt;
+  const int p = blockIdx.z, x = blockIdx.y;
+  if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
+  __syncthreads();
+  const int64_t nvl = nv, nv2 = nvl * nvl;
+  const int NV1 = nv + 1;
+  const int64_t pvs = (int64_t)nvl * NV1;  // one chunk slab
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool o2 = e < nv2;
+  const bool o1 = (x == 0) && e < nv;  // Omega1 element a = e
+  if (!o2 && !o1) return;
+  const int a = (int)(e / nvl), d = (int)(e % nvl);
+  const int n = cnt;
+  if (o2) {
+    double s2 = 0.0;
+    for (int t = 0; t < n; ++t) {
+      if (lqr[t] / no != x) continue;
+      const double* pv = Pvv + (int64_t)lz[t] * nchunks * pvs + (int64_t)a * NV1 + d;
+#pragma unroll 4
+      for (int c = 0; c < nchunks; ++c) s2 += pv[c * pvs];
+    }
+    Ot2[((int64_t)p * no + x) * nv2 + e] += s2;
+  }
+  if (o1) {
+    double s1 = 0.0;
+    for (int t = 0; t < n; ++t) {
+      const double* pv = Pvv + (int64_t)lz[t] * nchunks * pvs + (int64_t)e * NV1 + nv;
+      for (int c = 0; c < nchunks; ++c) s1 += pv[c * pvs];
+    }
+    Ot1[(int64_t)p * nvl + e] += s1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Preparation for the Jacobian transformations (Algorithm 2): for each distinct
+// occupied permutation (p,q,r) of a triple, with U = tau~_{pqr},
+//   Zv[a][b][p][d] -= sum_c    U[a,b,c] g_{qdrc}     (g_{qdrc} = Jo[q][r][d][c])
+//   Zo[a][q][p][l] += sum_{bc} U[a,b,c] g_{lbrc}     (g_{lbrc} = Jo[l][r][b][c])
+// ---------------------------------------------------------------------------
 
 // Zv, output-stationary: one workgroup per (p, b, 128 x 128 tile of (a, d)) sums the
 // batch's (triple, permutation) pairs with that p, in batch order, over c, and
@@ -749,26 +784,13 @@ __global__ __launch_bounds__(ZvCfg::NT) void k_zv(const double* __restrict__ cub
                                                   int tiles_m, int tiles_n) {
   typedef ZvCfg T;
   __shared__ double lds[T::LDS_DOUBLES];
-  __shared__ int lz[ZLIST_MAX], lqr[ZLIST_MAX];
+  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
   __shared__ int cnt;
   const int p = blockIdx.y;
   const int tpp = tiles_m * tiles_n;
   const int b = blockIdx.x / tpp, tile = blockIdx.x % tpp;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
-  if (threadIdx.x == 0) {
-    int n = 0;
-    for (int z = 0; z < ntri; ++z) {
-      const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
-      const int kind = tri_kind(i, j, k);
-      for (int pi = 0; pi < 6; ++pi) {
-        if (!perm_active(kind, pi)) continue;
-        int pp, q, r;
-        perm_pqr(pi, i, j, k, pp, q, r);
-        if (pp == p && n < ZLIST_MAX) { lz[n] = z * 6 + pi; lqr[n] = q * no + r; ++n; }
-      }
-    }
-    cnt = n;
-  }
+  if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
   __syncthreads();
   const int n = cnt;
   if (n == 0) return;
@@ -856,23 +878,10 @@ __global__ __launch_bounds__(256) void k_zo_reduce(const int* __restrict__ tri, 
                                                    const double* __restrict__ Pzo,
                                                    double* __restrict__ Zo, int no, int nv,
                                                    int nbchunks) {
-  __shared__ int lz[ZLIST_MAX];
+  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
   __shared__ int cnt;
   const int q = blockIdx.y, p = blockIdx.z;
-  if (threadIdx.x == 0) {
-    int n = 0;
-    for (int z = 0; z < ntri; ++z) {
-      const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
-      const int kind = tri_kind(i, j, k);
-      for (int pi = 0; pi < 6; ++pi) {
-        if (!perm_active(kind, pi)) continue;
-        int pp, qq, r;
-        perm_pqr(pi, i, j, k, pp, qq, r);
-        if (pp == p && qq == q && n < ZLIST_MAX) lz[n++] = z * 6 + pi;
-      }
-    }
-    cnt = n;
-  }
+  if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
   __syncthreads();
   const int n = cnt;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -881,6 +890,7 @@ __global__ __launch_bounds__(256) void k_zo_reduce(const int* __restrict__ tri, 
   const int64_t slab = (int64_t)nv * no;
   double s = 0.0;
   for (int t = 0; t < n; ++t) {
+    if (lqr[t] / no != q) continue;
     const double* pz = Pzo + (int64_t)lz[t] * nbchunks * slab + e;
     for (int c = 0; c < nbchunks; ++c) s += pz[c * slab];
   }
@@ -898,7 +908,7 @@ void launch_zv(const double* cubes, const Blocks& b, const int* tri, int ntri, d
 void launch_zo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pzo,
                double* Zo, int no, int nv, hipStream_t st, bool reduce) {
   typedef ZoCfg T;
-  const int nbc = omega_nbchunks(nv, ntri);
+  const int nbc = zo_nbchunks(nv, ntri);
   if (!reduce) {
     const int tm = (nv + T::BM - 1) / T::BM;
     hipLaunchKernelGGL(k_zo, dim3(nbc * tm, 6, ntri), dim3(T::NT), 0, st, cubes, b.Jo, tri, Pzo,
@@ -916,48 +926,70 @@ double zprep_flops(int no, int nv, const int* kinds, int n) {
   return perms * (2.0 * v * v * v * v + 2.0 * v * v * v * o);
 }
 
-// Split-K chunks of the b index per (triple, permutation, tile): enough
-// workgroups for several rounds over the chip (two resident per CU), as a
-// multiple of 8 so that the tiles of one (triple, permutation, chunk) -- which
-// share their A or B operand rows -- are dispatched to the same XCD (workgroups
-// go round-robin over the 8 XCDs in linear order, and tiles of one chunk are
-// nbchunks apart) and meet in its L2.
-int omega_nbchunks(int nv, int ntri) {
-  static const int target = [] {
-    const char* e = getenv("CC3_OMEGA_WG");
-    const int v = e ? atoi(e) : 0;
-    return v > 0 ? v : 2048;
-  }();
-  const int tm = (nv + OCfg::BM - 1) / OCfg::BM, tn = (nv + OCfg::BN - 1) / OCfg::BN;
-  const int per = 6 * tm * tn * (ntri > 0 ? ntri : 1);
-  int nbc = (target + per - 1) / per;
+// Split-K chunks of the b index of the Zo partials per (triple, permutation, a
+// tile): about 2048 workgroups per launch, as a multiple of 8 beyond 8.
+int zo_nbchunks(int nv, int ntri) {
+  const int t = (nv + 127) / 128;
+  const int per = 6 * t * t * (ntri > 0 ? ntri : 1);
+  int nbc = (2048 + per - 1) / per;
   if (nbc > 8) nbc = (nbc + 7) / 8 * 8;
   if (nbc > nv) nbc = nv;
   return nbc < 1 ? 1 : nbc;
 }
 
-void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pvv,
-                  double* Soo, int no, int nv, hipStream_t st) {
+// K chunks (runs of whole LDS stages) of the Omega GEMM of one (triple,
+// permutation, tile): enough workgroups for several rounds over the chip (two
+// resident per CU), as a multiple of 8 beyond 8 so that the tiles of one
+// (triple, permutation, chunk) -- which share operand rows -- are dispatched to
+// the same XCD (workgroups go round-robin over the 8 XCDs in linear order, and
+// tiles of one chunk are nchunks apart) and meet in its L2; at least 16 stages
+// per chunk.
+int omega_kchunks(int nv, int ntri) {
+  static const int target = [] {
+    const char* e = getenv("CC3_OMEGA_WG");
+    const int v = e ? atoi(e) : 0;
+    return v > 0 ? v : 2048;
+  }();
   typedef OCfg T;
-  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + T::BN - 1) / T::BN;
-  const int nbc = omega_nbchunks(nv, ntri);
-  const dim3 grid(nbc * tm * tn, 6, ntri), block(T::NT);
-  if (no + 1 <= 16)
-    hipLaunchKernelGGL(k_omega<1>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, nbc, tn);
-  else if (no + 1 <= 32)
-    hipLaunchKernelGGL(k_omega<2>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, nbc, tn);
-  else if (no + 1 <= 48)
-    hipLaunchKernelGGL(k_omega<3>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, nbc, tn);
-  else
-    hipLaunchKernelGGL(k_omega<4>, grid, block, 0, st, cubes, b.Gv, b.Jo, b.Hs, tri, Pvv, Soo, no, nv, nbc, tn);
+  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + 1 + T::BN - 1) / T::BN;
+  const int per = 6 * tm * tn * (ntri > 0 ? ntri : 1);
+  int nch = (target + per - 1) / per;
+  if (nch > 8) nch = (nch + 7) / 8 * 8;
+  const int S = (nv * nv + T::BK - 1) / T::BK;
+  const int cap = S / 16 > 1 ? S / 16 : 1;
+  if (nch > cap) nch = cap;
+  return nch < 1 ? 1 : nch;
 }
 
-void launch_reduce(const int* tri, int ntri, const double* Pvv, const double* Soo, double* Ot1,
-                   double* Ot2, double* OtT, int no, int nv, hipStream_t st) {
-  const int nbc = omega_nbchunks(nv, ntri);
+void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pvv,
+                  int no, int nv, hipStream_t st) {
+  typedef OCfg T;
+  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + 1 + T::BN - 1) / T::BN;
+  const int nch = omega_kchunks(nv, ntri);
+  hipLaunchKernelGGL(k_omega, dim3(nch * tm * tn, 6, ntri), dim3(T::NT), 0, st, cubes, b.Gbc,
+                     b.Gcb, tri, Pvv, no, nv, nch, tn);
+}
+
+void launch_omega_oo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* OtT,
+                     int no, int nv, hipStream_t st) {
+  const int ta = (nv + 63) / 64;
+  const dim3 grid(((nv + 1) / 2) * ta, no), block(256);
+  if (no <= 16)
+    hipLaunchKernelGGL(k_omega_oo<1>, grid, block, 0, st, cubes, b.Hs, tri, ntri, OtT, no, nv, ta);
+  else if (no <= 32)
+    hipLaunchKernelGGL(k_omega_oo<2>, grid, block, 0, st, cubes, b.Hs, tri, ntri, OtT, no, nv, ta);
+  else if (no <= 48)
+    hipLaunchKernelGGL(k_omega_oo<3>, grid, block, 0, st, cubes, b.Hs, tri, ntri, OtT, no, nv, ta);
+  else
+    hipLaunchKernelGGL(k_omega_oo<4>, grid, block, 0, st, cubes, b.Hs, tri, ntri, OtT, no, nv, ta);
+}
+
+void launch_reduce(const int* tri, int ntri, const double* Pvv, double* Ot1, double* Ot2, int no,
+                   int nv, hipStream_t st) {
+  const int nch = omega_kchunks(nv, ntri);
   const int64_t nv2 = (int64_t)nv * nv;
-  hipLaunchKernelGGL(k_reduce, dim3(nblk(nv2, 256), no, no), dim3(256), 0, st, tri, ntri, Pvv, Soo,
-                     Ot1, Ot2, OtT, no, nv, nbc);
+  hipLaunchKernelGGL(k_reduce, dim3(nblk(nv2, 256), no, no), dim3(256), 0, st, tri, ntri, Pvv, Ot1,
+                     Ot2, no, nv, nch);
 }
 
 // FLOP of the dominant contractions and their companions, padding excluded.
@@ -969,11 +1001,21 @@ double wbuild_flops(int no, int nv, const int* kinds, int n) {
   return f;
 }
 
+// k_omega: the vv term (2 nv^4) and Omega1 (2 nv^3) per permutation
 double omega_flops(int no, int nv, const int* kinds, int n) {
-  const double v = nv, o = no;
-  const double perm = 2.0 * v * v * v * v + 2.0 * v * v * v + 2.0 * v * v * v * (o + 1.0);
+  const double v = nv;
+  const double perm = 2.0 * v * v * v * v + 2.0 * v * v * v;
   double f = 0.0;
   for (int t = 0; t < n; ++t) f += (kinds[t] == TRI_DISTINCT ? 6.0 : 3.0) * perm;
+  (void)no;
+  return f;
+}
+
+// k_omega_oo: the oo and Fock terms (2 nv^3 no) per permutation
+double omega_oo_flops(int no, int nv, const int* kinds, int n) {
+  const double v = nv, o = no;
+  double f = 0.0;
+  for (int t = 0; t < n; ++t) f += (kinds[t] == TRI_DISTINCT ? 6.0 : 3.0) * 2.0 * v * v * v * o;
   return f;
 }
 

@@ -52,8 +52,11 @@ def close(name, got, ref, tol=TOL):
 
 
 @pytest.mark.parametrize("no,nv,nJ,t1z", [(4, 20, 60, False), (4, 20, 60, True), (3, 9, 12, False),
-                                          (5, 37, 50, False), (6, 130, 40, False)])
+                                          (5, 37, 50, False), (6, 130, 40, False),
+                                          (16, 16, 40, False)])
 def test_jacobian_prep_parity(ctx, no, nv, nJ, t1z):
+    """(16, 16): batches of 160 triples in which one occupied index heads up to 255
+    (triple, permutation) pairs, beyond half the per-index list bound."""
     torch = _torch()
     say(f"jacobian prep no={no} nv={nv} nJ={nJ} t1_zero={t1z}")
     d = make_inputs(no, nv, nJ, t1_zero=t1z)

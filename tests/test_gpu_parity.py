@@ -54,7 +54,8 @@ def assert_close(name, got, ref):
 
 
 @pytest.mark.parametrize("no,nv,nJ,t1z", [(4, 20, 60, False), (4, 20, 60, True), (3, 9, 12, False),
-                                          (5, 37, 50, False), (6, 130, 40, False)])
+                                          (5, 37, 50, False), (6, 130, 40, False),
+                                          (16, 16, 40, False)])
 def test_full_residual_parity(ctx, no, nv, nJ, t1z):
     """Whole call from Cholesky vectors; sizes cover one and two 128-wide tiles and ragged
     8-blocks (nv = 9, 37, 130)."""
