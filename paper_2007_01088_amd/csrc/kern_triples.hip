@@ -626,12 +626,14 @@ __device__ inline void u_view(int pi, int nv, int& slot, int& sbb, int& sm, int&
 // (read-modify-write; successive batches are ordered by the caller).  Wavefront w
 // owns the 16 columns a0 = tile + 16 w of both b and every row l (FNO blocks of
 // 16), as D[l][a] of the FP64 MFMA with A = Hs, B = U.  The kernel streams U once
-// per pair and is bound by HBM latency, so nothing is staged in LDS and there
-// are no barriers in the loop: each lane loads its operands in the MFMA layout
-// directly, the next step's loads in flight during the current step's MFMAs,
-// and the Hs fragments serve both b.  Within a 16-c step, lane group
-// kq = lane / 16 feeds c = c0 + 4 kq + t to MFMA t (the same order on both
-// operands, which leaves the sum unchanged).
+// per pair and is bound by the memory pipeline, so there are no workgroup
+// barriers in the loop: the next step's loads are in flight during the current
+// step's MFMAs, and the Hs fragments serve both b.  Within a 16-c step, lane
+// group kq = lane / 16 feeds c = c0 + 4 kq + t to MFMA t (the same order on both
+// operands, which leaves the sum unchanged).  Views with a contiguous are loaded
+// in the MFMA layout directly (16 consecutive a per row of c); views with c
+// contiguous are loaded along c (4 rows of 16 consecutive c per instruction) and
+// transposed through a wavefront-private LDS tile.
 template <int FNO>
 __global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cubes,
                                                   const double* __restrict__ Hs,
@@ -641,6 +643,7 @@ __global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cub
   constexpr int NB = 2;
   __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
   __shared__ int cnt;
+  __shared__ double lt[4][NB][16][17];  // per wavefront: 16 rows a x 16 c (+1 pad)
   const int p = blockIdx.y;
   const int bp = blockIdx.x / tiles_a;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -648,9 +651,8 @@ __global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cub
   if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
   __syncthreads();
   const int n = cnt;
-  if (n == 0 || a0 >= nv) return;  // no barrier follows
+  if (n == 0 || a0 >= nv) return;  // no workgroup barrier follows
   const int m = lane & 15, kq = lane >> 4;
-  const int a = min(a0 + m, nv - 1);
   int bb[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) bb[j] = min(NB * bp + j, nv - 1);
@@ -665,46 +667,81 @@ __global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cub
   const int cs = (nv + 15) / 16;
   const int nit = n * cs;
   double u[2][NB][4], h[2][FNO][4];
-  auto load = [&](int it, double (&uu)[NB][4], double (&hh)[FNO][4]) {
+  bool cc1[2];
+  auto load = [&](int it, double (&uu)[NB][4], double (&hh)[FNO][4], bool& ccont) {
     const int t = it / cs, c0 = (it - t * cs) * 16;
     const int zp = lz[t], zz = zp / 6, pi = zp % 6;
     int slot, sbb, sm, sk;
     u_view(pi, nv, slot, sbb, sm, sk);
-    const double* ua = cubes + ((int64_t)zz * NSLOT + slot) * nv3 + (int64_t)a * sm;
-    const double* hb = Hs + (int64_t)lqr[t] * no * nvl;
-    const int cb = c0 + 4 * kq;
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const int c = cb + tt;
+    const double* ub = cubes + ((int64_t)zz * NSLOT + slot) * nv3;
+    ccont = (sk == 1);
+    if (ccont) {  // element i: row a0 + 4 i + kq, c = c0 + m
+      const int c = c0 + m;
       const int cc = min(c, nv - 1);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const double v = ua[(int64_t)bb[j] * sbb + (int64_t)cc * sk];
-        uu[j][tt] = c < nv ? v : 0.0;
-      }
+      for (int i = 0; i < 4; ++i) {
+        const int row = min(a0 + 4 * i + kq, nv - 1);
 #pragma unroll
-      for (int f = 0; f < FNO; ++f) {
-        const int l = min(16 * f + m, no - 1);
-        hh[f][tt] = hb[(int64_t)cc * no + l];
+        for (int j = 0; j < NB; ++j) {
+          const double v = ub[(int64_t)row * sm + (int64_t)bb[j] * sbb + cc];
+          uu[j][i] = c < nv ? v : 0.0;
+        }
+      }
+    } else {  // element tt: row a0 + m, c = c0 + 4 kq + tt
+      const int64_t ra = (int64_t)min(a0 + m, nv - 1);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        const int c = c0 + 4 * kq + tt;
+        const int cc = min(c, nv - 1);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const double v = ub[ra + (int64_t)bb[j] * sbb + (int64_t)cc * sk];
+          uu[j][tt] = c < nv ? v : 0.0;
+        }
       }
     }
+    const double* hb = Hs + (int64_t)lqr[t] * no * nvl;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const int cc = min(c0 + 4 * kq + tt, nv - 1);
+#pragma unroll
+      for (int f = 0; f < FNO; ++f) hh[f][tt] = hb[(int64_t)cc * no + min(16 * f + m, no - 1)];
+    }
   };
-  auto mma = [&](const double (&uu)[NB][4], const double (&hh)[FNO][4]) {
+  auto mma = [&](const double (&uu)[NB][4], const double (&hh)[FNO][4], bool ccont) {
+    double x[NB][4];
+    if (ccont) {  // transpose through this wavefront's LDS tile
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lt[wave][j][4 * i + kq][m] = uu[j][i];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) x[j][tt] = lt[wave][j][m][4 * kq + tt];
+      __builtin_amdgcn_wave_barrier();
+    } else {
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) x[j][tt] = uu[j][tt];
+    }
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
       for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int f = 0; f < FNO; ++f)
-          acc[j][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(hh[f][tt], uu[j][tt], acc[j][f], 0, 0, 0);
+          acc[j][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(hh[f][tt], x[j][tt], acc[j][f], 0, 0, 0);
   };
-  load(0, u[0], h[0]);
+  load(0, u[0], h[0], cc1[0]);
   for (int it = 0; it < nit; it += 2) {
-    if (it + 1 < nit) load(it + 1, u[1], h[1]);
-    mma(u[0], h[0]);
+    if (it + 1 < nit) load(it + 1, u[1], h[1], cc1[1]);
+    mma(u[0], h[0], cc1[0]);
     if (it + 1 < nit) {
-      if (it + 2 < nit) load(it + 2, u[0], h[0]);
-      mma(u[1], h[1]);
+      if (it + 2 < nit) load(it + 2, u[0], h[0], cc1[0]);
+      mma(u[1], h[1], cc1[1]);
     }
   }
   const int ac = a0 + m;
