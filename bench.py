@@ -275,6 +275,9 @@ def main() -> int:
                     help="skip timing the mixed-precision W contractions (FP32, BF16x3, BF16x6)")
     ap.add_argument("--no-jacobian-prep", action="store_true",
                     help="skip timing the Jacobian-preparation intermediates (Algorithm 2)")
+    ap.add_argument("--standalone-steps", type=int, default=3,
+                    help="calls with CC3_ONE_STREAM after the timed region, for kernel durations "
+                         "without batch overlap (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-molecules", type=int, default=16,
@@ -366,6 +369,30 @@ def main() -> int:
     kernels = {k: {"launches": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
                    "share": v["total_ms"] / max(1e-9, sum(x["total_ms"] for x in stats.values()))}
                for k, v in stats.items()}
+    # Two-stream overlap of consecutive batches stretches each launch in the timed
+    # region; the same call with CC3_ONE_STREAM (after it, untimed for `value`) gives
+    # every kernel's duration without a neighbour on the device.
+    standalone = None
+    if args.standalone_steps > 0:
+        ctx.profile_enable(True)
+        for _ in range(args.standalone_steps):
+            ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], o1, o2, flags=cc3.ONE_STREAM)
+        torch.cuda.synchronize()
+        st_s = ctx.profile_get()
+        ctx.profile_enable(False)
+        s_dom = st_s[dom]
+        s_avg = s_dom["total_ms"] / s_dom["launches"]
+        s_ach = (s_dom["flops"] / s_dom["launches"]) / (s_avg * 1e-3) / 1e12
+        standalone = {
+            "steps": args.standalone_steps,
+            "roofline": {"bound": "mfma", "achieved": s_ach, "peak": peak, "unit": "TFLOP/s",
+                         "frac": s_ach / peak, "kernel": dom, "avg_launch_ms": s_avg},
+            "kernels": {k: {"launches": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
+                            "tflops": (v["flops"] / v["total_ms"] * 1e-9) if v["flops"] else None}
+                        for k, v in st_s.items()},
+        }
+        log(f"standalone {dom}: {s_avg:.3f} ms per launch, {s_ach:.1f} TFLOP/s "
+            f"({100 * s_ach / peak:.0f}% of peak)")
     # one sampled parity check of the timed output against nothing else than its own symmetry
     sym = float((o2 - o2.permute(1, 0, 3, 2)).abs().max() / o2.abs().max())
 
@@ -416,6 +443,7 @@ def main() -> int:
                    "nominal_flop_per_call": nominal, "executed_flop_per_call": executed},
         "roofline": roof,
         "kernels": kernels,
+        "standalone": standalone,
         "omega2_pair_symmetry": sym,
     }
     if mixed:

@@ -68,7 +68,11 @@ enum {
 /* flags */
 enum {
   CC3_ACCUMULATE = 1u,    /* add the triples contribution into omega1/omega2 instead of overwriting */
-  CC3_CHECK = 2u          /* verify input symmetries (t2, L) and positive denominators first */
+  CC3_CHECK = 2u,         /* verify input symmetries (t2, L) and positive denominators first */
+  CC3_ONE_STREAM = 4u     /* run the batches of the triple loop one after another on one stream
+                             instead of overlapping consecutive batches on two; the result is
+                             the same, each kernel runs without a neighbour on the device
+                             (standalone timing), the call is slower (one-shot calls only) */
 };
 
 /* ---------------------------------------------------------------------- */

@@ -82,7 +82,7 @@ static int common_checks(cc3_ctx* c, int no, int nv, int nchol, int prec, unsign
   if (!c) return fail(CC3_E_INVAL, "ctx is NULL");
   int rc = check_sizes(no, nv, nchol, prec);
   if (rc) return rc;
-  if (flags & ~(unsigned)(CC3_ACCUMULATE | CC3_CHECK))
+  if (flags & ~(unsigned)(CC3_ACCUMULATE | CC3_CHECK | CC3_ONE_STREAM))
     return fail(CC3_E_INVAL, "unknown flag bits 0x%x", flags);
   make_plan_ex(no, nv, nchol, prec, flags, true, 0, p);
   if (!ws) return fail(CC3_E_INVAL, "workspace is NULL");

@@ -317,8 +317,9 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
   if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, p.no, p.nv, w.lp, st);
   HIPCHK(hipEventRecord(rn.ev_fork, st));
   for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
-  // CC3_SERIAL=1 keeps every batch on one stream (kernel durations without overlap)
-  static const int nstream = env_int("CC3_SERIAL", 0) ? 1 : NSTREAM;
+  // CC3_ONE_STREAM (or CC3_SERIAL=1 in the environment) keeps every batch on one stream
+  static const int env_serial = env_int("CC3_SERIAL", 0);
+  const int nstream = (env_serial || (p.flags & CC3_ONE_STREAM)) ? 1 : NSTREAM;
   int nbatch = 0;
   for (int t0 = 0; t0 < n; t0 += p.batch, ++nbatch) {
     const int nb = std::min(p.batch, n - t0);
@@ -402,7 +403,8 @@ int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws&
   if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, no, nv, w.lp, st);
   HIPCHK(hipEventRecord(rn.ev_fork, st));
   for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
-  static const int nstream = env_int("CC3_SERIAL", 0) ? 1 : NSTREAM;
+  static const int env_serial = env_int("CC3_SERIAL", 0);
+  const int nstream = (env_serial || (p.flags & CC3_ONE_STREAM)) ? 1 : NSTREAM;
   const int n = p.ntri;
   int nbatch = 0;
   for (int t0 = 0; t0 < n; t0 += p.batch, ++nbatch) {

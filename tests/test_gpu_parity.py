@@ -70,6 +70,24 @@ def test_full_residual_parity(ctx, no, nv, nJ, t1z):
     assert_close("Omega2", o2.cpu().numpy(), r2)
 
 
+def test_one_stream_is_bit_identical(ctx):
+    """CC3_ONE_STREAM runs the batches on one stream instead of two; the kernels and the
+    batch-ordered reductions are the same, so the result is identical bit for bit."""
+    torch = _torch()
+    from paper_2007_01088_amd import cc3
+    no, nv, nJ = 9, 40, 60
+    say(f"one stream vs two, no={no} nv={nv}")
+    d = make_inputs(no, nv, nJ)
+    g = dev(torch, d)
+    a1, a2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
+    b1, b2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], flags=cc3.ONE_STREAM)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, b1) and torch.equal(a2, b2)
+    r1, r2 = O.triples_residual(d["eps"], d["L"], d["t1"], d["t2"])
+    assert_close("Omega1", b1.cpu().numpy(), r1)
+    assert_close("Omega2", b2.cpu().numpy(), r2)
+
+
 def test_blocks_form_parity(ctx):
     torch = _torch()
     no, nv, nJ = 5, 21, 30
