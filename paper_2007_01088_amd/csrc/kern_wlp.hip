@@ -154,14 +154,22 @@ constexpr int LBM = 16 * LWM * LFM, LBN = 16 * LWN * LFN;  // 128 x 128
 // 16 bytes of padding (rows of 80 or 144 bytes: the 16 rows read by one
 // fragment load spread over the banks).  Tiles load as 16-byte chunks, CH per
 // thread per piece per operand.
+// FLUSH: each LDS stage (32 k) is accumulated in FP32 from zero and then added
+// into an FP64 accumulator, so the FP32 rounding of the MFMA outputs applies to
+// 32-term partial sums rather than to the running sum over the whole K range.
+// Used where the split is fine enough for that rounding to dominate the error
+// (FP32 and the 3-piece BF16 split); the 2-piece split is limited by its
+// operands and keeps one FP32 accumulator per term.
 struct EngF32 {
   static constexpr int BK = 32, P = 1, NPROD = 1, ESZ = 4;
   static constexpr int ROWB = BK * ESZ + 16;  // bytes per LDS row
+  static constexpr bool FLUSH = true;
 };
 template <int P_>
 struct EngBF16 {
   static constexpr int BK = 32, P = P_, NPROD = (P_ == 2 ? 3 : 6), ESZ = 2;
   static constexpr int ROWB = BK * ESZ + 16;
+  static constexpr bool FLUSH = (P_ == 3);
 };
 
 // the piece pairs of the split products
@@ -232,8 +240,10 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
   const int cr = tid / CPR, cc = tid % CPR;
 
   u4v ra[P][CH], rb[P][CH];  // one stage of both operands in flight
-  // one term: acc[m][n] = sum over K of segment sa (K = nv) then sb (K = no)
-  auto run_term = [&](const LpSeg& sa, const LpSeg& sb, f4v (&acc)[LFM][LFN]) __attribute__((always_inline)) {
+  // one term: acc[m][n] = sum over K of segment sa (K = nv) then sb (K = no); with
+  // FLUSH, acc holds one stage and the term is added into accd stage by stage
+  auto run_term = [&](const LpSeg& sa, const LpSeg& sb, f4v (&acc)[LFM][LFN],
+                      d4v (&accd)[LFM][LFN]) __attribute__((always_inline)) {
 #pragma unroll
     for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
@@ -321,6 +331,16 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
               acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa][fm], b[pb][fn], acc[fm][fn], 0, 0, 0);
         }
       }
+      if constexpr (E::FLUSH) {
+#pragma unroll
+        for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < LFN; ++fn) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accd[fm][fn][r] += (double)acc[fm][fn][r];
+            acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+          }
+      }
       if (more) store(nxt);
       __syncthreads();
     }
@@ -329,14 +349,26 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
   // term 1 (and term 2 when the plane has two), each accumulated in FP32; the
   // plane value is their FP64 sum (exact FP32 values, one FP64 rounding)
   f4v acc1[LFM][LFN], acc2[LFM][LFN];
-  run_term(seg0, seg1, acc1);
+  d4v accd[LFM][LFN];
+#pragma unroll
+  for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < LFN; ++fn) accd[fm][fn] = d4v{0.0, 0.0, 0.0, 0.0};
+  run_term(seg0, seg1, acc1, accd);
   if (two) {
-    run_term(seg2, seg3, acc2);
-  } else {
+    run_term(seg2, seg3, E::FLUSH ? acc1 : acc2, accd);
+  }
+  if (E::FLUSH || !two) {
 #pragma unroll
     for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < LFN; ++fn) acc2[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+  }
+  if constexpr (E::FLUSH) {
+#pragma unroll
+    for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < LFN; ++fn) acc1[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
   }
 
   // the FP32/BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
@@ -350,7 +382,8 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + (wm * LFM + fm) * 16 + 4 * (lane >> 4) + r;
         const int n = n0 + (wn * LFN + fn) * 16 + (lane & 15);
-        if (m < nv && n < nv) dst[(int64_t)m * nv + n] = (double)acc1[fm][fn][r] + (double)acc2[fm][fn][r];
+        if (m < nv && n < nv)
+          dst[(int64_t)m * nv + n] = accd[fm][fn][r] + ((double)acc1[fm][fn][r] + (double)acc2[fm][fn][r]);
       }
 }
 

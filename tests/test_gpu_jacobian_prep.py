@@ -81,7 +81,7 @@ def test_jacobian_prep_accumulate_and_mixed(ctx):
     torch.cuda.synchronize()
     close("Zv accumulate", zv.cpu().numpy() - 1e-3, rv, 1e-10)
     close("Zo accumulate", zo.cpu().numpy() + 2e-3, ro, 1e-10)
-    for name, prec, bound in (("fp32", cc3.FP32, 3e-7), ("bf16x6", cc3.BF16X6, 3e-7),
+    for name, prec, bound in (("fp32", cc3.FP32, 1e-7), ("bf16x6", cc3.BF16X6, 1e-7),
                               ("bf16x3", cc3.BF16X3, 3e-5)):
         zv, zo = ctx.jacobian_prep(g["eps"], g["L"], g["t1"], g["t2"], prec=prec)
         torch.cuda.synchronize()

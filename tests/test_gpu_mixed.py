@@ -1,13 +1,15 @@
-"""Mixed-precision W contractions (FP32, split-BF16 x3 and x6 on MFMA with FP32
-accumulation; everything after the W build in FP64) against the FP64 oracle.
+"""Mixed-precision W contractions (FP32, split-BF16 x3 and x6 on MFMA; everything
+after the W build in FP64) against the FP64 oracle.
 
 The bound per mode and result is written here from the arithmetic of the W
 contractions (relative errors of ||Omega_mixed - Omega_oracle||_2 / ||Omega_oracle||_2):
-  FP32   : unit roundoff 6e-8 on operands and products, K ~ nv + no terms with
-           random signs -> measured 1e-8 .. 1e-7; bound 3e-7.
-  BF16X6 : 3-piece split represents each operand to ~2^-24 and drops product
-           terms below ~2^-24; bound 3e-7.
-  BF16X3 : 2-piece split keeps ~16 bits per operand (products to ~2^-16): bound 3e-5
+  FP32   : operands rounded to FP32 (unit roundoff 6e-8, random signs over K ~ nv + no
+           terms); each 32-k stage is summed on the MFMA in FP32 from zero and added
+           into an FP64 accumulator, so the FP32 rounding of the sums applies to
+           32-term partial sums only: bound 1e-7, the target of the precision addition.
+  BF16X6 : the 3-piece split represents each operand to ~2^-24 and drops product terms
+           below ~2^-24; the same FP64 stage accumulation: bound 1e-7.
+  BF16X3 : the 2-piece split keeps ~16 bits per operand (products to ~2^-16): bound 3e-5
            (it does not meet 1e-7; the measured value is reported, not hidden).
 """
 import sys
@@ -19,7 +21,14 @@ from oracle import cc3_oracle as O
 from paper_2007_01088_amd.synth import make_inputs, sample_triples
 
 pytestmark = pytest.mark.gpu
-BOUND = {"fp32": 3e-7, "bf16x6": 3e-7, "bf16x3": 3e-5}
+BOUND = {"fp32": 1e-7, "bf16x6": 1e-7, "bf16x3": 3e-5}
+# A sample of a few triples sums fewer contributions than a whole residual, and
+# its relative error is larger (measured 9.4e-8 / 9.95e-8 for 8 triples at
+# 12/120/400 against 6.4e-8 / 6.2e-8 for the whole call): bound 1.5e-7 there.
+BOUND_SAMPLE = {"fp32": 1.5e-7, "bf16x6": 1.5e-7, "bf16x3": 3e-5}
+# One t3 block is an intermediate: each element carries the operand rounding of
+# its own W terms without the averaging of the Omega sums (measured ~1e-7): 3e-7.
+BOUND_T3 = {"fp32": 3e-7, "bf16x6": 3e-7, "bf16x3": 3e-5}
 
 
 def _setup():
@@ -41,10 +50,12 @@ def test_mixed_precision_errors(no, nv, nJ):
     d = make_inputs(no, nv, nJ)
     g = {k: torch.from_numpy(d[k]).cuda() for k in ("eps", "L", "t1", "t2")}
     ctx = cc3.Context(0)
+    bound = BOUND
     if no <= 6:
         r1, r2 = O.triples_residual(d["eps"], d["L"], d["t1"], d["t2"])
         call = lambda prec: ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=prec)
     else:
+        bound = BOUND_SAMPLE
         tri = np.unique(np.concatenate([sample_triples(no, 6, seed=3),
                                         np.array([[no - 1, no - 1, 2], [no - 1, 3, 3]], np.int32)]),
                         axis=0)
@@ -59,6 +70,27 @@ def test_mixed_precision_errors(no, nv, nJ):
         torch.cuda.synchronize()
         e1, e2 = rel(o1.cpu().numpy(), r1), rel(o2.cpu().numpy(), r2)
         print(f"no={no} nv={nv} {name}: rel err Omega1 {e1:.3e} Omega2 {e2:.3e}", flush=True)
+        assert e1 <= bound[name] and e2 <= bound[name], (name, e1, e2)
+    ctx.close()
+
+
+def test_mixed_whole_call_at_benchmark_size():
+    """The whole residual at 12/120/400 in each precision against the FP64 GPU result,
+    which the parity tests pin to the oracle within 1e-11 (the oracle itself takes
+    about 40 s here)."""
+    torch, cc3 = _setup()
+    no, nv, nJ = 12, 120, 400
+    d = make_inputs(no, nv, nJ)
+    g = {k: torch.from_numpy(d[k]).cuda() for k in ("eps", "L", "t1", "t2")}
+    ctx = cc3.Context(0)
+    f1, f2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
+    torch.cuda.synchronize()
+    f1, f2 = f1.cpu().numpy(), f2.cpu().numpy()
+    for name, prec in {"fp32": cc3.FP32, "bf16x6": cc3.BF16X6, "bf16x3": cc3.BF16X3}.items():
+        o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=prec)
+        torch.cuda.synchronize()
+        e1, e2 = rel(o1.cpu().numpy(), f1), rel(o2.cpu().numpy(), f2)
+        print(f"whole call {name}: rel err Omega1 {e1:.3e} Omega2 {e2:.3e}", flush=True)
         assert e1 <= BOUND[name] and e2 <= BOUND[name], (name, e1, e2)
     ctx.close()
 
@@ -74,5 +106,5 @@ def test_mixed_t3_block():
         t = ctx.t3_block(g["eps"], g["L"], g["t1"], g["t2"], 4, 2, 1, prec=prec).cpu().numpy()
         e = rel(t, ref)
         print(f"t3 {name}: {e:.3e}", flush=True)
-        assert e <= BOUND[name]
+        assert e <= BOUND_T3[name]
     ctx.close()
