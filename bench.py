@@ -278,6 +278,7 @@ def main() -> int:
     ap.add_argument("--standalone-steps", type=int, default=3,
                     help="calls with CC3_ONE_STREAM after the timed region, for kernel durations "
                          "without batch overlap (0: skip)")
+    ap.add_argument("--no-cvs", action="store_true", help="skip the CVS worklist timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-molecules", type=int, default=16,
@@ -473,6 +474,24 @@ def main() -> int:
         }
         log(f"jacobian prep: {out['jacobian_prep']['value']:.2f} TFLOP/s, {dtj * 1e3:.1f} ms per call")
         del zv, zo
+    if not args.no_cvs:
+        # the core-valence separation worklist: only the triples that contain the lowest
+        # occupied orbital (one core orbital of interest), through the subset entry point
+        core = cc3.cvs_triples(no, [0])
+        ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], core)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], core)
+        torch.cuda.synchronize()
+        dtc = (time.perf_counter() - t0) / args.steps
+        ntri = len(cc3.cvs_triples(no, list(range(no))))
+        out["cvs"] = {"what": "contravariant residual over the CVS worklist (triples with "
+                              "occupied orbital 0 as the core index), cc3_triples_residual_subset",
+                      "core": [0], "triples": int(len(core)), "of_triples": int(ntri),
+                      "ms_per_call": dtc * 1e3, "full_call_ms": ms, "speedup": ms / (dtc * 1e3)}
+        log(f"cvs worklist: {len(core)} of {ntri} triples, {dtc * 1e3:.1f} ms per call "
+            f"({ms / (dtc * 1e3):.1f}x faster than the full call)")
     if args.serve_molecules > 0:
         ctx.close()
         del g, o1, o2

@@ -58,9 +58,11 @@ enum {
 /* arithmetic of the W contractions (the t3-building GEMMs, Algorithm 1 first statement) */
 enum {
   CC3_FP64 = 0,   /* FP64 MFMA everywhere */
-  CC3_FP32 = 1,   /* W contractions on FP32 MFMA with FP32 accumulation */
-  CC3_BF16X3 = 2, /* W on bf16 MFMA, 2-piece split, 3 products, FP32 accumulation */
-  CC3_BF16X6 = 3  /* W on bf16 MFMA, 3-piece split, 6 products, FP32 accumulation */
+  CC3_FP32 = 1,   /* W contractions on FP32 MFMA; each 32-k stage summed in FP32, the
+                     stages accumulated in FP64 */
+  CC3_BF16X3 = 2, /* W on bf16 MFMA, 2-piece split, 3 products, FP32 accumulation per term */
+  CC3_BF16X6 = 3  /* W on bf16 MFMA, 3-piece split, 6 products; each 32-k stage summed in
+                     FP32, the stages accumulated in FP64 */
 };
 /* In every precision the denominator division, the P-symmetrisation, the
  * contravariant combination and the Omega accumulation are FP64. */
@@ -181,6 +183,21 @@ int cc3_jacobian_prep(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps
  * issues for the dominant contractions and their small companions, padding
  * excluded.  Either pointer may be NULL.  Errors: CC3_E_INVAL. */
 int cc3_flops(int no, int nv, double* nominal, double* executed);
+
+/* Core-valence separation worklist (Sec. "Results", core excitations): the
+ * triple loop of the Jacobian transformations skips the occupied triples none
+ * of whose indices is a core orbital of interest, which takes their cost from
+ * 8 nv^4 no^3 to 8 nv^4 no^2; the ground state keeps every triple.  Writes the
+ * unordered triples i >= j >= k (i == j == k excluded, as in the full loop) that
+ * contain at least one of the `ncore` HOST indices `core` (each in [0, no),
+ * repeats allowed), in the loop's lexicographic order, to the HOST array
+ * triples[n][3] (int32), and their number to *ntriples.  With triples == NULL
+ * only the count is written; otherwise `capacity` is the number of rows the
+ * array holds.  The list feeds cc3_triples_residual_subset.  Host-only, no
+ * context needed.  Errors: CC3_E_INVAL (bad sizes, index out of range, or
+ * capacity smaller than the count). */
+int cc3_cvs_triples(int no, const int32_t* core, int ncore, int32_t* triples, int capacity,
+                    int* ntriples);
 
 /* ---------------------------------------------------------------------- */
 /* Kernel timing (HIP events on the launch stream)                          */

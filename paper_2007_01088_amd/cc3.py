@@ -60,6 +60,8 @@ _jprep = _sig("cc3_jacobian_prep", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, 
                                      _c_int, ctypes.c_uint, _vp, _c_size, _vp])
 _flops = _sig("cc3_flops", [_c_int, _c_int, ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double)])
+_cvs = _sig("cc3_cvs_triples", [_c_int, ctypes.POINTER(ctypes.c_int32), _c_int,
+                                ctypes.POINTER(ctypes.c_int32), _c_int, ctypes.POINTER(ctypes.c_int)])
 _prof_enable = _sig("cc3_profile_enable", [_vp, _c_int])
 _prof_get = _sig("cc3_profile_get", [_vp, ctypes.POINTER(KernelStat), _c_int,
                                      ctypes.POINTER(_c_int)])
@@ -102,7 +104,7 @@ _srv_stats = _sig("cc3_server_get_stats", [_vp, ctypes.POINTER(ServerStats)])
 
 EXPORTED = ["cc3_create", "cc3_destroy", "cc3_last_error", "cc3_workspace_size",
             "cc3_triples_residual", "cc3_triples_residual_blocks", "cc3_triples_residual_subset",
-            "cc3_t3_block", "cc3_flops", "cc3_profile_enable", "cc3_profile_get",
+            "cc3_t3_block", "cc3_flops", "cc3_cvs_triples", "cc3_profile_enable", "cc3_profile_get",
             "cc3_jacobian_prep", "cc3_server_create", "cc3_server_destroy", "cc3_server_footprint",
             "cc3_molecule_register", "cc3_molecule_release", "cc3_submit", "cc3_poll",
             "cc3_wait", "cc3_cancel", "cc3_server_get_stats"]
@@ -142,6 +144,21 @@ def workspace_size(no: int, nv: int, nchol: int, prec: int = FP64, flags: int = 
     n = _c_size(0)
     _check(_ws_size(no, nv, nchol, prec, flags, ctypes.byref(n)), "cc3_workspace_size")
     return n.value
+
+
+def cvs_triples(no: int, core) -> np.ndarray:
+    """The restricted-loop triples (int32 [n][3], lexicographic) containing at least one
+    of the core orbital indices `core` (cc3_cvs_triples)."""
+    import numpy as np
+    c = np.ascontiguousarray(np.asarray(core, dtype=np.int32).reshape(-1))
+    cp = c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if c.size else None
+    n = ctypes.c_int(0)
+    _check(_cvs(no, cp, int(c.size), None, 0, ctypes.byref(n)), "cc3_cvs_triples")
+    out = np.zeros((n.value, 3), dtype=np.int32)
+    if n.value:
+        _check(_cvs(no, cp, int(c.size), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    n.value, ctypes.byref(n)), "cc3_cvs_triples")
+    return out
 
 
 def flops(no: int, nv: int) -> tuple[float, float]:

@@ -77,6 +77,41 @@ extern "C" int cc3_flops(int no, int nv, double* nominal, double* executed) {
   return CC3_OK;
 }
 
+extern "C" int cc3_cvs_triples(int no, const int32_t* core, int ncore, int32_t* triples,
+                               int capacity, int* ntriples) {
+  if (no < 1 || no > 63) return fail(CC3_E_INVAL, "cc3_cvs_triples: no must be in [1, 63] (got %d)", no);
+  if (ncore < 0 || (ncore > 0 && !core)) return fail(CC3_E_INVAL, "cc3_cvs_triples: bad core list");
+  if (!ntriples) return fail(CC3_E_INVAL, "cc3_cvs_triples: ntriples is NULL");
+  bool is_core[64] = {};
+  for (int c = 0; c < ncore; ++c) {
+    if (core[c] < 0 || core[c] >= no)
+      return fail(CC3_E_INVAL, "cc3_cvs_triples: core index %d outside [0, %d)", core[c], no);
+    is_core[core[c]] = true;
+  }
+  int n = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      *ntriples = n;
+      if (!triples) return CC3_OK;
+      if (capacity < n)
+        return fail(CC3_E_INVAL, "cc3_cvs_triples: capacity %d below the count %d", capacity, n);
+      n = 0;
+    }
+    for (int i = 0; i < no; ++i)
+      for (int j = 0; j <= i; ++j)
+        for (int k = 0; k <= j; ++k) {
+          if ((i == j && j == k) || !(is_core[i] || is_core[j] || is_core[k])) continue;
+          if (pass == 1) {
+            triples[3 * n] = i;
+            triples[3 * n + 1] = j;
+            triples[3 * n + 2] = k;
+          }
+          ++n;
+        }
+  }
+  return CC3_OK;
+}
+
 static int common_checks(cc3_ctx* c, int no, int nv, int nchol, int prec, unsigned flags,
                          void* ws, size_t ws_bytes, Plan* p) {
   if (!c) return fail(CC3_E_INVAL, "ctx is NULL");

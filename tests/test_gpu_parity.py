@@ -203,6 +203,30 @@ def test_subset_sums_to_whole(ctx):
     assert_close("Ot2", w2.cpu().numpy(), r2)
 
 
+def test_cvs_worklist(ctx):
+    """The core-valence separation worklist (triples with a core index, here the two
+    lowest occupied orbitals) through the subset entry point: parity with the oracle
+    on the same triples, and with the valence-only complement it sums to the whole."""
+    torch = _torch()
+    from paper_2007_01088_amd import cc3
+    no, nv = 8, 28
+    d = make_inputs(no, nv, 40)
+    g = dev(torch, d)
+    core = cc3.cvs_triples(no, [0, 1])
+    allt = np.array(O.unordered_triples(no), dtype=np.int32)
+    keep = {tuple(x) for x in core.tolist()}
+    val = np.array([x for x in allt.tolist() if tuple(x) not in keep], dtype=np.int32)
+    say(f"cvs: {len(core)} of {len(allt)} triples contain a core index")
+    c1, c2 = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], core)
+    v1, v2 = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], val)
+    w1, w2 = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], allt)
+    r1, r2 = O.omega_tilde_subset(d["eps"], d["L"], d["t1"], d["t2"], core)
+    assert_close("Ot1 cvs", c1.cpu().numpy(), r1)
+    assert_close("Ot2 cvs", c2.cpu().numpy(), r2)
+    assert_close("Ot1 cvs + valence", (c1 + v1).cpu().numpy(), w1.cpu().numpy())
+    assert_close("Ot2 cvs + valence", (c2 + v2).cpu().numpy(), w2.cpu().numpy())
+
+
 @pytest.mark.parametrize("no,nv,nJ,count", [(12, 120, 400, 10), (23, 250, 800, 2),
                                             (31, 400, 1200, 0)])
 def test_sampled_parity_full_sizes(ctx, no, nv, nJ, count):
