@@ -71,10 +71,20 @@ enum {
 enum {
   CC3_ACCUMULATE = 1u,    /* add the triples contribution into omega1/omega2 instead of overwriting */
   CC3_CHECK = 2u,         /* verify input symmetries (t2, L) and positive denominators first */
-  CC3_ONE_STREAM = 4u     /* run the batches of the triple loop one after another on one stream
+  CC3_ONE_STREAM = 4u,    /* run the batches of the triple loop one after another on one stream
                              instead of overlapping consecutive batches on two; the result is
                              the same, each kernel runs without a neighbour on the device
                              (standalone timing), the call is slower (one-shot calls only) */
+  CC3_LOWP_CONTRACT = 8u, /* "mixed-all": with prec = CC3_FP32, the vv term and Omega1 of the
+                             Omega contraction also run on FP32 MFMA, over FP32 roundings of the
+                             contravariant t3 and of the (vv|ov) and (ov|ov) blocks; each K chunk
+                             sums in FP32, the chunks and triples in FP64.  The oo and Fock terms
+                             and the back-transformation stay FP64.  One-shot residual calls
+                             only (not cc3_jacobian_prep, not serving); other precisions:
+                             CC3_E_INVAL.  The workspace grows (cc3_workspace_size with it). */
+  CC3_DETERMINISTIC = 16u /* accepted for callers that ask for it: every call is deterministic
+                             anyway (fixed-order reductions, no floating-point atomics), so the
+                             same inputs and sizes give the same bits */
 };
 
 /* ---------------------------------------------------------------------- */

@@ -23,7 +23,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_PRECOND, E_NOTFOUND, E_BUSY, E_TIMEOUT, E_CANCELLED = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
-ACCUMULATE, CHECK, ONE_STREAM = 1, 2, 4
+ACCUMULATE, CHECK, ONE_STREAM, LOWP_CONTRACT, DETERMINISTIC = 1, 2, 4, 8, 16
 
 _c_int, _c_size, _vp, _dp = ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p
 

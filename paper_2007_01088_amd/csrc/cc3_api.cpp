@@ -117,8 +117,11 @@ static int common_checks(cc3_ctx* c, int no, int nv, int nchol, int prec, unsign
   if (!c) return fail(CC3_E_INVAL, "ctx is NULL");
   int rc = check_sizes(no, nv, nchol, prec);
   if (rc) return rc;
-  if (flags & ~(unsigned)(CC3_ACCUMULATE | CC3_CHECK | CC3_ONE_STREAM))
+  if (flags & ~(unsigned)(CC3_ACCUMULATE | CC3_CHECK | CC3_ONE_STREAM | CC3_LOWP_CONTRACT |
+                         CC3_DETERMINISTIC))
     return fail(CC3_E_INVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & CC3_LOWP_CONTRACT) && prec != CC3_FP32)
+    return fail(CC3_E_INVAL, "CC3_LOWP_CONTRACT needs prec = CC3_FP32 (got %d)", prec);
   make_plan_ex(no, nv, nchol, prec, flags, true, 0, p);
   if (!ws) return fail(CC3_E_INVAL, "workspace is NULL");
   if (((uintptr_t)ws) & 255) return fail(CC3_E_INVAL, "workspace must be 256-byte aligned");
@@ -257,6 +260,8 @@ extern "C" int cc3_jacobian_prep(cc3_ctx* c, int no, int nv, int nchol, const do
                                  const double* L, const double* t1, const double* t2, double* zv,
                                  double* zo, int prec, unsigned flags, void* ws, size_t ws_bytes,
                                  cc3_stream_t stream) {
+  if (flags & CC3_LOWP_CONTRACT)
+    return fail(CC3_E_INVAL, "CC3_LOWP_CONTRACT applies to the residual calls only");
   Plan p;
   int rc = common_checks(c, no, nv, nchol, prec, flags, ws, ws_bytes, &p);
   if (rc) return rc;

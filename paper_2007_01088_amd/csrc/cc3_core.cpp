@@ -220,6 +220,12 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   // partial slabs: Omega chunks of nv x (nv + 1), or Jacobian-preparation chunks of nv x no
   p->pvv_bytes = align256(tc * 6 * v * std::max(v + 1, o) * 8);
   p->off_Pvv = take(2 * p->pvv_bytes);
+  if (flags & CC3_LOWP_CONTRACT) {
+    p->gf_bytes = align256(o * (v + o) * v * v * 4);
+    p->off_gf = take(2 * p->gf_bytes);
+    p->cubef_bytes = align256((size_t)batch * 2 * p->cube * 4);
+    p->off_cubef = take(2 * p->cubef_bytes);
+  }
   p->off_tri = take((size_t)std::max(1, p->ntri) * 3 * sizeof(int) + 64);
   p->off_flag = take(64);
   // the Cholesky scratch is dead once the blocks are built: it shares the cube region
@@ -245,6 +251,12 @@ Ws carve(const Plan& p, void* ws, const Blocks* external_blocks) {
   for (int k = 0; k < 2; ++k) {
     w.Pvv[k] = (double*)(base + p.off_Pvv + k * p.pvv_bytes);
     w.cubes[k] = (double*)(base + p.off_cubes + k * p.cube_bytes);
+  }
+  w.GbcF = w.GcbF = w.cubesF[0] = w.cubesF[1] = nullptr;
+  if (p.gf_bytes) {
+    w.GbcF = (float*)(base + p.off_gf);
+    w.GcbF = (float*)(base + p.off_gf + p.gf_bytes);
+    for (int k = 0; k < 2; ++k) w.cubesF[k] = (float*)(base + p.off_cubef + k * p.cubef_bytes);
   }
   w.tri = (int*)(base + p.off_tri);
   w.flag = (int*)(base + p.off_flag);
@@ -315,6 +327,12 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
   std::vector<int> kinds;
   launch_t2N(t2, w.t2N, p.no, p.nv, st);
   if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, p.no, p.nv, w.lp, st);
+  const bool lowp_contract = w.GbcF != nullptr;
+  if (lowp_contract) {
+    const int64_t gn = (int64_t)p.no * (p.nv + p.no) * p.nv * p.nv;
+    launch_to_f32(w.b.Gbc, w.GbcF, gn, st);
+    launch_to_f32(w.b.Gcb, w.GcbF, gn, st);
+  }
   HIPCHK(hipEventRecord(rn.ev_fork, st));
   for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
   // CC3_ONE_STREAM (or CC3_SERIAL=1 in the environment) keeps every batch on one stream
@@ -338,11 +356,14 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
     }
     {
       Timer tm(pf, sk, FAM_MIX, 0.0, 0.0);
-      launch_mix(eps, tb, nb, w.cubes[k], p.no, p.nv, sk);
+      launch_mix(eps, tb, nb, w.cubes[k], lowp_contract ? w.cubesF[k] : nullptr, p.no, p.nv, sk);
     }
     {
       Timer tm(pf, sk, FAM_OMEGA, omega_flops(p.no, p.nv, kinds.data(), nb), 0.0);
-      launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], p.no, p.nv, sk);
+      if (lowp_contract)
+        launch_omega_f32(w.cubesF[k], w.GbcF, w.GcbF, tb, nb, w.Pvv[k], p.no, p.nv, sk);
+      else
+        launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], p.no, p.nv, sk);
     }
     if (nbatch > 0) HIPCHK(hipStreamWaitEvent(sk, rn.ev_red[(nbatch - 1) % nstream], 0));
     {
@@ -424,7 +445,7 @@ int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws&
     }
     {
       Timer tm(pf, sk, FAM_MIX, 0.0, 0.0);
-      launch_mix(eps, tb, nb, w.cubes[k], no, nv, sk);
+      launch_mix(eps, tb, nb, w.cubes[k], nullptr, no, nv, sk);
     }
     {
       Timer tm(pf, sk, FAM_ZPREP, zprep_flops(no, nv, kinds.data(), nb) * ((double)no / (nv + no)), 0.0);

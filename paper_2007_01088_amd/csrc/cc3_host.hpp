@@ -80,6 +80,7 @@ struct Ws {
   CholeskyScratch cs;
   double *Ot1, *Ot2, *OtT, *t2N;
   double *cubes[2], *Pvv[2];
+  float *GbcF, *GcbF, *cubesF[2];  // mixed-all (CC3_LOWP_CONTRACT) only, else null
   int* tri;
   int* flag;
   LpOperands lp;

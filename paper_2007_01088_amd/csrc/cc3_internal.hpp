@@ -49,6 +49,8 @@ struct Plan {
   // byte offsets into the workspace
   size_t off_blocks;  // integral blocks (when the workspace holds them)
   size_t off_Ot1, off_Ot2, off_OtT, off_lp, off_t2N, off_Pvv, off_tri, off_flag, off_cubes;
+  size_t off_gf, gf_bytes;        // mixed-all: FP32 Gbc and Gcb (0 bytes otherwise)
+  size_t off_cubef, cubef_bytes;  // mixed-all: FP32 tau~ and tau~T per triple, per buffer set
   size_t off_chol;  // Cholesky scratch (aliases the cube region)
   size_t chol_bytes, cube_bytes, pvv_bytes;  // per buffer set (two sets)
   size_t total;
@@ -83,8 +85,9 @@ void launch_triple_table(int* tri, int no, int nbatch, hipStream_t st);
 void launch_t2N(const double* t2, double* t2N, int no, int nv, hipStream_t st);
 void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
                    double* cubes, int no, int nv, bool all_terms, hipStream_t st);
-void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, int no, int nv,
-                hipStream_t st);
+// cubesF (nullable): also write FP32 copies of tau~ and tau~T, [triple][2][nv^3]
+void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF, int no,
+                int nv, hipStream_t st);
 void launch_tau_export(const double* eps, const int* tri, const double* cubes, double* tau, int no,
                        int nv, hipStream_t st);
 // Omega contraction of a batch: the vv term and Omega1 into per-(triple,
@@ -98,6 +101,11 @@ void launch_reduce(const int* tri, int ntri, const double* Pvv, double* Ot1, dou
                    int nv, hipStream_t st);
 void launch_omega_oo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* OtT,
                      int no, int nv, hipStream_t st);
+// The mixed-all form of launch_omega: FP32 MFMA over FP32 copies of the cubes
+// (tau~, tau~T per triple) and of Gbc / Gcb; partial slabs in FP64 as above.
+void launch_omega_f32(const float* cubesF, const float* GbcF, const float* GcbF, const int* tri,
+                      int ntri, double* Pvv, int no, int nv, hipStream_t st);
+void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 // Ot~2[p][q][a][b] = Ot2[p][q][a][b] + OtT[p][q][b][a]  (contravariant doubles residual)
 void launch_combine(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
                     double* O2, int no, int nv, hipStream_t st);

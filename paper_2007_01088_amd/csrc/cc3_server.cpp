@@ -471,8 +471,9 @@ extern "C" int cc3_molecule_release(cc3_server* s, uint64_t mol) {
 extern "C" int cc3_submit(cc3_server* s, uint64_t mol, const double* t1, const double* t2,
                           int prec, unsigned flags, uint64_t* ticket) {
   if (!s || !ticket) return fail(CC3_E_INVAL, "cc3_submit: server or ticket is NULL");
-  if (flags & ~(unsigned)(CC3_ACCUMULATE | CC3_CHECK))
-    return fail(CC3_E_INVAL, "unknown flag bits 0x%x", flags);
+  if (flags & ~(unsigned)(CC3_ACCUMULATE | CC3_CHECK | CC3_DETERMINISTIC))
+    return fail(CC3_E_INVAL, "cc3_submit takes CC3_ACCUMULATE, CC3_CHECK and CC3_DETERMINISTIC "
+                "only (flags 0x%x)", flags);
   Molecule* m;
   Plan p;
   uint64_t t;

@@ -265,9 +265,12 @@ __device__ inline double xval(const double* __restrict__ cz, int kind, int64_t n
          P0[c * nv2 + a * nv + b];
 }
 
+// cubesF (nullable): FP32 copies of tau~ and tau~T for the mixed-all form,
+// [triple][2][nv^3]
 __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
                                              const int* __restrict__ tri,
-                                             double* __restrict__ cubes, int no, int nv) {
+                                             double* __restrict__ cubes, float* __restrict__ cubesF,
+                                             int no, int nv) {
   __shared__ double Xs[6 * TSZ];
   const int z = blockIdx.y;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
@@ -398,22 +401,30 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
       {
         const int u = e >> 6, v = (e >> 3) & 7, w = e & 7;
         const int a = A0 + u, b = B0 + v, c = C0 + w;
-        if (a < nv && b < nv && c < nv) TT[(a * nvl + b) * nvl + c] = Xs[o * TSZ + TP(u, v, w)];
+        if (a < nv && b < nv && c < nv) {
+          const double x = Xs[o * TSZ + TP(u, v, w)];
+          TT[(a * nvl + b) * nvl + c] = x;
+          if (cubesF) cubesF[(int64_t)z * 2 * nv3 + (a * nvl + b) * nvl + c] = (float)x;
+        }
       }
       {
         const int u = e >> 6, w = (e >> 3) & 7, v = e & 7;
         const int a = A0 + u, b = B0 + v, c = C0 + w;
-        if (a < nv && b < nv && c < nv) TTT[(a * nvl + c) * nvl + b] = Xs[o * TSZ + TP(u, v, w)];
+        if (a < nv && b < nv && c < nv) {
+          const double x = Xs[o * TSZ + TP(u, v, w)];
+          TTT[(a * nvl + c) * nvl + b] = x;
+          if (cubesF) cubesF[((int64_t)z * 2 + 1) * nv3 + (a * nvl + c) * nvl + b] = (float)x;
+        }
       }
     }
   }
 }
 
-void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, int no, int nv,
-                hipStream_t st) {
+void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF, int no,
+                int nv, hipStream_t st) {
   const int nb = (nv + MT - 1) / MT;
   const int nbt = nb * (nb + 1) * (nb + 2) / 6;
-  hipLaunchKernelGGL(k_mix, dim3(nbt, ntri), dim3(256), 0, st, eps, tri, cubes, no, nv);
+  hipLaunchKernelGGL(k_mix, dim3(nbt, ntri), dim3(256), 0, st, eps, tri, cubes, cubesF, no, nv);
 }
 
 // tau^{abc}_{ijk} = -X / eps^{abc}_{ijk} for one ordered triple whose six terms were all built
@@ -457,16 +468,50 @@ void launch_tau_export(const double* eps, const int* tri, const double* cubes, d
 // LDS stages; each chunk writes a partial slab Pvv[z][pi][chunk][a][n] (n <= nv)
 // that k_reduce sums in a fixed order.  128 x 128 tiles on 8 wavefronts of
 // 32 x 64, 16 k per LDS stage, two workgroups per CU.
+// The same GEMM runs on FP64 MFMA (E = double) or, for the "mixed-all" form, on
+// FP32 MFMA over FP32 copies of the cubes and of Gbc / Gcb (E = float), with the
+// products of each K chunk summed in FP32 and the chunks summed in FP64 by k_reduce.
 typedef TileCfg<4, 2, 2, 4, 16> OCfg;
+typedef float f4v_ __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(OCfg::NT) void k_omega(const double* __restrict__ cubes,
-                                                    const double* __restrict__ Gbc,
-                                                    const double* __restrict__ Gcb,
+template <class E>
+struct OmegaAcc;
+template <>
+struct OmegaAcc<double> {
+  typedef d4v V;
+  static __device__ V mfma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ double load(BufRsrc r, unsigned off) { return buf_load_f64(r, off); }
+  // D[row][col] of the 16x16x4 FP64 MFMA: row = lane/16 + 4 r
+  static __device__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct OmegaAcc<float> {
+  typedef f4v_ V;
+  static __device__ V mfma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ float load(BufRsrc r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  }
+  // D[row][col] of the 16x16x4 FP32 MFMA: row = 4 (lane/16) + r
+  static __device__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// cubes: the batch's cube slots, nslot per triple, the first of them slot0 (the
+// FP64 cubes hold all five slots; the FP32 copies only TT and TTT)
+template <class E>
+__global__ __launch_bounds__(OCfg::NT) void k_omega(const E* __restrict__ cubes, int nslot,
+                                                    int slot0, const E* __restrict__ Gbc,
+                                                    const E* __restrict__ Gcb,
                                                     const int* __restrict__ tri,
                                                     double* __restrict__ Pvv, int no, int nv,
                                                     int nchunks, int tiles_n) {
   typedef OCfg T;
-  __shared__ double lds[T::LDS_DOUBLES];
+  typedef OmegaAcc<E> M;
+  constexpr unsigned ES = sizeof(E);
+  __shared__ E lds[T::LDS_DOUBLES];
   const int pi = blockIdx.y, z = blockIdx.z;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   if (!perm_active(tri_kind(i, j, k), pi)) return;
@@ -482,12 +527,12 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(const double* __restrict__ c
   const bool cb = (pi == 2 || pi == 4);
   const bool amaj = !(pi == 0 || pi == 3);  // a contiguous, k stride nv
   const int slot = (pi == 1 || pi == 3 || pi == 4) ? SLOT_TTT : SLOT_TT;
-  const double* U = cubes + ((int64_t)z * NSLOT + slot) * nv3;
-  const double* G = (cb ? Gcb : Gbc) + (int64_t)r * (nv + no) * nv2;
+  const E* U = cubes + ((int64_t)z * nslot + slot - slot0) * nv3;
+  const E* G = (cb ? Gcb : Gbc) + (int64_t)r * (nv + no) * nv2;
   const int ask = amaj ? nv : 1;  // k stride of A in doubles
   // tile origins (k = 0) of the two operands
-  const double* A0 = amaj ? U + m0 : U + (int64_t)m0 * K;
-  const double* B0 = G + (int64_t)n0 * K;
+  const E* A0 = amaj ? U + m0 : U + (int64_t)m0 * K;
+  const E* B0 = G + (int64_t)n0 * K;
 
   // Per-thread part of every stage.  A: element e at (row/column x_e, k_e) of the
   // stage, global byte offset aoff[e] + k_e * ask * 8 from the stage origin
@@ -507,25 +552,25 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(const double* __restrict__ c
 #pragma unroll
     for (int e = 0; e < T::EA; ++e) {
       ak[e] = k0t + e * KP;
-      aoff[e] = xc * 8u;
+      aoff[e] = xc * ES;
       alds[e] = lds_idx<T::BK>(ak[e], x, T::LDA);
     }
   } else {
 #pragma unroll
     for (int e = 0; e < T::EA; ++e) {
       ak[e] = kt;
-      aoff[e] = (unsigned)(min(m0 + xt + e * RP, nv - 1) - m0) * (unsigned)K * 8u;
+      aoff[e] = (unsigned)(min(m0 + xt + e * RP, nv - 1) - m0) * (unsigned)K * ES;
       alds[e] = lds_idx<T::BK>(kt, xt + e * RP, T::LDA);
     }
   }
 #pragma unroll
   for (int e = 0; e < T::EB; ++e) {
     const int n = n0 + xt + e * RP;
-    boff[e] = (unsigned)((n < nv ? n : nv + q) - n0) * (unsigned)K * 8u;
+    boff[e] = (unsigned)((n < nv ? n : nv + q) - n0) * (unsigned)K * ES;
     blds[e] = T::BK * T::LDA + lds_idx<T::BK>(kt, xt + e * RP, T::LDB);
   }
-  const unsigned ask8 = (unsigned)ask * 8u;
-  double ra[T::EA], rb[T::EB];
+  const unsigned ask8 = (unsigned)ask * ES;
+  E ra[T::EA], rb[T::EB];
   auto fetch = [&](int s) {
     const int k0 = s * T::BK;
     const BufRsrc sa = buf_rsrc(A0 + (int64_t)k0 * ask), sb = buf_rsrc(B0 + k0);
@@ -534,36 +579,54 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(const double* __restrict__ c
     for (int e = 0; e < T::EA; ++e) {
       const bool in = ak[e] <= kl;
       const int kc = in ? ak[e] : kl;
-      const double v = buf_load_f64(sa, aoff[e] + (unsigned)kc * ask8);
-      ra[e] = in ? v : 0.0;
+      const E v = M::load(sa, aoff[e] + (unsigned)kc * ask8);
+      ra[e] = in ? v : E(0);
     }
     const bool inb = kt <= kl;
-    const unsigned kb = (unsigned)(inb ? kt : kl) * 8u;
+    const unsigned kb = (unsigned)(inb ? kt : kl) * ES;
 #pragma unroll
     for (int e = 0; e < T::EB; ++e) {
-      const double v = buf_load_f64(sb, boff[e] + kb);
-      rb[e] = inb ? v : 0.0;
+      const E v = M::load(sb, boff[e] + kb);
+      rb[e] = inb ? v : E(0);
     }
   };
-  auto store = [&](double* st) {
+  auto store = [&](E* st) {
 #pragma unroll
     for (int e = 0; e < T::EA; ++e) st[alds[e]] = ra[e];
 #pragma unroll
     for (int e = 0; e < T::EB; ++e) st[blds[e]] = rb[e];
   };
-  d4v acc[T::FM][T::FN];
-  zero_acc<T>(acc);
+  typename M::V acc[T::FM][T::FN];
+#pragma unroll
+  for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < T::FN; ++fn) acc[fm][fn] = typename M::V{0, 0, 0, 0};
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
   fetch(s0);
   store(lds);
   __syncthreads();
   for (int s = s0; s < s1; ++s) {
-    double* cur = lds + ((s - s0) & 1) * T::STAGE;
-    double* nxt = lds + ((s - s0 + 1) & 1) * T::STAGE;
+    E* cur = lds + ((s - s0) & 1) * T::STAGE;
+    E* nxt = lds + ((s - s0 + 1) & 1) * T::STAGE;
     const bool more = s + 1 < s1;
     if (more) fetch(s + 1);
-    mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
+    // lane supplies A[m = l%16][k = l/16] and B[k = l/16][n = l%16] to each MFMA
+#pragma unroll
+    for (int kk = 0; kk < T::BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      const int sw = (lane & 15) ^ lds_swz<T::BK>(kr);
+      E a[T::FM], b[T::FN];
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm) a[fm] = cur[kr * T::LDA + (wm * T::FM + fm) * 16 + sw];
+#pragma unroll
+      for (int fn = 0; fn < T::FN; ++fn)
+        b[fn] = cur[T::BK * T::LDA + kr * T::LDB + (wn * T::FN + fn) * 16 + sw];
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < T::FN; ++fn) acc[fm][fn] = M::mfma(a[fm], b[fn], acc[fm][fn]);
+    }
     if (more) store(nxt);
     __syncthreads();
   }
@@ -575,9 +638,9 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(const double* __restrict__ c
     for (int fn = 0; fn < T::FN; ++fn)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const int a = m0 + acc_row<T>(wm, fm, lane, rr);
+        const int a = m0 + (wm * T::FM + fm) * 16 + M::row(lane, rr);
         const int n = n0 + acc_col<T>(wn, fn, lane);
-        if (a < nv && n <= nv) pvv[(int64_t)a * NV1 + n] = acc[fm][fn][rr];
+        if (a < nv && n <= nv) pvv[(int64_t)a * NV1 + n] = (double)acc[fm][fn][rr];
       }
 }
 
@@ -1003,8 +1066,30 @@ void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri
   typedef OCfg T;
   const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + 1 + T::BN - 1) / T::BN;
   const int nch = omega_kchunks(nv, ntri);
-  hipLaunchKernelGGL(k_omega, dim3(nch * tm * tn, 6, ntri), dim3(T::NT), 0, st, cubes, b.Gbc,
-                     b.Gcb, tri, Pvv, no, nv, nch, tn);
+  hipLaunchKernelGGL(k_omega<double>, dim3(nch * tm * tn, 6, ntri), dim3(T::NT), 0, st, cubes,
+                     (int)NSLOT, 0, b.Gbc, b.Gcb, tri, Pvv, no, nv, nch, tn);
+}
+
+void launch_omega_f32(const float* cubesF, const float* GbcF, const float* GcbF, const int* tri,
+                      int ntri, double* Pvv, int no, int nv, hipStream_t st) {
+  typedef OCfg T;
+  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + 1 + T::BN - 1) / T::BN;
+  const int nch = omega_kchunks(nv, ntri);
+  hipLaunchKernelGGL(k_omega<float>, dim3(nch * tm * tn, 6, ntri), dim3(T::NT), 0, st, cubesF, 2,
+                     (int)SLOT_TT, GbcF, GcbF, tri, Pvv, no, nv, nch, tn);
+}
+
+// FP32 copies for the mixed-all form: dst[e] = (float)src[e]
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
+  unsigned g = nblk(n, 256);
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_to_f32, dim3(g), dim3(256), 0, st, src, dst, n);
 }
 
 void launch_omega_oo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* OtT,
