@@ -129,6 +129,7 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
   const int ldb = T::BK * T::LDA + kt * T::LDB + (xt ^ lds_swz<T::BK>(kt));
   double ra[T::EA], rb[T::EB];
   int lseg = 0, lk0 = 0;  // the next stage to load
+  int ks_load = 0;         // MFMA k-steps of 4 that hold data in the stage just loaded
   auto fetch = [&]() {
     const char *pa, *pb;
     if (lseg == 0) { pa = A0; pb = B0; }
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
       const double v = buf_load_f64(sb, (unsigned)(rowb[e] * ld + kc) * 8u);
       rb[e] = in ? v : 0.0;
     }
+    ks_load = min(T::BK, ld - lk0 + 3) / 4;  // a segment's last stage may be part zeros
     lk0 += T::BK;
     if (lk0 >= ld) { lk0 = 0; ++lseg; }
   };
@@ -169,8 +171,26 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
     double* cur = lds + (s & 1) * T::STAGE;
     double* nxt = lds + ((s + 1) & 1) * T::STAGE;
     const bool more = s + 1 < nsteps;
+    const int ks = ks_load;  // k-steps of the stage computed now (uniform)
     if (more) fetch();
-    mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
+    // as mfma_stage, skipping the k-steps of a segment's last stage that hold only zeros
+#pragma unroll
+    for (int kk = 0; kk < T::BK / 4; ++kk) {
+      if (kk >= ks) break;
+      const int kr = kk * 4 + (lane >> 4);
+      const int sw = (lane & 15) ^ lds_swz<T::BK>(kr);
+      double a[T::FM], b[T::FN];
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm) a[fm] = cur[kr * T::LDA + (wm * T::FM + fm) * 16 + sw];
+#pragma unroll
+      for (int fn = 0; fn < T::FN; ++fn)
+        b[fn] = cur[T::BK * T::LDA + kr * T::LDB + (wn * T::FN + fn) * 16 + sw];
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < T::FN; ++fn)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
+    }
     if (more) store(nxt);
     __syncthreads();
   }

@@ -189,6 +189,7 @@ struct LpSeg {
   int64_t a_rs, b_rs;   // row strides in bytes
   int64_t a_ps, b_ps;   // piece strides in bytes
   int ksteps;           // K steps of BK
+  int kreal;            // K before padding (the products past it are zero)
 };
 
 template <class E>
@@ -222,13 +223,13 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
                 ps_Go = o * o * v * lk;
   // segments: term 1 vv, term 1 oo, term 2 vv, term 2 oo (rows m for A, n for B)
   const LpSeg seg0 = {t2L + ((p1 * o + q1) * v) * dk * ESZ, GwTL + ((r1 * v + y) * v) * dk * ESZ,
-            dk * ESZ, dk * ESZ, ps_t2 * ESZ, ps_Gw * ESZ, (int)(dk / BK)};
+            dk * ESZ, dk * ESZ, ps_t2 * ESZ, ps_Gw * ESZ, (int)(dk / BK), nv};
   const LpSeg seg1 = {t2NL + ((p1 * v + y) * v) * lk * ESZ, GoTL + ((q1 * o + r1) * v) * lk * ESZ,
-            lk * ESZ, lk * ESZ, ps_t2N * ESZ, ps_Go * ESZ, (int)(lk / BK)};
+            lk * ESZ, lk * ESZ, ps_t2N * ESZ, ps_Go * ESZ, (int)(lk / BK), no};
   const LpSeg seg2 = {GwTL + ((r2 * v + y) * v) * dk * ESZ, t2L + ((p2 * o + q2) * v) * dk * ESZ,
-            dk * ESZ, dk * ESZ, ps_Gw * ESZ, ps_t2 * ESZ, (int)(dk / BK)};
+            dk * ESZ, dk * ESZ, ps_Gw * ESZ, ps_t2 * ESZ, (int)(dk / BK), nv};
   const LpSeg seg3 = {GoTL + ((q2 * o + r2) * v) * lk * ESZ, t2NL + ((p2 * v + y) * v) * lk * ESZ,
-            lk * ESZ, lk * ESZ, ps_Go * ESZ, ps_t2N * ESZ, (int)(lk / BK)};
+            lk * ESZ, lk * ESZ, ps_Go * ESZ, ps_t2N * ESZ, (int)(lk / BK), no};
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -290,9 +291,14 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
       const bool more = s + 1 < nsteps;
       if (more) load(s + 1);
       if constexpr (P == 1) {
-        // FP32: k=4 MFMA steps; lane supplies A[m = l%16][k = l/16], B[k = l/16][n = l%16]
+        // FP32: k=4 MFMA steps; lane supplies A[m = l%16][k = l/16], B[k = l/16][n = l%16].
+        // The k-steps past the segment's real K hold zero padding and are skipped.
+        const bool first = s < sa.ksteps;
+        const int k0 = (first ? s : s - sa.ksteps) * BK;
+        const int ks = min(BK, (first ? sa.kreal : sb.kreal) - k0 + 3) / 4;
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
+          if (kk >= ks) break;
           const int kc = kk * 4 + (lane >> 4);
           float a[LFM], b[LFN];
 #pragma unroll
