@@ -425,32 +425,34 @@ def main() -> int:
             }
             log(f"mixed {name}: {mixed[name]['value']:.2f} TFLOP/s, "
                 f"err {mixed[name]['rel_err_omega1']:.2e}/{mixed[name]['rel_err_omega2']:.2e}")
-        # "mixed-all": the vv and Omega1 contraction on FP32 MFMA as well
-        m1 = torch.empty_like(o1)
-        m2 = torch.empty_like(o2)
-        fl = cc3.LOWP_CONTRACT
-        ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=cc3.FP32, flags=fl)
-        torch.cuda.synchronize()
-        ctx.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=cc3.FP32, flags=fl)
-        torch.cuda.synchronize()
-        dtm = (time.perf_counter() - t0) / args.steps
-        st_m = ctx.profile_get()
-        ctx.profile_enable(False)
-        om = st_m.get("omega_contract", {"total_ms": 0.0, "launches": 1, "flops": 0.0})
-        mixed["fp32_all"] = {
-            "value": nominal / dtm / 1e12, "ms_per_step": dtm * 1e3,
-            "rel_err_omega1": float((m1 - o1).norm() / o1.norm()),
-            "rel_err_omega2": float((m2 - o2).norm() / o2.norm()),
-            "omega_contract_tflops": om["flops"] / (om["total_ms"] * 1e-3) / 1e12 if om["total_ms"] else None,
-            "peak_tflops": PEAK_TFLOPS["fp32"],
-            "what": "W and the vv/Omega1 contraction on FP32 MFMA (CC3_LOWP_CONTRACT); oo, Fock "
-                    "and back-transformation FP64",
-        }
-        log(f"mixed fp32_all: {mixed['fp32_all']['value']:.2f} TFLOP/s, "
-            f"err {mixed['fp32_all']['rel_err_omega1']:.2e}/{mixed['fp32_all']['rel_err_omega2']:.2e}")
+        # "mixed-all": the vv and Omega1 contraction in the low precision as well
+        for name, prec in (("fp32_all", cc3.FP32), ("bf16x6_all", cc3.BF16X6),
+                           ("bf16x3_all", cc3.BF16X3)):
+            m1 = torch.empty_like(o1)
+            m2 = torch.empty_like(o2)
+            fl = cc3.LOWP_CONTRACT
+            ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=prec, flags=fl)
+            torch.cuda.synchronize()
+            ctx.profile_enable(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=prec, flags=fl)
+            torch.cuda.synchronize()
+            dtm = (time.perf_counter() - t0) / args.steps
+            st_m = ctx.profile_get()
+            ctx.profile_enable(False)
+            om = st_m.get("omega_contract", {"total_ms": 0.0, "launches": 1, "flops": 0.0})
+            mixed[name] = {
+                "value": nominal / dtm / 1e12, "ms_per_step": dtm * 1e3,
+                "rel_err_omega1": float((m1 - o1).norm() / o1.norm()),
+                "rel_err_omega2": float((m2 - o2).norm() / o2.norm()),
+                "omega_contract_tflops": om["flops"] / (om["total_ms"] * 1e-3) / 1e12
+                if om["total_ms"] else None,
+                "what": "W and the vv/Omega1 contraction in this precision (CC3_LOWP_CONTRACT); "
+                        "oo, Fock and back-transformation FP64",
+            }
+            log(f"mixed {name}: {mixed[name]['value']:.2f} TFLOP/s, "
+                f"err {mixed[name]['rel_err_omega1']:.2e}/{mixed[name]['rel_err_omega2']:.2e}")
 
     out = {
         "metric": "Triples-residual TFLOP/s (4nv^4no^3/call)",

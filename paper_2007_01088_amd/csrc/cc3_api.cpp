@@ -120,8 +120,8 @@ static int common_checks(cc3_ctx* c, int no, int nv, int nchol, int prec, unsign
   if (flags & ~(unsigned)(CC3_ACCUMULATE | CC3_CHECK | CC3_ONE_STREAM | CC3_LOWP_CONTRACT |
                          CC3_DETERMINISTIC))
     return fail(CC3_E_INVAL, "unknown flag bits 0x%x", flags);
-  if ((flags & CC3_LOWP_CONTRACT) && prec != CC3_FP32)
-    return fail(CC3_E_INVAL, "CC3_LOWP_CONTRACT needs prec = CC3_FP32 (got %d)", prec);
+  if ((flags & CC3_LOWP_CONTRACT) && prec == CC3_FP64)
+    return fail(CC3_E_INVAL, "CC3_LOWP_CONTRACT needs a low precision (FP32, BF16X3, BF16X6)");
   make_plan_ex(no, nv, nchol, prec, flags, true, 0, p);
   if (!ws) return fail(CC3_E_INVAL, "workspace is NULL");
   if (((uintptr_t)ws) & 255) return fail(CC3_E_INVAL, "workspace must be 256-byte aligned");

@@ -221,9 +221,14 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   p->pvv_bytes = align256(tc * 6 * v * std::max(v + 1, o) * 8);
   p->off_Pvv = take(2 * p->pvv_bytes);
   if (flags & CC3_LOWP_CONTRACT) {
-    p->gf_bytes = align256(o * (v + o) * v * v * 4);
+    if (prec == CC3_FP32) {
+      p->gf_bytes = align256(o * (v + o) * v * v * 4);
+      p->cubef_bytes = align256((size_t)batch * 2 * p->cube * 4);
+    } else {
+      p->gf_bytes = align256(lp_contract_g_bytes(prec, no, nv));
+      p->cubef_bytes = align256((size_t)batch * lp_contract_cube_bytes(prec, nv));
+    }
     p->off_gf = take(2 * p->gf_bytes);
-    p->cubef_bytes = align256((size_t)batch * 2 * p->cube * 4);
     p->off_cubef = take(2 * p->cubef_bytes);
   }
   p->off_tri = take((size_t)std::max(1, p->ntri) * 3 * sizeof(int) + 64);
@@ -252,11 +257,11 @@ Ws carve(const Plan& p, void* ws, const Blocks* external_blocks) {
     w.Pvv[k] = (double*)(base + p.off_Pvv + k * p.pvv_bytes);
     w.cubes[k] = (double*)(base + p.off_cubes + k * p.cube_bytes);
   }
-  w.GbcF = w.GcbF = w.cubesF[0] = w.cubesF[1] = nullptr;
+  w.GbcX = w.GcbX = w.cubesX[0] = w.cubesX[1] = nullptr;
   if (p.gf_bytes) {
-    w.GbcF = (float*)(base + p.off_gf);
-    w.GcbF = (float*)(base + p.off_gf + p.gf_bytes);
-    for (int k = 0; k < 2; ++k) w.cubesF[k] = (float*)(base + p.off_cubef + k * p.cubef_bytes);
+    w.GbcX = base + p.off_gf;
+    w.GcbX = base + p.off_gf + p.gf_bytes;
+    for (int k = 0; k < 2; ++k) w.cubesX[k] = base + p.off_cubef + k * p.cubef_bytes;
   }
   w.tri = (int*)(base + p.off_tri);
   w.flag = (int*)(base + p.off_flag);
@@ -327,11 +332,16 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
   std::vector<int> kinds;
   launch_t2N(t2, w.t2N, p.no, p.nv, st);
   if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, p.no, p.nv, w.lp, st);
-  const bool lowp_contract = w.GbcF != nullptr;
-  if (lowp_contract) {
+  const bool lowp_contract = w.GbcX != nullptr;
+  const int lpP = !lowp_contract || p.prec == CC3_FP32 ? 0 : p.prec == CC3_BF16X3 ? 2 : 3;
+  if (lowp_contract && lpP == 0) {
     const int64_t gn = (int64_t)p.no * (p.nv + p.no) * p.nv * p.nv;
-    launch_to_f32(w.b.Gbc, w.GbcF, gn, st);
-    launch_to_f32(w.b.Gcb, w.GcbF, gn, st);
+    launch_to_f32(w.b.Gbc, (float*)w.GbcX, gn, st);
+    launch_to_f32(w.b.Gcb, (float*)w.GcbX, gn, st);
+  } else if (lowp_contract) {
+    launch_lp_contract_convert(w.b, p.prec, p.no, p.nv, w.GbcX, w.GcbX, st);
+    for (int k = 0; k < 2; ++k)
+      launch_lp_zero_pad(w.cubesX[k], (int64_t)p.batch * 4 * lpP * p.nv, p.nv, st);
   }
   HIPCHK(hipEventRecord(rn.ev_fork, st));
   for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
@@ -356,12 +366,16 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
     }
     {
       Timer tm(pf, sk, FAM_MIX, 0.0, 0.0);
-      launch_mix(eps, tb, nb, w.cubes[k], lowp_contract ? w.cubesF[k] : nullptr, p.no, p.nv, sk);
+      launch_mix(eps, tb, nb, w.cubes[k], lowp_contract && lpP == 0 ? (float*)w.cubesX[k] : nullptr,
+                 lpP ? w.cubesX[k] : nullptr, lpP, p.no, p.nv, sk);
     }
     {
       Timer tm(pf, sk, FAM_OMEGA, omega_flops(p.no, p.nv, kinds.data(), nb), 0.0);
-      if (lowp_contract)
-        launch_omega_f32(w.cubesF[k], w.GbcF, w.GcbF, tb, nb, w.Pvv[k], p.no, p.nv, sk);
+      if (lowp_contract && lpP == 0)
+        launch_omega_f32((const float*)w.cubesX[k], (const float*)w.GbcX, (const float*)w.GcbX, tb,
+                         nb, w.Pvv[k], p.no, p.nv, sk);
+      else if (lowp_contract)
+        launch_omega_lp(p.prec, w.cubesX[k], w.GbcX, w.GcbX, tb, nb, w.Pvv[k], p.no, p.nv, sk);
       else
         launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], p.no, p.nv, sk);
     }
@@ -445,7 +459,7 @@ int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws&
     }
     {
       Timer tm(pf, sk, FAM_MIX, 0.0, 0.0);
-      launch_mix(eps, tb, nb, w.cubes[k], nullptr, no, nv, sk);
+      launch_mix(eps, tb, nb, w.cubes[k], nullptr, nullptr, 0, no, nv, sk);
     }
     {
       Timer tm(pf, sk, FAM_ZPREP, zprep_flops(no, nv, kinds.data(), nb) * ((double)no / (nv + no)), 0.0);

@@ -38,6 +38,31 @@ __device__ inline double buf_load_f64(BufRsrc r, unsigned off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
+// Split of an FP64 value into BF16 pieces (the low-precision forms):
+// bf16_rn rounds to the nearest BF16, ties to even.
+__device__ inline uint16_t bf16_rn(double x) {
+  // round-to-nearest-even of the FP32 rounding of x (x is representable after
+  // the first rounding to FP32 for the magnitudes of the pieces used here)
+  const float f = (float)x;
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline double bf16_val(uint16_t h) { return (double)__uint_as_float(((uint32_t)h) << 16); }
+
+// pieces of x: piece 0 = hi, 1 = next, 2 = last (BF16); FP32 uses one float
+template <int P>
+__device__ inline void split_bf16(double x, uint16_t (&pc)[P]) {
+  double rest = x;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    pc[i] = bf16_rn(rest);
+    rest -= bf16_val(pc[i]);
+  }
+}
+
+
 // Tile geometry: WM x WN wavefronts, each owning FM x FN blocks of 16x16
 // outputs; BK (a multiple of 4) k values per LDS stage.
 template <int WM_, int WN_, int FM_, int FN_, int BK_ = 8>
@@ -108,42 +133,6 @@ __device__ inline void load_stage(const Opnd& o, int x0, int k0, double (&r)[E],
     }
   }
 }
-
-// Global -> registers for the stages of one operand view, with the per-thread
-// part of the addressing computed once (init) and only a uniform origin per
-// stage.  Rows x >= xlim repeat row xlim - 1 (their products only reach
-// outputs that are never stored); elements with k >= klim read as 0, which
-// zeroes their products whatever the other operand holds there (finite data).
-// Per-thread byte offsets from the stage origin stay below 4 GiB for every
-// supported size (rows < 128 of stride <= nv^2, k < 32 of stride <= nv^2).
-template <int X, int BK, int E, int NT>
-struct StageLoader {
-  unsigned xo[E];  // byte offset of element e's row from the tile origin
-  int k_t, dk;     // element e lies at k = k_t + e * dk within the stage
-  __device__ void init(const Opnd& o, int x0, int tid) {
-    const StageMap<X, BK, NT> mp(o.xfast, tid);
-    k_t = mp.k_t;
-    dk = mp.dk;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int x = min(x0 + mp.x_t + e * mp.dx, o.xlim - 1) - x0;
-      xo[e] = (unsigned)x * (unsigned)o.sx * 8u;
-    }
-  }
-  __device__ void load(const Opnd& o, int x0, int k0, double (&r)[E]) const {
-    const char* org = (const char*)(o.p + ((int64_t)x0 * o.sx + (int64_t)k0 * o.sk));
-    const bool full = k0 + BK <= o.klim;
-    const int kmax = o.klim - 1 - k0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int k = k_t + e * dk;
-      const bool in = full || k <= kmax;
-      const int kc = in ? k : kmax;
-      const double v = *(const double*)(org + (xo[e] + (unsigned)kc * (unsigned)o.sk * 8u));
-      r[e] = in ? v : 0.0;
-    }
-  }
-};
 
 // Registers -> swizzled k-major LDS tile (same element mapping as load_stage).
 template <int X, int BK, int E, int NT, int LD>

@@ -80,7 +80,9 @@ struct Ws {
   CholeskyScratch cs;
   double *Ot1, *Ot2, *OtT, *t2N;
   double *cubes[2], *Pvv[2];
-  float *GbcF, *GcbF, *cubesF[2];  // mixed-all (CC3_LOWP_CONTRACT) only, else null
+  // mixed-all (CC3_LOWP_CONTRACT) only, else null: low-precision Gbc and Gcb, and the
+  // per-set views of tau~ (FP32 tau~ and tau~T, or the split-BF16 k-major views)
+  void *GbcX, *GcbX, *cubesX[2];
   int* tri;
   int* flag;
   LpOperands lp;

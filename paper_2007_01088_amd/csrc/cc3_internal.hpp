@@ -12,6 +12,38 @@ namespace cc3 {
 // the per-p pair lists of the kernels hold 2 * MAX_BATCH entries.
 constexpr int MAX_BATCH = 160;
 
+// triple kinds
+enum { TRI_DISTINCT = 0, TRI_IJ = 1, TRI_JK = 2 };
+
+__host__ __device__ inline int tri_kind(int i, int j, int k) {
+  if (i == j) return TRI_IJ;  // i == j > k
+  if (j == k) return TRI_JK;  // i > j == k
+  return TRI_DISTINCT;
+}
+
+// The occupied permutation pi of (i,j,k) used for the contravariant contributions:
+// 0 (i,j,k)  1 (j,i,k)  2 (k,j,i)  3 (i,k,j)  4 (j,k,i)  5 (k,i,j).
+// All six are distinct when i, j, k differ; {0,2,3} when i == j; {0,1,2} when j == k.
+__host__ __device__ inline bool perm_active(int kind, int pi) {
+  if (kind == TRI_IJ) return pi == 0 || pi == 2 || pi == 3;
+  if (kind == TRI_JK) return pi <= 2;
+  return true;
+}
+
+__host__ __device__ inline void perm_pqr(int pi, int i, int j, int k, int& p, int& q, int& r) {
+  switch (pi) {
+    case 0: p = i; q = j; r = k; break;
+    case 1: p = j; q = i; r = k; break;
+    case 2: p = k; q = j; r = i; break;
+    case 3: p = i; q = k; r = j; break;
+    case 4: p = j; q = k; r = i; break;
+    default: p = k; q = i; r = j; break;
+  }
+}
+
+// K padded to a multiple of 32 (the low-precision operand rows)
+__host__ __device__ inline int64_t kpad32(int64_t k) { return (k + 31) / 32 * 32; }
+
 // Device-resident, internally laid out integral blocks (all float64):
 //   Gw[r][y][z][d] = g_{ydzr}         (vv|vo), the W contraction operand (d fastest)
 //   Go[q][r][z][l] = g_{lqzr}         (oo|vo) (l fastest)
@@ -49,8 +81,8 @@ struct Plan {
   // byte offsets into the workspace
   size_t off_blocks;  // integral blocks (when the workspace holds them)
   size_t off_Ot1, off_Ot2, off_OtT, off_lp, off_t2N, off_Pvv, off_tri, off_flag, off_cubes;
-  size_t off_gf, gf_bytes;        // mixed-all: FP32 Gbc and Gcb (0 bytes otherwise)
-  size_t off_cubef, cubef_bytes;  // mixed-all: FP32 tau~ and tau~T per triple, per buffer set
+  size_t off_gf, gf_bytes;        // mixed-all: low-precision Gbc and Gcb (0 bytes otherwise)
+  size_t off_cubef, cubef_bytes;  // mixed-all: low-precision views of tau~, per buffer set
   size_t off_chol;  // Cholesky scratch (aliases the cube region)
   size_t chol_bytes, cube_bytes, pvv_bytes;  // per buffer set (two sets)
   size_t total;
@@ -85,9 +117,10 @@ void launch_triple_table(int* tri, int no, int nbatch, hipStream_t st);
 void launch_t2N(const double* t2, double* t2N, int no, int nv, hipStream_t st);
 void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
                    double* cubes, int no, int nv, bool all_terms, hipStream_t st);
-// cubesF (nullable): also write FP32 copies of tau~ and tau~T, [triple][2][nv^3]
-void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF, int no,
-                int nv, hipStream_t st);
+// Mixed-all copies (nullable): cubesF, FP32 tau~ and tau~T, [triple][2][nv^3]; YL,
+// the split-BF16 k-major views of k_omega_lp with lpP pieces
+void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF,
+                void* YL, int lpP, int no, int nv, hipStream_t st);
 void launch_tau_export(const double* eps, const int* tri, const double* cubes, double* tau, int no,
                        int nv, hipStream_t st);
 // Omega contraction of a batch: the vv term and Omega1 into per-(triple,
@@ -106,6 +139,16 @@ void launch_omega_oo(const double* cubes, const Blocks& b, const int* tri, int n
 void launch_omega_f32(const float* cubesF, const float* GbcF, const float* GcbF, const int* tri,
                       int ntri, double* Pvv, int no, int nv, hipStream_t st);
 void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+// The mixed-all form with split BF16 (kern_wlp.hip): bytes of one of the two
+// operand blocks and of one triple's views; their conversion, the views' K
+// padding, and the GEMM.
+size_t lp_contract_g_bytes(int prec, int no, int nv);
+size_t lp_contract_cube_bytes(int prec, int nv);
+void launch_lp_contract_convert(const Blocks& b, int prec, int no, int nv, void* GbcL, void* GcbL,
+                                hipStream_t st);
+void launch_lp_zero_pad(void* YL, int64_t rows, int nv, hipStream_t st);
+void launch_omega_lp(int prec, const void* YL, const void* GbcL, const void* GcbL, const int* tri,
+                     int ntri, double* Pvv, int no, int nv, hipStream_t st);
 // Ot~2[p][q][a][b] = Ot2[p][q][a][b] + OtT[p][q][b][a]  (contravariant doubles residual)
 void launch_combine(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
                     double* O2, int no, int nv, hipStream_t st);

@@ -31,35 +31,6 @@ namespace cc3 {
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// triple kinds
-enum { TRI_DISTINCT = 0, TRI_IJ = 1, TRI_JK = 2 };
-
-__host__ __device__ inline int tri_kind(int i, int j, int k) {
-  if (i == j) return TRI_IJ;  // i == j > k
-  if (j == k) return TRI_JK;  // i > j == k
-  return TRI_DISTINCT;
-}
-
-// The occupied permutation pi of (i,j,k) used for the contravariant contributions:
-// 0 (i,j,k)  1 (j,i,k)  2 (k,j,i)  3 (i,k,j)  4 (j,k,i)  5 (k,i,j).
-// All six are distinct when i, j, k differ; {0,2,3} when i == j; {0,1,2} when j == k.
-__host__ __device__ inline bool perm_active(int kind, int pi) {
-  if (kind == TRI_IJ) return pi == 0 || pi == 2 || pi == 3;
-  if (kind == TRI_JK) return pi <= 2;
-  return true;
-}
-
-__host__ __device__ inline void perm_pqr(int pi, int i, int j, int k, int& p, int& q, int& r) {
-  switch (pi) {
-    case 0: p = i; q = j; r = k; break;
-    case 1: p = j; q = i; r = k; break;
-    case 2: p = k; q = j; r = i; break;
-    case 3: p = i; q = k; r = j; break;
-    case 4: p = j; q = k; r = i; break;
-    default: p = k; q = i; r = j; break;
-  }
-}
-
 // cube slots of one triple's workspace
 enum { SLOT_P0 = 0, SLOT_P1 = 1, SLOT_P2 = 2, SLOT_TT = 3, SLOT_TTT = 4, NSLOT = 5 };
 
@@ -285,12 +256,34 @@ __device__ inline double xval(const double* __restrict__ cz, int kind, int64_t n
          P0[c * nv2 + a * nv + b];
 }
 
-// cubesF (nullable): FP32 copies of tau~ and tau~T for the mixed-all form,
-// [triple][2][nv^3]
+// The split-BF16 pieces of x at row `row`, column kk of view v of triple z in
+// YL[z][4][P][nv][Kp] (Kp = kpad32(nv^2)).
+__device__ inline void yl_put(uint16_t* YL, int P, int z, int v, int row, int64_t kk, int nv,
+                              double x) {
+  const int64_t Kp = kpad32((int64_t)nv * nv);
+  uint16_t* base = YL + (((int64_t)z * 4 + v) * P * nv + row) * Kp + kk;
+  const int64_t ps = (int64_t)nv * Kp;
+  if (P == 2) {
+    uint16_t pc[2];
+    split_bf16<2>(x, pc);
+    base[0] = pc[0];
+    base[ps] = pc[1];
+  } else {
+    uint16_t pc[3];
+    split_bf16<3>(x, pc);
+    base[0] = pc[0];
+    base[ps] = pc[1];
+    base[2 * ps] = pc[2];
+  }
+}
+
+// Mixed-all copies (nullable): cubesF, FP32 tau~ and tau~T, [triple][2][nv^3];
+// YL, the split-BF16 k-major views of the split-BF16 Omega GEMM (k_omega_lp),
+// [triple][4][piece][a][kk < Kp] with lpP pieces.
 __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
                                              const int* __restrict__ tri,
                                              double* __restrict__ cubes, float* __restrict__ cubesF,
-                                             int no, int nv) {
+                                             uint16_t* __restrict__ YL, int lpP, int no, int nv) {
   __shared__ double Xs[6 * TSZ];
   const int z = blockIdx.y;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
@@ -425,6 +418,10 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
           const double x = Xs[o * TSZ + TP(u, v, w)];
           TT[(a * nvl + b) * nvl + c] = x;
           if (cubesF) cubesF[(int64_t)z * 2 * nv3 + (a * nvl + b) * nvl + c] = (float)x;
+          if (YL) {  // view 0 at [a][b nv + c], view 1 at [b][a nv + c]
+            yl_put(YL, lpP, z, 0, a, b * nvl + c, nv, x);
+            yl_put(YL, lpP, z, 1, b, a * nvl + c, nv, x);
+          }
         }
       }
       {
@@ -434,17 +431,22 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
           const double x = Xs[o * TSZ + TP(u, v, w)];
           TTT[(a * nvl + c) * nvl + b] = x;
           if (cubesF) cubesF[((int64_t)z * 2 + 1) * nv3 + (a * nvl + c) * nvl + b] = (float)x;
+          if (YL) {  // view 2 at [c][a nv + b], view 3 at [a][c nv + b]
+            yl_put(YL, lpP, z, 2, c, a * nvl + b, nv, x);
+            yl_put(YL, lpP, z, 3, a, c * nvl + b, nv, x);
+          }
         }
       }
     }
   }
 }
 
-void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF, int no,
-                int nv, hipStream_t st) {
+void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF,
+                void* YL, int lpP, int no, int nv, hipStream_t st) {
   const int nb = (nv + MT - 1) / MT;
   const int nbt = nb * (nb + 1) * (nb + 2) / 6;
-  hipLaunchKernelGGL(k_mix, dim3(nbt, ntri), dim3(256), 0, st, eps, tri, cubes, cubesF, no, nv);
+  hipLaunchKernelGGL(k_mix, dim3(nbt, ntri), dim3(256), 0, st, eps, tri, cubes, cubesF,
+                     (uint16_t*)YL, lpP, no, nv);
 }
 
 // tau^{abc}_{ijk} = -X / eps^{abc}_{ijk} for one ordered triple whose six terms were all built

@@ -36,28 +36,6 @@ __host__ __device__ inline int kpad(int k) { return (k + 31) / 32 * 32; }
 // ---------------------------------------------------------------------------
 // Operand conversion: FP64 value -> pieces
 // ---------------------------------------------------------------------------
-__device__ inline uint16_t bf16_rn(double x) {
-  // round-to-nearest-even of the FP32 rounding of x (x is representable after
-  // the first rounding to FP32 for the magnitudes of the pieces used here)
-  const float f = (float)x;
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline double bf16_val(uint16_t h) { return (double)__uint_as_float(((uint32_t)h) << 16); }
-
-// pieces of x: piece 0 = hi, 1 = next, 2 = last (BF16); FP32 uses one float
-template <int P>
-__device__ inline void split_bf16(double x, uint16_t (&pc)[P]) {
-  double rest = x;
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    pc[i] = bf16_rn(rest);
-    rest -= bf16_val(pc[i]);
-  }
-}
-
 // Generic re-layout: out[piece][outer][x][kk] (kk < K padded) from an FP64
 // source element (outer, x, k) at src[outer * so + x * sx + k * sk] * sign.
 // `piece_stride` is the element distance between pieces of the whole array.
@@ -391,6 +369,191 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
         if (m < nv && n < nv)
           dst[(int64_t)m * nv + n] = accd[fm][fn][r] + ((double)acc1[fm][fn][r] + (double)acc2[fm][fn][r]);
       }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-all Omega contraction (the vv term and Omega1) on split-BF16 MFMA
+// ---------------------------------------------------------------------------
+// The long-K GEMM of k_omega per (triple, permutation, 128 x 128 tile, K chunk):
+//   Pvv[z][pi][chunk][a][n] = sum_{kk in chunk} Y_v(pi)[a][kk] G[r][n'][kk],
+// with every operand row k-contiguous and zero-padded to Kp = kpad32(nv^2):
+//   YL[z][v][piece][a][kk]: the four k-major views of tau~ that the six
+//     permutations need, kk = x nv + y, written by k_mix:
+//     v = 0: tau~[a][x][y] (pi 0);  1: tau~[x][a][y] (pi 1, 4);
+//     v = 2: tau~[x][y][a] (pi 2, 5);  3: tau~[a][y][x] (pi 3);
+//   GL[piece][r][n'][kk]: Gbc (or Gcb for pi 2, 4) rows, n' = n for n < nv and
+//     nv + q (the Omega1 row) for n >= nv.
+// Each chunk sums in FP32 on the MFMA; k_reduce sums the chunks in FP64.  The
+// tile, LDS layout and loads are those of k_wbuild_lp.
+template <class E>
+__global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
+                                                  const char* __restrict__ GbcL,
+                                                  const char* __restrict__ GcbL,
+                                                  const int* __restrict__ tri,
+                                                  double* __restrict__ Pvv, int no, int nv,
+                                                  int nchunks, int tiles_n) {
+  constexpr int BK = E::BK, P = E::P, ESZ = E::ESZ, ROWB = E::ROWB;
+  constexpr int TILEB = LBM * ROWB;
+  constexpr int STAGEB = 2 * P * TILEB;
+  __shared__ __attribute__((aligned(16))) char lds[2 * STAGEB];
+  const int pi = blockIdx.y, z = blockIdx.z;
+  const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+  if (!perm_active(tri_kind(i, j, k), pi)) return;
+  int p, q, r;
+  perm_pqr(pi, i, j, k, p, q, r);
+  const int ch = blockIdx.x % nchunks, tile = blockIdx.x / nchunks;
+  const int m0 = (tile / tiles_n) * LBM, n0 = (tile % tiles_n) * LBN;
+  const int64_t Kp = kpad32((int64_t)nv * nv);
+  const int S = (int)(Kp / BK);
+  const int s0 = (int)((int64_t)ch * S / nchunks), s1 = (int)((int64_t)(ch + 1) * S / nchunks);
+  if (s0 >= s1) return;
+  const int view = pi == 0 ? 0 : pi == 3 ? 3 : (pi == 1 || pi == 4) ? 1 : 2;
+  const bool cb = (pi == 2 || pi == 4);
+  const int64_t rs = Kp * ESZ;                                   // row stride, bytes
+  const int64_t y_ps = (int64_t)nv * rs;                         // piece stride of a view
+  const int64_t g_ps = (int64_t)no * (nv + no) * rs;             // piece stride of GL
+  const char* ya = YL + ((int64_t)z * 4 + view) * P * y_ps;
+  const char* gb = (cb ? GcbL : GbcL) + (int64_t)r * (nv + no) * rs;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % LWM, wn = wave / LWM;
+  constexpr int CPR = BK * ESZ / 16;  // 16-byte chunks per row
+  constexpr int RPP = LNT / CPR;      // rows per pass of the workgroup
+  constexpr int CH = LBM / RPP;       // chunks per thread
+  const int cr = tid / CPR, cc = tid % CPR;
+  int64_t arow[CH], brow[CH];  // byte offsets of this thread's rows
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int row = cr + c * RPP;
+    arow[c] = (int64_t)min(m0 + row, nv - 1) * rs;  // rows past nv: outputs never stored
+    const int n = n0 + row;
+    brow[c] = (int64_t)(n < nv ? n : nv + q) * rs;
+  }
+  u4v ra[P][CH], rb[P][CH];
+  auto load = [&](int s) __attribute__((always_inline)) {
+    const int64_t koff = (int64_t)s * BK * ESZ + cc * 16;
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int pc = 0; pc < P; ++pc) {
+        ra[pc][c] = *(const u4v*)(ya + pc * y_ps + arow[c] + koff);
+        rb[pc][c] = *(const u4v*)(gb + pc * g_ps + brow[c] + koff);
+      }
+  };
+  auto store = [&](char* st) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int row = cr + c * RPP;
+#pragma unroll
+      for (int pc = 0; pc < P; ++pc) {
+        *(u4v*)(st + pc * TILEB + row * ROWB + cc * 16) = ra[pc][c];
+        *(u4v*)(st + (P + pc) * TILEB + row * ROWB + cc * 16) = rb[pc][c];
+      }
+    }
+  };
+  f4v acc[LFM][LFN];
+#pragma unroll
+  for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < LFN; ++fn) acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+  load(s0);
+  store(lds);
+  __syncthreads();
+  for (int s = s0; s < s1; ++s) {
+    char* cur = lds + ((s - s0) & 1) * STAGEB;
+    char* nxt = lds + ((s - s0 + 1) & 1) * STAGEB;
+    const bool more = s + 1 < s1;
+    if (more) load(s + 1);
+    // one k=32 step per product; lane supplies A[m = l%16][k = 8(l/16)..+7]
+    const int kb = (lane >> 4) * 16;
+    bf8v a[P][LFM], b[P][LFN];
+#pragma unroll
+    for (int pc = 0; pc < P; ++pc) {
+#pragma unroll
+      for (int fm = 0; fm < LFM; ++fm)
+        a[pc][fm] = *(const bf8v*)(cur + pc * TILEB + ((wm * LFM + fm) * 16 + (lane & 15)) * ROWB + kb);
+#pragma unroll
+      for (int fn = 0; fn < LFN; ++fn)
+        b[pc][fn] = *(const bf8v*)(cur + (P + pc) * TILEB + ((wn * LFN + fn) * 16 + (lane & 15)) * ROWB + kb);
+    }
+#pragma unroll
+    for (int t = 0; t < E::NPROD; ++t) {
+      int pa, pb;
+      prod_pair(P, t, pa, pb);
+#pragma unroll
+      for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < LFN; ++fn)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa][fm], b[pb][fn], acc[fm][fn], 0, 0, 0);
+    }
+    if (more) store(nxt);
+    __syncthreads();
+  }
+  // the BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
+  const int NV1 = nv + 1;
+  double* pvv = Pvv + (((int64_t)z * 6 + pi) * nchunks + ch) * (int64_t)nv * NV1;
+#pragma unroll
+  for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < LFN; ++fn)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int a = m0 + (wm * LFM + fm) * 16 + 4 * (lane >> 4) + rr;
+        const int n = n0 + (wn * LFN + fn) * 16 + (lane & 15);
+        if (a < nv && n <= nv) pvv[(int64_t)a * NV1 + n] = (double)acc[fm][fn][rr];
+      }
+}
+
+// Zero the K padding [nv^2, Kp) of `rows` rows of stride Kp (the YL views; k_mix
+// writes only kk < nv^2).
+__global__ void k_zero_pad(uint16_t* __restrict__ p, int64_t rows, int64_t K, int64_t Kp) {
+  const int64_t w = Kp - K;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rows * w;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[(e / w) * Kp + K + e % w] = 0;
+}
+
+void launch_lp_zero_pad(void* YL, int64_t rows, int nv, hipStream_t st) {
+  const int64_t K = (int64_t)nv * nv, Kp = kpad32(K);
+  if (Kp == K || rows == 0) return;
+  unsigned g = nblk(rows * (Kp - K), 256);
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_zero_pad, dim3(g), dim3(256), 0, st, (uint16_t*)YL, rows, K, Kp);
+}
+
+size_t lp_contract_g_bytes(int prec, int no, int nv) {
+  const int P = prec == CC3_BF16X3 ? 2 : 3;
+  return (size_t)P * no * (nv + no) * (size_t)kpad32((int64_t)nv * nv) * 2;  // one of Gbc, Gcb
+}
+size_t lp_contract_cube_bytes(int prec, int nv) {
+  const int P = prec == CC3_BF16X3 ? 2 : 3;
+  return (size_t)4 * P * nv * (size_t)kpad32((int64_t)nv * nv) * 2;  // per triple
+}
+
+void launch_lp_contract_convert(const Blocks& b, int prec, int no, int nv, void* GbcL, void* GcbL,
+                                hipStream_t st) {
+  const int64_t v = nv, o = no, K = v * v, Kp = kpad32(K);
+  const int64_t ps = o * (v + o) * Kp;  // piece stride (elements)
+  if (prec == CC3_BF16X3) {
+    lp_copy<2>(b.Gbc, (v + o) * K, K, 1, 1.0, no, nv + no, (int)K, GbcL, ps, st);
+    lp_copy<2>(b.Gcb, (v + o) * K, K, 1, 1.0, no, nv + no, (int)K, GcbL, ps, st);
+  } else {
+    lp_copy<3>(b.Gbc, (v + o) * K, K, 1, 1.0, no, nv + no, (int)K, GbcL, ps, st);
+    lp_copy<3>(b.Gcb, (v + o) * K, K, 1, 1.0, no, nv + no, (int)K, GcbL, ps, st);
+  }
+}
+
+void launch_omega_lp(int prec, const void* YL, const void* GbcL, const void* GcbL, const int* tri,
+                     int ntri, double* Pvv, int no, int nv, hipStream_t st) {
+  const int tm = (nv + LBM - 1) / LBM, tn = (nv + 1 + LBN - 1) / LBN;
+  const int nch = omega_kchunks(nv, ntri);
+  const dim3 grid(nch * tm * tn, 6, ntri), block(LNT);
+  const char *y = (const char*)YL, *gb = (const char*)GbcL, *gc = (const char*)GcbL;
+  if (prec == CC3_BF16X3)
+    hipLaunchKernelGGL(k_omega_lp<EngBF16<2>>, grid, block, 0, st, y, gb, gc, tri, Pvv, no, nv, nch, tn);
+  else
+    hipLaunchKernelGGL(k_omega_lp<EngBF16<3>>, grid, block, 0, st, y, gb, gc, tri, Pvv, no, nv, nch, tn);
 }
 
 void launch_wbuild_lp(const LpOperands& lp, const int* tri, int ntri, double* cubes, int no, int nv,

@@ -34,7 +34,7 @@ BOUND_T3 = {"fp32": 3e-7, "bf16x6": 3e-7, "bf16x3": 3e-5}
 # that GEMM summed over all of K with cancellation, carries the most: measured 1.8e-7 at
 # (5,48,60) and 3.0e-7 at 12/120/400 (Omega2 7.8e-8 / 6.5e-8).  It does not meet 1e-7 on
 # Omega1; bound 5e-7.
-BOUND_ALL = 5e-7
+BOUND_ALL = {"fp32": 5e-7, "bf16x6": 5e-7, "bf16x3": 3e-5}
 
 
 def _setup():
@@ -116,11 +116,13 @@ def test_mixed_t3_block():
     ctx.close()
 
 
-def test_mixed_all_fp32():
-    """"Mixed-all" (CC3_LOWP_CONTRACT with FP32): the vv and Omega1 contraction on FP32 MFMA
-    too.  Against the oracle at (5,48,60) and against the FP64 GPU call at 12/120/400;
-    the measured errors are printed and bounded by BOUND_ALL (below)."""
+@pytest.mark.parametrize("name", ["fp32", "bf16x6", "bf16x3"])
+def test_mixed_all(name):
+    """"Mixed-all" (CC3_LOWP_CONTRACT): the vv and Omega1 contraction in the low precision
+    too (FP32 MFMA, or split BF16).  Against the oracle at (5,48,60) and against the FP64
+    GPU call at 12/120/400; the measured errors are printed and bounded by BOUND_ALL."""
     torch, cc3 = _setup()
+    prec = {"fp32": cc3.FP32, "bf16x6": cc3.BF16X6, "bf16x3": cc3.BF16X3}[name]
     ctx = cc3.Context(0)
     for (no, nv, nJ) in ((5, 48, 60), (12, 120, 400)):
         d = make_inputs(no, nv, nJ)
@@ -131,13 +133,14 @@ def test_mixed_all_fp32():
             f1, f2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
             torch.cuda.synchronize()
             r1, r2 = f1.cpu().numpy(), f2.cpu().numpy()
-        o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=cc3.FP32,
+        o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=prec,
                                       flags=cc3.LOWP_CONTRACT)
         torch.cuda.synchronize()
         e1, e2 = rel(o1.cpu().numpy(), r1), rel(o2.cpu().numpy(), r2)
-        print(f"mixed-all fp32 no={no} nv={nv}: rel err Omega1 {e1:.3e} Omega2 {e2:.3e}", flush=True)
-        assert e1 <= BOUND_ALL and e2 <= BOUND_ALL, (no, nv, e1, e2)
+        print(f"mixed-all {name} no={no} nv={nv}: rel err Omega1 {e1:.3e} Omega2 {e2:.3e}",
+              flush=True)
+        assert e1 <= BOUND_ALL[name] and e2 <= BOUND_ALL[name], (no, nv, e1, e2)
     with pytest.raises(cc3.CC3Error):
-        ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=cc3.BF16X6,
+        ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=cc3.FP64,
                              flags=cc3.LOWP_CONTRACT)
     ctx.close()
