@@ -383,8 +383,9 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
 //     v = 2: tau~[x][y][a] (pi 2, 5);  3: tau~[a][y][x] (pi 3);
 //   GL[piece][r][n'][kk]: Gbc (or Gcb for pi 2, 4) rows, n' = n for n < nv and
 //     nv + q (the Omega1 row) for n >= nv.
-// Each chunk sums in FP32 on the MFMA; k_reduce sums the chunks in FP64.  The
-// tile, LDS layout and loads are those of k_wbuild_lp.
+// Each chunk sums in FP32 on the MFMA (with FLUSH, stage by stage into FP64);
+// k_reduce sums the chunks in FP64.  The tile, LDS layout and loads are those of
+// k_wbuild_lp.
 template <class E>
 __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
                                                   const char* __restrict__ GbcL,
@@ -453,10 +454,14 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
     }
   };
   f4v acc[LFM][LFN];
+  d4v accd[LFM][LFN];  // FLUSH: each stage's FP32 sum added in FP64
 #pragma unroll
   for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
-    for (int fn = 0; fn < LFN; ++fn) acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int fn = 0; fn < LFN; ++fn) {
+      acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+      accd[fm][fn] = d4v{0.0, 0.0, 0.0, 0.0};
+    }
   load(s0);
   store(lds);
   __syncthreads();
@@ -487,6 +492,16 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
         for (int fn = 0; fn < LFN; ++fn)
           acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa][fm], b[pb][fn], acc[fm][fn], 0, 0, 0);
     }
+    if constexpr (E::FLUSH) {
+#pragma unroll
+      for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < LFN; ++fn) {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) accd[fm][fn][rr] += (double)acc[fm][fn][rr];
+          acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+        }
+    }
     if (more) store(nxt);
     __syncthreads();
   }
@@ -501,7 +516,7 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
       for (int rr = 0; rr < 4; ++rr) {
         const int a = m0 + (wm * LFM + fm) * 16 + 4 * (lane >> 4) + rr;
         const int n = n0 + (wn * LFN + fn) * 16 + (lane & 15);
-        if (a < nv && n <= nv) pvv[(int64_t)a * NV1 + n] = (double)acc[fm][fn][rr];
+        if (a < nv && n <= nv) pvv[(int64_t)a * NV1 + n] = accd[fm][fn][rr] + (double)acc[fm][fn][rr];
       }
 }
 
