@@ -240,6 +240,10 @@ __device__ inline void decode_block_triple(int idx, int& A, int& B, int& C) {
   A = idx; B = b; C = c;
 }
 
+// Threads per mix workgroup: each handles MIXH of the 512 elements of an
+// orientation tile.
+constexpr int MIXT = 512, MIXH = 512 / MIXT;
+
 __device__ inline double xval(const double* __restrict__ cz, int kind, int64_t nv, int a, int b,
                               int c) {
   const int64_t nv2 = nv * nv, nv3 = nv2 * nv;
@@ -280,7 +284,7 @@ __device__ inline void yl_put(uint16_t* YL, int P, int z, int v, int row, int64_
 // Mixed-all copies (nullable): cubesF, FP32 tau~ and tau~T, [triple][2][nv^3];
 // YL, the split-BF16 k-major views of the split-BF16 Omega GEMM (k_omega_lp),
 // [triple][4][piece][a][kk < Kp] with lpP pieces.
-__global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
+__global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
                                              const int* __restrict__ tri,
                                              double* __restrict__ cubes, float* __restrict__ cubesF,
                                              uint16_t* __restrict__ YL, int lpP, int no, int nv) {
@@ -306,8 +310,8 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
     orient(o, q0, q1, q2);
     const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = t + 256 * h;
+    for (int h = 0; h < MIXH; ++h) {
+      const int e = t + MIXT * h;
       const int u = e >> 6, v = (e >> 3) & 7, w = e & 7;  // pass 0: c fastest
       const int a = A0 + u, b = B0 + v, c = C0 + w;
       double x = 0.0;
@@ -323,8 +327,8 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
     orient(o, q0, q1, q2);
     const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = t + 256 * h;
+    for (int h = 0; h < MIXH; ++h) {
+      const int e = t + MIXT * h;
       const int u = e >> 6, w = (e >> 3) & 7, v = e & 7;  // pass 1: b fastest
       const int a = A0 + u, b = B0 + v, c = C0 + w;
       if (a < nv && b < nv && c < nv) {
@@ -343,8 +347,8 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
       orient(o, q0, q1, q2);
       const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int e = t + 256 * h;
+      for (int h = 0; h < MIXH; ++h) {
+        const int e = t + MIXT * h;
         const int v = e >> 6, w = (e >> 3) & 7, u = e & 7;  // pass 2: a fastest
         const int a = A0 + u, b = B0 + v, c = C0 + w;
         if (a < nv && b < nv && c < nv) Xs[o * TSZ + TP(u, v, w)] += P2[c * nv2 + b * nvl + a];
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
   }
   __syncthreads();
   // 2. tau~ on the orbit, held in registers until every thread has read X
-  double tt[6][2];
+  double tt[6][MIXH];
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
     int q0, q1, q2;
@@ -362,8 +366,8 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
     const int o_acb = orient_of(q0, q2), o_cba = orient_of(q2, q1), o_bac = orient_of(q1, q0);
     const int o_bca = orient_of(q1, q2), o_cab = orient_of(q2, q0);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = t + 256 * h;
+    for (int h = 0; h < MIXH; ++h) {
+      const int e = t + MIXT * h;
       const int u = e >> 6, v = (e >> 3) & 7, w = e & 7;
       const int a = A0 + u, b = B0 + v, c = C0 + w;
       double val = 0.0;
@@ -385,8 +389,8 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
 #pragma unroll
   for (int o = 0; o < 6; ++o)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = t + 256 * h;
+    for (int h = 0; h < MIXH; ++h) {
+      const int e = t + MIXT * h;
       Xs[o * TSZ + TP(e >> 6, (e >> 3) & 7, e & 7)] = tt[o][h];
     }
   __syncthreads();
@@ -409,8 +413,8 @@ __global__ __launch_bounds__(256) void k_mix(const double* __restrict__ eps,
     if (dup) continue;
     const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = t + 256 * h;
+    for (int h = 0; h < MIXH; ++h) {
+      const int e = t + MIXT * h;
       {
         const int u = e >> 6, v = (e >> 3) & 7, w = e & 7;
         const int a = A0 + u, b = B0 + v, c = C0 + w;
@@ -445,7 +449,7 @@ void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, floa
                 void* YL, int lpP, int no, int nv, hipStream_t st) {
   const int nb = (nv + MT - 1) / MT;
   const int nbt = nb * (nb + 1) * (nb + 2) / 6;
-  hipLaunchKernelGGL(k_mix, dim3(nbt, ntri), dim3(256), 0, st, eps, tri, cubes, cubesF,
+  hipLaunchKernelGGL(k_mix, dim3(nbt, ntri), dim3(MIXT), 0, st, eps, tri, cubes, cubesF,
                      (uint16_t*)YL, lpP, no, nv);
 }
 
