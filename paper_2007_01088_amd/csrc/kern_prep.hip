@@ -76,19 +76,56 @@ __global__ void k_t1_oo(const double* __restrict__ L, const double* __restrict__
   }
 }
 
-__global__ void k_t1_vo(const double* __restrict__ L, const double* __restrict__ t1,
-                        const double* __restrict__ Loo, double* __restrict__ LvoT, int no, int nv) {
-  const int J = blockIdx.y;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= no * nv) return;
-  const int k = idx / nv, c = idx % nv;
+// LvoT[J][k][c] for 16 consecutive c of one J.  The rows L_{no+c, no+d} and t1
+// pass through LDS in chunks of 64 d, so every global read is a row segment;
+// each sum keeps the order of the formula above (d ascending, then l).
+__global__ __launch_bounds__(256) void k_t1_vo(const double* __restrict__ L,
+                                               const double* __restrict__ t1,
+                                               const double* __restrict__ Loo,
+                                               double* __restrict__ LvoT, int no, int nv) {
+  constexpr int RC = 16, DC = 64, PER = (RC * 64 + 255) / 256;  // no <= 63
+  __shared__ double Ls[RC][DC + 1];
+  __shared__ double Ts[64][DC + 1];
+  const int J = blockIdx.y, c0 = blockIdx.x * RC, tid = threadIdx.x;
   const int nmo = no + nv;
   const double* LJ = L + (int64_t)J * nmo * nmo;
-  double v = LJ[(int64_t)(no + c) * nmo + k];
-  for (int d = 0; d < nv; ++d) v += LJ[(int64_t)(no + c) * nmo + no + d] * t1[(int64_t)k * nv + d];
+  double acc[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + 256 * i, ci = e % RC, k = e / RC, c = c0 + ci;
+    acc[i] = (k < no && c < nv) ? LJ[(int64_t)(no + c) * nmo + k] : 0.0;
+  }
+  for (int d0 = 0; d0 < nv; d0 += DC) {
+    const int dn = min(DC, nv - d0);
+    for (int e = tid; e < RC * DC; e += 256) {
+      const int ci = e / DC, dd = e % DC, c = c0 + ci;
+      Ls[ci][dd] = (c < nv && dd < dn) ? LJ[(int64_t)(no + c) * nmo + no + d0 + dd] : 0.0;
+    }
+    for (int e = tid; e < no * DC; e += 256) {
+      const int k = e / DC, dd = e % DC;
+      Ts[k][dd] = dd < dn ? t1[(int64_t)k * nv + d0 + dd] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + 256 * i, ci = e % RC, k = e / RC;
+      if (k < no) {
+        double v = acc[i];
+        for (int dd = 0; dd < dn; ++dd) v += Ls[ci][dd] * Ts[k][dd];
+        acc[i] = v;
+      }
+    }
+    __syncthreads();
+  }
   const double* LooJ = Loo + (int64_t)J * no * no;
-  for (int l = 0; l < no; ++l) v -= t1[(int64_t)l * nv + c] * LooJ[(int64_t)l * no + k];
-  LvoT[(int64_t)J * no * nv + (int64_t)k * nv + c] = v;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + 256 * i, ci = e % RC, k = e / RC, c = c0 + ci;
+    if (k >= no || c >= nv) continue;
+    double v = acc[i];
+    for (int l = 0; l < no; ++l) v -= t1[(int64_t)l * nv + c] * LooJ[(int64_t)l * no + k];
+    LvoT[(int64_t)J * no * nv + (int64_t)k * nv + c] = v;
+  }
 }
 
 void launch_t1_transform(const double* L, const double* t1, const CholeskyScratch& cs, int no,
@@ -98,8 +135,8 @@ void launch_t1_transform(const double* L, const double* t1, const CholeskyScratc
   int m = no * no > no * nv ? no * no : no * nv;
   hipLaunchKernelGGL(k_t1_oo, dim3(nblk(m, 256), nJ), dim3(256), 0, st, L, t1, cs.Loo, cs.LooT,
                      cs.Lov, no, nv);
-  hipLaunchKernelGGL(k_t1_vo, dim3(nblk((int64_t)no * nv, 256), nJ), dim3(256), 0, st, L, t1,
-                     cs.Loo, cs.LvoT, no, nv);
+  hipLaunchKernelGGL(k_t1_vo, dim3(nblk(nv, 16), nJ), dim3(256), 0, st, L, t1, cs.Loo, cs.LvoT,
+                     no, nv);
 }
 
 // ---------------------------------------------------------------------------
@@ -130,19 +167,20 @@ __global__ void k_fock_sm(const double* __restrict__ t1, const double* __restric
   }
 }
 
-// F[k][c] for 64 consecutive c of one k; four slices of the Cholesky index
+// F[k][c] for 64 consecutive c of one k; sixteen slices of the Cholesky index
 // summed through LDS in a fixed order.
-__global__ __launch_bounds__(256) void k_fock(const double* __restrict__ Lov,
-                                              const double* __restrict__ s,
-                                              const double* __restrict__ M, double* __restrict__ F,
-                                              int no, int nv, int nJ) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(1024) void k_fock(const double* __restrict__ Lov,
+                                               const double* __restrict__ s,
+                                               const double* __restrict__ M, double* __restrict__ F,
+                                               int no, int nv, int nJ) {
+  constexpr int NS = 16;
+  __shared__ double red[64 * NS];
   const int k = blockIdx.x;
   const int c = blockIdx.y * 64 + (threadIdx.x & 63);
   const int js = threadIdx.x >> 6;
   double v = 0.0;
   if (c < nv) {
-    for (int J = js; J < nJ; J += 4) {
+    for (int J = js; J < nJ; J += NS) {
       const double* LJ = Lov + (int64_t)J * no * nv;
       double w = 2.0 * s[J] * LJ[(int64_t)k * nv + c];
       const double* MJ = M + (int64_t)J * no * no + (int64_t)k * no;
@@ -152,15 +190,17 @@ __global__ __launch_bounds__(256) void k_fock(const double* __restrict__ Lov,
   }
   red[threadIdx.x] = v;
   __syncthreads();
-  if (js == 0 && c < nv)
-    F[(int64_t)k * nv + c] = (red[threadIdx.x] + red[threadIdx.x + 64]) +
-                             (red[threadIdx.x + 128] + red[threadIdx.x + 192]);
+  for (int h = NS / 2; h >= 1; h >>= 1) {
+    if (js < h) red[threadIdx.x] += red[threadIdx.x + 64 * h];
+    __syncthreads();
+  }
+  if (js == 0 && c < nv) F[(int64_t)k * nv + c] = red[threadIdx.x];
 }
 
 void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no, int nv, int nJ,
                  hipStream_t st) {
   hipLaunchKernelGGL(k_fock_sm, dim3(nJ), dim3(256), 0, st, t1, cs.Lov, cs.s, cs.M, no, nv);
-  hipLaunchKernelGGL(k_fock, dim3(no, nblk(nv, 64)), dim3(256), 0, st, cs.Lov, cs.s, cs.M, F, no,
+  hipLaunchKernelGGL(k_fock, dim3(no, nblk(nv, 64)), dim3(1024), 0, st, cs.Lov, cs.s, cs.M, F, no,
                      nv, nJ);
 }
 
@@ -170,32 +210,55 @@ void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no,
 // ---------------------------------------------------------------------------
 enum BuildKind { BUILD_PLAIN = 0, BUILD_JO = 1, BUILD_HS = 2, BUILD_GO = 3, BUILD_GW = 4 };
 
-typedef TileCfg<2, 2, 4, 4, 16> BuildCfg;
+typedef TileCfg<4, 2, 2, 4, 16> BuildCfg;  // 8 wavefronts, 128 x 128 tiles
 
-__global__ __launch_bounds__(BuildCfg::NT, 2) void k_build(
-    const double* __restrict__ Ap, int64_t a_sm, int64_t a_sk, int64_t a_bs,
-    const double* __restrict__ Bp, int64_t b_sk, int64_t b_sn, int64_t b_bs, int M, int N, int K,
-    double* __restrict__ C, int64_t c_bs, int kind, int no, int nv, const double* __restrict__ F) {
+// One product of a grouped build launch: C_z = A_z B_z for z < batch, with
+// A(m, J) at A[z * a_bs + m * a_sm + J * a_sk], B(J, n) at B[z * b_bs + J * b_sk + n * b_sn].
+struct BuildProb {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t a_sm, a_sk, a_bs, b_sk, b_sn, b_bs, c_bs;
+  int M, N, kind, batch;
+};
+enum { MAX_BUILD_PROBS = 6 };
+// The products of one launch, all with the same K; workgroups first0[p] ..
+// first0[p + 1] - 1 take the tiles of product p.
+struct BuildSet {
+  BuildProb p[MAX_BUILD_PROBS];
+  unsigned first0[MAX_BUILD_PROBS + 1];
+  int n, K, no, nv;
+  const double* F;
+};
+
+__global__ __launch_bounds__(BuildCfg::NT, 2) void k_build(const BuildSet set) {
   typedef BuildCfg T;
   __shared__ double lds[T::LDS_DOUBLES];
-  const int mt = (M + T::BM - 1) / T::BM;
-  const int m0 = (blockIdx.x % mt) * T::BM;
-  const int n0 = (blockIdx.x / mt) * T::BN;
-  const int z = blockIdx.z;
-  const double* A = Ap + (int64_t)z * a_bs;
-  const double* B = Bp + (int64_t)z * b_bs;
+  int pi = 0;
+  while (pi + 1 < set.n && blockIdx.x >= set.first0[pi + 1]) ++pi;
+  const BuildProb& pr = set.p[pi];
+  const int M = pr.M, N = pr.N, K = set.K, kind = pr.kind, no = set.no, nv = set.nv;
+  const int mt = (M + T::BM - 1) / T::BM, nt = (N + T::BN - 1) / T::BN;
+  const unsigned local = blockIdx.x - set.first0[pi];
+  const int z = (int)(local / (unsigned)(mt * nt));
+  const int t = (int)(local % (unsigned)(mt * nt));
+  const int m0 = (t % mt) * T::BM;
+  const int n0 = (t / mt) * T::BN;
+  const double* A = pr.A + (int64_t)z * pr.a_bs;
+  const double* B = pr.B + (int64_t)z * pr.b_bs;
   d4v acc[T::FM][T::FN];
   zero_acc<T>(acc);
   const int nsteps = (K + T::BK - 1) / T::BK;
   auto ops = [&](int s, Opnd& oa, Opnd& ob, int& k0) {
     k0 = s * T::BK;
-    oa = make_opnd(A, a_sm, a_sk, M, K, true);
-    ob = make_opnd(B, b_sn, b_sk, N, K, true);
+    oa = make_opnd(A, pr.a_sm, pr.a_sk, M, K, true);
+    ob = make_opnd(B, pr.b_sn, pr.b_sk, N, K, true);
   };
   k_loop<T>(nsteps, m0, n0, ops, acc, lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
-  double* Cz = C + (int64_t)z * c_bs;
+  double* Cz = pr.C + (int64_t)z * pr.c_bs;
+  const double* F = set.F;
 #pragma unroll
   for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
@@ -224,14 +287,24 @@ __global__ __launch_bounds__(BuildCfg::NT, 2) void k_build(
       }
 }
 
-static void build(const double* A, int64_t a_sm, int64_t a_sk, int64_t a_bs, const double* B,
-                  int64_t b_sk, int64_t b_sn, int64_t b_bs, int M, int N, int K, double* C,
-                  int64_t c_bs, int batch, int kind, int no, int nv, const double* F,
-                  hipStream_t st) {
+static void add_build(BuildSet& set, const double* A, int64_t a_sm, int64_t a_sk, int64_t a_bs,
+                      const double* B, int64_t b_sk, int64_t b_sn, int64_t b_bs, int M, int N,
+                      double* C, int64_t c_bs, int batch, int kind) {
+  BuildProb& p = set.p[set.n++];
+  p.A = A; p.a_sm = a_sm; p.a_sk = a_sk; p.a_bs = a_bs;
+  p.B = B; p.b_sk = b_sk; p.b_sn = b_sn; p.b_bs = b_bs;
+  p.C = C; p.c_bs = c_bs;
+  p.M = M; p.N = N; p.kind = kind; p.batch = batch;
+}
+
+static void launch_build_set(BuildSet& set, hipStream_t st) {
   typedef BuildCfg T;
-  const unsigned mt = nblk(M, T::BM), nt = nblk(N, T::BN);
-  hipLaunchKernelGGL(k_build, dim3(mt * nt, 1, batch), dim3(T::NT), 0, st, A, a_sm, a_sk, a_bs, B,
-                     b_sk, b_sn, b_bs, M, N, K, C, c_bs, kind, no, nv, F);
+  set.first0[0] = 0;
+  for (int i = 0; i < set.n; ++i) {
+    const BuildProb& p = set.p[i];
+    set.first0[i + 1] = set.first0[i] + nblk(p.M, T::BM) * nblk(p.N, T::BN) * (unsigned)p.batch;
+  }
+  hipLaunchKernelGGL(k_build, dim3(set.first0[set.n]), dim3(T::NT), 0, st, set);
 }
 
 // Gcb[r][n][c][b] = Gbc[r][n][b][c]: nv x nv transposes, one per (r, n), through
@@ -267,25 +340,26 @@ void launch_build_blocks(const CholeskyScratch& cs, const Blocks& bl, int no, in
                          hipStream_t st) {
   const int64_t nv2 = (int64_t)nv * nv, nv3 = nv2 * nv, onv = (int64_t)no * nv;
   const int64_t gs = (int64_t)(nv + no) * nv2;  // one r slab of Gbc / Gcb
+  // all six products share K = nJ: one launch, the large ones first
+  BuildSet set = {};
+  set.K = nJ; set.no = no; set.nv = nv; set.F = bl.F;
   // Gw[r][y][z][d] = sum_J LvoT[J][r][z] Lvv[J][(y,d)]   (rows z, columns (y,d), batch r)
-  build(cs.LvoT, 1, onv, nv, cs.Lvv, nv2, 1, 0, nv, (int)nv2, nJ, bl.Gw, nv3, no, BUILD_GW, no,
-        nv, nullptr, st);
+  add_build(set, cs.LvoT, 1, onv, nv, cs.Lvv, nv2, 1, 0, nv, (int)nv2, bl.Gw, nv3, no, BUILD_GW);
   // Gbc[r][(d,b)][c] = sum_J Lvv[J][(d,b)] Lov[J][r][c]            (rows n = d < nv)
-  build(cs.Lvv, 1, nv2, 0, cs.Lov, onv, 1, nv, (int)nv2, nv, nJ, bl.Gbc, gs, no, BUILD_PLAIN, no,
-        nv, nullptr, st);
+  add_build(set, cs.Lvv, 1, nv2, 0, cs.Lov, onv, 1, nv, (int)nv2, nv, bl.Gbc, gs, no, BUILD_PLAIN);
   // Gbc[r][nv + (l,b)][c] = sum_J Lov[J][(l,b)] Lov[J][r][c]      (rows n = nv + l)
-  build(cs.Lov, 1, onv, 0, cs.Lov, onv, 1, nv, (int)onv, nv, nJ, bl.Gbc + nv3, gs, no,
-        BUILD_PLAIN, no, nv, nullptr, st);
-  launch_gcb(bl, no, nv, st);
+  add_build(set, cs.Lov, 1, onv, 0, cs.Lov, onv, 1, nv, (int)onv, nv, bl.Gbc + nv3, gs, no,
+            BUILD_PLAIN);
   // Jo[q][r][b][c] = sum_J Lov[J][q][b] Lov[J][r][c]
-  build(cs.Lov, 1, onv, 0, cs.Lov, onv, 1, 0, (int)onv, (int)onv, nJ, bl.Jo, 0, 1, BUILD_JO, no,
-        nv, nullptr, st);
+  add_build(set, cs.Lov, 1, onv, 0, cs.Lov, onv, 1, 0, (int)onv, (int)onv, bl.Jo, 0, 1, BUILD_JO);
   // Hs[q][r][c][l] = delta_lq F[r][c] - sum_J Loo[J][q][l] Lov[J][r][c]
-  build(cs.Loo, 1, (int64_t)no * no, 0, cs.Lov, onv, 1, 0, no * no, (int)onv, nJ, bl.Hs, 0, 1,
-        BUILD_HS, no, nv, bl.F, st);
+  add_build(set, cs.Loo, 1, (int64_t)no * no, 0, cs.Lov, onv, 1, 0, no * no, (int)onv, bl.Hs, 0,
+            1, BUILD_HS);
   // Go[q][r][z][l] = sum_J LooT[J][q][l] LvoT[J][r][z]   (LooT[J][q][l] = Lt_lq)
-  build(cs.LooT, 1, (int64_t)no * no, 0, cs.LvoT, onv, 1, 0, no * no, (int)onv, nJ, bl.Go, 0, 1,
-        BUILD_GO, no, nv, nullptr, st);
+  add_build(set, cs.LooT, 1, (int64_t)no * no, 0, cs.LvoT, onv, 1, 0, no * no, (int)onv, bl.Go, 0,
+            1, BUILD_GO);
+  launch_build_set(set, st);
+  launch_gcb(bl, no, nv, st);
 }
 
 // ---------------------------------------------------------------------------
