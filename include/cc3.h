@@ -14,13 +14,20 @@
  * Conventions shared by every entry point
  *   - Return value: CC3_OK (0) or a negative CC3_E_* code; cc3_last_error()
  *     then returns a thread-local message describing the failure.
- *   - Unless stated otherwise, array pointers are DEVICE pointers (memory of
- *     the context's GPU, e.g. torch CUDA tensors or hipMalloc), row-major,
- *     float64, owned by the caller.  The library keeps no pointer after the
+ *   - Array pointers are row-major float64 arrays owned by the caller.  The
+ *     one-shot residual calls (cc3_triples_residual, cc3_triples_residual_blocks,
+ *     cc3_triples_residual_subset, cc3_t3_block) take device memory of the
+ *     context's GPU (torch CUDA tensors, hipMalloc) or host memory, pageable or
+ *     pinned, told apart with hipPointerGetAttributes: a host input is copied on
+ *     `stream` into the workspace, a host output is produced there and copied
+ *     back.  cc3_jacobian_prep takes device pointers only (its outputs are as
+ *     large as the integral blocks).  The library keeps no pointer after the
  *     work it enqueued has completed.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
  *     and the call returns without waiting for it; results are valid once the
- *     stream has reached that point.
+ *     stream has reached that point.  A call with any host-memory argument
+ *     waits for its stream before it returns (its host outputs are then final
+ *     and its host inputs may be reused).
  *   - Index order: occupied orbitals first.  eps[no+nv]; L[nchol][nmo][nmo]
  *     (nmo = no+nv, symmetric in the last two indices); t1[no][nv] = t^a_i;
  *     t2[no][no][nv][nv] = t^{ab}_{ij} with t2[i][j][a][b] == t2[j][i][b][a];
@@ -45,7 +52,8 @@ typedef void* cc3_stream_t; /* hipStream_t */
 /* status codes */
 enum {
   CC3_OK = 0,
-  CC3_E_INVAL = -1,    /* bad argument: sizes, null or host pointer, unknown enum */
+  CC3_E_INVAL = -1,    /* bad argument: sizes, null pointer, host pointer where only device
+                          memory is accepted, unknown enum */
   CC3_E_NOMEM = -2,    /* workspace (or arena) too small for the request */
   CC3_E_DEVICE = -3,   /* a HIP runtime call failed */
   CC3_E_PRECOND = -4,  /* CC3_CHECK found a violated input symmetry or denominator */
@@ -121,8 +129,8 @@ int cc3_workspace_size(int no, int nv, int nchol, int prec, unsigned flags, size
  * canonical reference).  The integral blocks stay resident in the workspace
  * for the whole call.
  *
- * Inputs (device): eps[no+nv], L[nchol][nmo][nmo], t1[no][nv], t2[no][no][nv][nv].
- * Outputs (device): omega1[no][nv], omega2[no][no][nv][nv]: the covariant
+ * Inputs (device or host): eps[no+nv], L[nchol][nmo][nmo], t1[no][nv], t2[no][no][nv][nv].
+ * Outputs (device or host): omega1[no][nv], omega2[no][no][nv][nv]: the covariant
  * triples contribution  Omega^a_i = Ot^a_i,
  * Omega^{ab}_{ij} = 1/3 [(2 Ot^{ab}_{ij} + Ot^{ba}_{ij}) + (2 Ot^{ba}_{ji} + Ot^{ab}_{ji})],
  * written (or added, with CC3_ACCUMULATE).
@@ -136,7 +144,8 @@ int cc3_triples_residual(cc3_ctx* ctx, int no, int nv, int nchol, const double* 
                          size_t workspace_bytes, cc3_stream_t stream);
 
 /* The same residual from integral blocks already in the T1-transformed basis,
- * laid out in the paper's index order (device, row-major):
+ * laid out in the paper's index order (device or host, row-major; host
+ * g_vvvo and g_vvov pass through the workspace in slabs of the first index):
  *   g_vvvo[b][d][c][k] = g_{bdck},  g_oovo[l][j][c][k] = g_{ljck},
  *   g_ovov[j][b][k][c] = g_{jbkc},  g_ooov[j][l][k][c] = g_{jlkc},
  *   g_vvov[d][b][k][c] = g_{dbkc},  F_ov[k][c] = F_{kc}.
@@ -155,7 +164,8 @@ int cc3_triples_residual_blocks(cc3_ctx* ctx, int no, int nv, const double* eps,
  *   Ot2[p][l][a][b] -= sum_c U^{abc} g_{qlrc};  Ot2[p][q][a][d] += sum_bc U^{abc} g_{dbrc}.
  * triples: HOST int32 array [ntriples][3] with i >= j >= k, not all equal, each
  * < no (copied before the call returns).  omega1_tilde[no][nv] and
- * omega2_tilde[no][no][nv][nv] (device) are overwritten.  Used for sampled
+ * omega2_tilde[no][no][nv][nv] (device or host) are overwritten; the call waits
+ * for its stream before it returns.  Used for sampled
  * parity at large sizes and to emulate a triple-partitioned multi-GPU run.
  * Workspace as for cc3_triples_residual.  Errors: CC3_E_INVAL (bad triple),
  * CC3_E_NOMEM, CC3_E_DEVICE. */
@@ -167,7 +177,8 @@ int cc3_triples_residual_subset(cc3_ctx* ctx, int no, int nv, int nchol, const d
 
 /* Debug export of the t3 amplitudes of one ordered triple (i, j, k) (any order,
  * not all equal): tau[a][b][c] = tau^{abc}_{ijk} = -(eps^{abc}_{ijk})^{-1} P^{abc}_{ijk} B^{abc}_{ijk}
- * (Algorithm 1, first statement), written to the device array tau[nv][nv][nv].
+ * (Algorithm 1, first statement), written to tau[nv][nv][nv] (device or host); the
+ * call waits for its stream before it returns.
  * Inputs as for cc3_triples_residual.  Errors: CC3_E_INVAL, CC3_E_NOMEM, CC3_E_DEVICE. */
 int cc3_t3_block(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps, const double* L,
                  const double* t1, const double* t2, int i, int j, int k, double* tau, int prec,

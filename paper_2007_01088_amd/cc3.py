@@ -206,9 +206,10 @@ class Context:
             omega2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=t2.device)
         nbytes = workspace_size(no, nv, nchol, prec, flags)
         ws = self.workspace(nbytes)
-        _check(_residual(self._h, no, nv, nchol, _ptr(eps, "eps"), _ptr(L, "L"), _ptr(t1, "t1"),
-                         _ptr(t2, "t2"), _ptr(omega1, "omega1"), _ptr(omega2, "omega2"), prec,
-                         flags, ws.data_ptr(), ws.numel(), _stream(stream)),
+        _check(_residual(self._h, no, nv, nchol, _any_ptr(eps, "eps"), _any_ptr(L, "L"),
+                         _any_ptr(t1, "t1"), _any_ptr(t2, "t2"), _any_ptr(omega1, "omega1"),
+                         _any_ptr(omega2, "omega2"), prec, flags, ws.data_ptr(), ws.numel(),
+                         _stream(stream)),
                "cc3_triples_residual")
         return omega1, omega2
 
@@ -221,12 +222,13 @@ class Context:
             omega2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=t2.device)
         nbytes = workspace_size(no, nv, 0, prec, flags)
         ws = self.workspace(nbytes)
-        _check(_residual_blocks(self._h, no, nv, _ptr(eps, "eps"), _ptr(g_vvvo, "g_vvvo"),
-                                _ptr(g_oovo, "g_oovo"), _ptr(g_ovov, "g_ovov"),
-                                _ptr(g_ooov, "g_ooov"), _ptr(g_vvov, "g_vvov"),
-                                _ptr(F_ov, "F_ov"), _ptr(t2, "t2"), _ptr(omega1, "omega1"),
-                                _ptr(omega2, "omega2"), prec, flags, ws.data_ptr(), ws.numel(),
-                                _stream(stream)), "cc3_triples_residual_blocks")
+        _check(_residual_blocks(self._h, no, nv, _any_ptr(eps, "eps"), _any_ptr(g_vvvo, "g_vvvo"),
+                                _any_ptr(g_oovo, "g_oovo"), _any_ptr(g_ovov, "g_ovov"),
+                                _any_ptr(g_ooov, "g_ooov"), _any_ptr(g_vvov, "g_vvov"),
+                                _any_ptr(F_ov, "F_ov"), _any_ptr(t2, "t2"),
+                                _any_ptr(omega1, "omega1"), _any_ptr(omega2, "omega2"), prec,
+                                flags, ws.data_ptr(), ws.numel(), _stream(stream)),
+               "cc3_triples_residual_blocks")
         return omega1, omega2
 
     def triples_residual_subset(self, eps, L, t1, t2, triples, prec=FP64, flags=0, stream=None):
@@ -239,10 +241,10 @@ class Context:
         o2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=t2.device)
         nbytes = workspace_size(no, nv, nchol, prec, flags)
         ws = self.workspace(nbytes)
-        _check(_residual_subset(self._h, no, nv, nchol, _ptr(eps, "eps"), _ptr(L, "L"),
-                                _ptr(t1, "t1"), _ptr(t2, "t2"),
+        _check(_residual_subset(self._h, no, nv, nchol, _any_ptr(eps, "eps"), _any_ptr(L, "L"),
+                                _any_ptr(t1, "t1"), _any_ptr(t2, "t2"),
                                 tri.ctypes.data_as(ctypes.c_void_p), int(tri.shape[0]),
-                                _ptr(o1, "o1"), _ptr(o2, "o2"), prec, flags, ws.data_ptr(),
+                                _any_ptr(o1, "o1"), _any_ptr(o2, "o2"), prec, flags, ws.data_ptr(),
                                 ws.numel(), _stream(stream)), "cc3_triples_residual_subset")
         return o1, o2
 
@@ -252,9 +254,9 @@ class Context:
         tau = torch.empty((nv, nv, nv), dtype=torch.float64, device=t2.device)
         nbytes = workspace_size(no, nv, nchol, prec, 0)
         ws = self.workspace(nbytes)
-        _check(_t3_block(self._h, no, nv, nchol, _ptr(eps, "eps"), _ptr(L, "L"), _ptr(t1, "t1"),
-                         _ptr(t2, "t2"), i, j, k, _ptr(tau, "tau"), prec, ws.data_ptr(),
-                         ws.numel(), _stream(stream)), "cc3_t3_block")
+        _check(_t3_block(self._h, no, nv, nchol, _any_ptr(eps, "eps"), _any_ptr(L, "L"),
+                         _any_ptr(t1, "t1"), _any_ptr(t2, "t2"), i, j, k, _any_ptr(tau, "tau"),
+                         prec, ws.data_ptr(), ws.numel(), _stream(stream)), "cc3_t3_block")
         return tau
 
     def jacobian_prep(self, eps, L, t1, t2, zv=None, zo=None, prec=FP64, flags=0, stream=None):

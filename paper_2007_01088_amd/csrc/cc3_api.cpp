@@ -3,6 +3,9 @@
 // evaluation on the caller's stream (Algorithm 1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
+#include <initializer_list>
 #include <mutex>
 #include <vector>
 
@@ -112,6 +115,69 @@ extern "C" int cc3_cvs_triples(int no, const int32_t* core, int ncore, int32_t* 
   return CC3_OK;
 }
 
+// Host-memory arguments of the one-shot calls.  An input in host memory is
+// copied on the call's stream into a workspace staging area, and the kernels read
+// the copy; an output in host memory is produced in a staging area and copied
+// back, and the call then waits for its stream, so that the caller's host
+// buffers hold the results (and may be reused) when it returns.
+struct HostArgs {
+  struct Out {
+    double* dev;   // where the kernels write
+    double* host;  // the caller's host buffer, or null for device memory
+    size_t n;
+  };
+  hipStream_t st;
+  bool any = false;
+  // On return `p` points at device memory holding the input.
+  int in(const double*& p, const char* what, double* stage, size_t n) {
+    bool host = false;
+    int rc = classify_ptr(p, what, &host);
+    if (rc || !host) return rc;
+    HIPCHK(hipMemcpyAsync(stage, p, n * sizeof(double), hipMemcpyHostToDevice, st));
+    p = stage;
+    any = true;
+    return CC3_OK;
+  }
+  int out(double* p, const char* what, double* stage, size_t n, Out& o) {
+    bool host = false;
+    int rc = classify_ptr(p, what, &host);
+    if (rc) return rc;
+    o.n = n;
+    o.host = host ? p : nullptr;
+    o.dev = host ? stage : p;
+    any = any || host;
+    return CC3_OK;
+  }
+  // the caller's current values, for CC3_ACCUMULATE into a host output
+  int preload(const Out& o) {
+    if (o.host) HIPCHK(hipMemcpyAsync(o.dev, o.host, o.n * sizeof(double), hipMemcpyHostToDevice, st));
+    return CC3_OK;
+  }
+  int finish(std::initializer_list<const Out*> outs) {
+    for (const Out* o : outs)
+      if (o->host)
+        HIPCHK(hipMemcpyAsync(o->host, o->dev, o->n * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (any) HIPCHK(hipStreamSynchronize(st));
+    return CC3_OK;
+  }
+};
+
+// Staging area of a host L: the cube region after the Cholesky scratch.
+static double* stage_L(const Plan& p, void* ws) {
+  return (double*)((char*)ws + p.off_cubes + p.chol_bytes);
+}
+
+// eps, L (Cholesky form only), t1 and t2 onto the device.
+static int stage_inputs(HostArgs& h, const Plan& p, const Ws& w, void* ws, const double*& eps,
+                        const double*& L, const double*& t1, const double*& t2) {
+  const size_t o = p.no, v = p.nv, J = p.nchol;
+  int rc;
+  if ((rc = h.in(eps, "eps", w.st_eps, o + v))) return rc;
+  if (J && (rc = h.in(L, "L", stage_L(p, ws), J * (o + v) * (o + v)))) return rc;
+  if (t1 && (rc = h.in(t1, "t1", w.st_t1, o * v))) return rc;
+  return h.in(t2, "t2", w.st_t2, o * o * v * v);
+}
+
 static int common_checks(cc3_ctx* c, int no, int nv, int nchol, int prec, unsigned flags,
                          void* ws, size_t ws_bytes, Plan* p) {
   if (!c) return fail(CC3_E_INVAL, "ctx is NULL");
@@ -139,17 +205,23 @@ extern "C" int cc3_triples_residual(cc3_ctx* c, int no, int nv, int nchol, const
   int rc = common_checks(c, no, nv, nchol, prec, flags, ws, ws_bytes, &p);
   if (rc) return rc;
   if (nchol < 1) return fail(CC3_E_INVAL, "nchol must be >= 1 for the Cholesky form");
-  const void* ptrs[] = {eps, L, t1, t2, omega1, omega2};
-  const char* names[] = {"eps", "L", "t1", "t2", "omega1", "omega2"};
-  for (int i = 0; i < 6; ++i)
-    if ((rc = check_dev_ptr(ptrs[i], names[i]))) return rc;
   hipStream_t st = (hipStream_t)stream;
   Ws w = carve(p, ws, nullptr);
+  const size_t o = no, v = nv;
+  const bool acc = (flags & CC3_ACCUMULATE) != 0;
   std::lock_guard<std::mutex> g(c->mu);
+  HostArgs h{st};
+  HostArgs::Out O1, O2;
+  if ((rc = stage_inputs(h, p, w, ws, eps, L, t1, t2))) return rc;
+  if ((rc = h.out(omega1, "omega1", w.st_o1, o * v, O1))) return rc;
+  if ((rc = h.out(omega2, "omega2", w.t2N, o * o * v * v, O2))) return rc;  // t2N is free by then
+  if (acc && (rc = h.preload(O1))) return rc;
   if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, L, t2, st))) return rc;
   if ((rc = prepare_cholesky(&c->prof, p, w, L, t1, st))) return rc;
-  return residual_from_blocks(c->run, &c->prof, p, w, eps, t2, omega1, omega2,
-                              (flags & CC3_ACCUMULATE) != 0, st);
+  if ((rc = residual_from_blocks(c->run, &c->prof, p, w, eps, t2, O1.dev, O2.dev, acc, st,
+                                 acc ? O2.host : nullptr)))
+    return rc;
+  return h.finish({&O1, &O2});
 }
 
 extern "C" int cc3_triples_residual_blocks(cc3_ctx* c, int no, int nv, const double* eps,
@@ -162,21 +234,67 @@ extern "C" int cc3_triples_residual_blocks(cc3_ctx* c, int no, int nv, const dou
   Plan p;
   int rc = common_checks(c, no, nv, 0, prec, flags, ws, ws_bytes, &p);
   if (rc) return rc;
-  const void* ptrs[] = {eps, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov, t2, omega1, omega2};
-  const char* names[] = {"eps", "g_vvvo", "g_oovo", "g_ovov", "g_ooov",
-                         "g_vvov", "F_ov", "t2", "omega1", "omega2"};
-  for (int i = 0; i < 10; ++i)
-    if ((rc = check_dev_ptr(ptrs[i], names[i]))) return rc;
   hipStream_t st = (hipStream_t)stream;
   Ws w = carve(p, ws, nullptr);
+  const size_t o = no, v = nv;
+  const bool acc = (flags & CC3_ACCUMULATE) != 0;
   std::lock_guard<std::mutex> g(c->mu);
+  HostArgs h{st};
+  HostArgs::Out O1, O2;
+  const double* none = nullptr;
+  if ((rc = stage_inputs(h, p, w, ws, eps, none, none, t2))) return rc;
+  if ((rc = h.out(omega1, "omega1", w.st_o1, o * v, O1))) return rc;
+  if ((rc = h.out(omega2, "omega2", w.t2N, o * o * v * v, O2))) return rc;
+  if (acc && (rc = h.preload(O1))) return rc;
   if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, nullptr, t2, st))) return rc;
   {
     Timer tm(&c->prof, st, FAM_BUILD, 0.0, 0.0);
-    launch_relayout_blocks(g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov, w.b, no, nv, st);
+    // host blocks pass through the cube region: the small ones whole, then
+    // slabs of the first virtual index of g_vvvo and g_vvov
+    char* cr = (char*)ws + p.off_cubes;
+    const size_t b3 = (o * o * o * v * 8 + 255) & ~(size_t)255;
+    const size_t b2 = (o * o * v * v * 8 + 255) & ~(size_t)255;
+    const size_t b1 = (o * v * 8 + 255) & ~(size_t)255;
+    if ((rc = h.in(g_oovo, "g_oovo", (double*)cr, o * o * o * v))) return rc;
+    if ((rc = h.in(g_ooov, "g_ooov", (double*)(cr + b3), o * o * o * v))) return rc;
+    if ((rc = h.in(g_ovov, "g_ovov", (double*)(cr + 2 * b3), o * o * v * v))) return rc;
+    if ((rc = h.in(F_ov, "F_ov", (double*)(cr + 2 * b3 + b2), o * v))) return rc;
+    launch_relayout_small(g_oovo, g_ovov, g_ooov, F_ov, w.b, no, nv, st);
+    bool hv = false, hw = false;
+    if ((rc = classify_ptr(g_vvvo, "g_vvvo", &hv)) || (rc = classify_ptr(g_vvov, "g_vvov", &hw)))
+      return rc;
+    const size_t slab = o * v * v;  // doubles per first index of g_vvvo and g_vvov
+    int ny = nv;
+    if (hv || hw) {
+      const size_t small = 2 * b3 + b2 + b1, region = p.total - p.off_cubes;
+      const size_t fit = (region - small) / (2 * ((slab * 8 + 255) & ~(size_t)255));
+      ny = (int)std::max<size_t>(1, std::min<size_t>(nv, fit));
+      const char* cap = getenv("CC3_STAGE_Y");  // smaller slabs (tests of the staging)
+      if (cap && atoi(cap) > 0) ny = std::min(ny, atoi(cap));
+    }
+    double* sa = (double*)(cr + 2 * b3 + b2 + b1);
+    double* sb = sa + (size_t)ny * slab;
+    for (int y0 = 0; y0 < nv; y0 += ny) {
+      const int n = std::min(ny, nv - y0);
+      const double* a = g_vvvo + (size_t)y0 * slab;
+      const double* b = g_vvov + (size_t)y0 * slab;
+      if (hv) {
+        HIPCHK(hipMemcpyAsync(sa, a, n * slab * 8, hipMemcpyHostToDevice, st));
+        a = sa;
+      }
+      if (hw) {
+        HIPCHK(hipMemcpyAsync(sb, b, n * slab * 8, hipMemcpyHostToDevice, st));
+        b = sb;
+      }
+      launch_relayout_vv(a, b, y0, n, w.b, no, nv, st);
+    }
+    h.any = h.any || hv || hw;
+    launch_gcb(w.b, no, nv, st);
   }
-  return residual_from_blocks(c->run, &c->prof, p, w, eps, t2, omega1, omega2,
-                              (flags & CC3_ACCUMULATE) != 0, st);
+  if ((rc = residual_from_blocks(c->run, &c->prof, p, w, eps, t2, O1.dev, O2.dev, acc, st,
+                                 acc ? O2.host : nullptr)))
+    return rc;
+  return h.finish({&O1, &O2});
 }
 
 extern "C" int cc3_triples_residual_subset(cc3_ctx* c, int no, int nv, int nchol,
@@ -198,13 +316,14 @@ extern "C" int cc3_triples_residual_subset(cc3_ctx* c, int no, int nv, int nchol
       return fail(CC3_E_INVAL, "triple %d = (%d,%d,%d) is not an unordered triple i>=j>=k "
                   "(not all equal) below no=%d", t, i, j, k, no);
   }
-  const void* ptrs[] = {eps, L, t1, t2, omega1_tilde, omega2_tilde};
-  const char* names[] = {"eps", "L", "t1", "t2", "omega1_tilde", "omega2_tilde"};
-  for (int i = 0; i < 6; ++i)
-    if ((rc = check_dev_ptr(ptrs[i], names[i]))) return rc;
   hipStream_t st = (hipStream_t)stream;
   Ws w = carve(p, ws, nullptr);
   std::lock_guard<std::mutex> g(c->mu);
+  HostArgs h{st};
+  HostArgs::Out O1, O2;
+  if ((rc = stage_inputs(h, p, w, ws, eps, L, t1, t2))) return rc;
+  if ((rc = h.out(omega1_tilde, "omega1_tilde", w.st_o1, (size_t)no * nv, O1))) return rc;
+  if ((rc = h.out(omega2_tilde, "omega2_tilde", w.t2N, (size_t)no * no * nv * nv, O2))) return rc;
   if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, L, t2, st))) return rc;
   if ((rc = prepare_cholesky(&c->prof, p, w, L, t1, st))) return rc;
   launch_fill(w.Ot1, (int64_t)no * nv, 0.0, st);
@@ -216,9 +335,10 @@ extern "C" int cc3_triples_residual_subset(cc3_ctx* c, int no, int nv, int nchol
     if ((rc = triple_loop(c->run, &c->prof, p, w, eps, t2, w.tri, triples, ntriples, st)))
       return rc;
   }
-  launch_combine(w.Ot1, w.Ot2, w.OtT, omega1_tilde, omega2_tilde, no, nv, st);
+  launch_combine(w.Ot1, w.Ot2, w.OtT, O1.dev, O2.dev, no, nv, st);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
+  if ((rc = h.finish({&O1, &O2}))) return rc;
+  HIPCHK(hipStreamSynchronize(st));  // the host triples were copied on st
   return CC3_OK;
 }
 
@@ -233,13 +353,14 @@ extern "C" int cc3_t3_block(cc3_ctx* c, int no, int nv, int nchol, const double*
   if (i < 0 || j < 0 || k < 0 || i >= no || j >= no || k >= no || (i == j && j == k))
     return fail(CC3_E_INVAL, "(%d,%d,%d) is not an ordered triple of distinct-enough indices < %d",
                 i, j, k, no);
-  const void* ptrs[] = {eps, L, t1, t2, tau};
-  const char* names[] = {"eps", "L", "t1", "t2", "tau"};
-  for (int a = 0; a < 5; ++a)
-    if ((rc = check_dev_ptr(ptrs[a], names[a]))) return rc;
   hipStream_t st = (hipStream_t)stream;
   Ws w = carve(p, ws, nullptr);
   std::lock_guard<std::mutex> g(c->mu);
+  HostArgs hs{st};
+  HostArgs::Out T;
+  if ((rc = stage_inputs(hs, p, w, ws, eps, L, t1, t2))) return rc;
+  // a host tau is produced in the second cube buffer set, unused by this call
+  if ((rc = hs.out(tau, "tau", w.cubes[1], (size_t)nv * nv * nv, T))) return rc;
   if ((rc = prepare_cholesky(&c->prof, p, w, L, t1, st))) return rc;
   const int h[3] = {i, j, k};
   HIPCHK(hipMemcpyAsync(w.tri, h, sizeof h, hipMemcpyHostToDevice, st));
@@ -250,8 +371,9 @@ extern "C" int cc3_t3_block(cc3_ctx* c, int no, int nv, int nchol, const double*
     launch_lp_convert(t2, w.b, no, nv, w.lp, st);
     launch_wbuild_lp(w.lp, w.tri, 1, w.cubes[0], no, nv, true, st);
   }
-  launch_tau_export(eps, w.tri, w.cubes[0], tau, no, nv, st);
+  launch_tau_export(eps, w.tri, w.cubes[0], T.dev, no, nv, st);
   HIPCHK(hipGetLastError());
+  if ((rc = hs.finish({&T}))) return rc;
   HIPCHK(hipStreamSynchronize(st));
   return CC3_OK;
 }

@@ -53,6 +53,18 @@ int check_dev_ptr(const void* p, const char* what) {
   return CC3_OK;
 }
 
+int classify_ptr(const void* p, const char* what, bool* host) {
+  if (!p) return fail(CC3_E_INVAL, "%s is NULL", what);
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // unregistered (pageable) host memory
+    *host = true;
+    return CC3_OK;
+  }
+  *host = !(a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged);
+  return CC3_OK;
+}
+
 // ---------------------------------------------------------------------------
 // kernel timing
 // ---------------------------------------------------------------------------
@@ -238,7 +250,19 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
                           align256(J * o * v * 8) * 2 + align256(J * 8) + align256(J * o * o * 8)
                     : 0;
   p->cube_bytes = align256((size_t)batch * 5 * p->cube * 8);
-  p->off_cubes = take(std::max(p->chol_bytes, 2 * p->cube_bytes));
+  size_t region = std::max(p->chol_bytes, 2 * p->cube_bytes);
+  if (with_blocks) {
+    const size_t nmo = o + v;
+    p->off_stage = take(align256(nmo * 8) + 2 * align256(o * v * 8) + align256(o * o * v * v * 8));
+    // setup-time staging in the cube region: a host L after the Cholesky scratch,
+    // or the small host blocks plus one y slab of g_vvvo and of g_vvov
+    const size_t small = 2 * align256(o * o * o * v * 8) + align256(o * o * v * v * 8) +
+                         align256(o * v * 8);
+    p->stage_region = std::max(p->chol_bytes + align256(J * nmo * nmo * 8),
+                               small + 2 * align256(o * v * v * 8));
+    region = std::max(region, p->stage_region);
+  }
+  p->off_cubes = take(region);
   p->off_chol = p->off_cubes;
   p->total = off;
   return CC3_OK;
@@ -265,6 +289,15 @@ Ws carve(const Plan& p, void* ws, const Blocks* external_blocks) {
   }
   w.tri = (int*)(base + p.off_tri);
   w.flag = (int*)(base + p.off_flag);
+  w.st_eps = w.st_t1 = w.st_t2 = w.st_o1 = nullptr;
+  if (p.stage_region) {
+    const size_t o = p.no, v = p.nv;
+    char* s = base + p.off_stage;
+    w.st_eps = (double*)s; s += align256((o + v) * 8);
+    w.st_t1 = (double*)s; s += align256(o * v * 8);
+    w.st_o1 = (double*)s; s += align256(o * v * 8);
+    w.st_t2 = (double*)s;
+  }
   const size_t J = p.nchol, o = p.no, v = p.nv;
   char* c = base + p.off_chol;
   size_t off = 0;
@@ -400,7 +433,7 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
 
 int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const double* eps,
                          const double* t2, double* omega1, double* omega2, bool accumulate,
-                         hipStream_t st) {
+                         hipStream_t st, const double* omega2_in) {
   const int no = p.no, nv = p.nv;
   launch_fill(w.Ot1, (int64_t)no * nv, 0.0, st);
   launch_fill(w.Ot2, (int64_t)no * no * nv * nv, 0.0, st);
@@ -410,6 +443,9 @@ int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, c
   host_triples(no, nbatches(p), ht);
   int rc = triple_loop(rn, pf, p, w, eps, t2, w.tri, ht.data(), p.ntri, st);
   if (rc) return rc;
+  if (omega2_in)
+    HIPCHK(hipMemcpyAsync(omega2, omega2_in, sizeof(double) * no * no * nv * nv,
+                          hipMemcpyHostToDevice, st));
   {
     Timer tm(pf, st, FAM_BACK, 0.0, 0.0);
     launch_back_transform(w.Ot1, w.Ot2, w.OtT, omega1, omega2, no, nv, accumulate, st);

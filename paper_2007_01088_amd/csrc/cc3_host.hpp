@@ -26,6 +26,9 @@ const char* last_error_str();  // this thread's last message
 
 int check_sizes(int no, int nv, int nchol, int prec);
 int check_dev_ptr(const void* p, const char* what);
+// Non-null check plus the memory kind: *host = false for device (or managed)
+// memory, true for host memory, pageable or pinned.
+int classify_ptr(const void* p, const char* what, bool* host);
 
 // ---- kernel timing ------------------------------------------------------------
 enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_REDUCE, FAM_BACK, FAM_ZPREP, FAM_OMEGA_OO, NFAM };
@@ -86,6 +89,8 @@ struct Ws {
   int* tri;
   int* flag;
   LpOperands lp;
+  // one-shot calls: staging areas of host-memory eps, t1, t2, omega1 (null otherwise)
+  double *st_eps, *st_t1, *st_t2, *st_o1;
 };
 
 // `with_blocks`: the integral blocks live in the workspace (one-shot calls) or
@@ -103,9 +108,11 @@ int prepare_cholesky(Profiler* pf, const Plan& p, const Ws& w, const double* L, 
 int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const double* eps,
                 const double* t2, const int* tri, const int* ht, int n, hipStream_t st);
 // Ot <- 0, the whole restricted loop, back-transformation into (omega1, omega2).
+// `omega2_in`, when given, is host memory copied into omega2 just before the
+// back-transformation (CC3_ACCUMULATE into host outputs staged in t2N).
 int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const double* eps,
                          const double* t2, double* omega1, double* omega2, bool accumulate,
-                         hipStream_t st);
+                         hipStream_t st, const double* omega2_in = nullptr);
 // Algorithm 2: zv[a][b][i][d] = Z~v_{abid}, zo[a][j][i][l] = Z~o_{ajil} (zeroed first
 // unless accumulate), over every unordered triple.
 int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w,

@@ -84,6 +84,10 @@ struct Plan {
   size_t off_gf, gf_bytes;        // mixed-all: low-precision Gbc and Gcb (0 bytes otherwise)
   size_t off_cubef, cubef_bytes;  // mixed-all: low-precision views of tau~, per buffer set
   size_t off_chol;  // Cholesky scratch (aliases the cube region)
+  // one-shot calls only (0 otherwise): staging of host-memory arguments, eps, t1, t2
+  // and omega1 at off_stage; a host L, or the host integral blocks, pass through
+  // the cube region during setup (stage_region bytes from off_cubes)
+  size_t off_stage, stage_region;
   size_t chol_bytes, cube_bytes, pvv_bytes;  // per buffer set (two sets)
   size_t total;
 };
@@ -109,9 +113,15 @@ void launch_fock(const double* t1, const CholeskyScratch& cs, double* F, int no,
                  hipStream_t st);
 void launch_build_blocks(const CholeskyScratch& cs, const Blocks& b, int no, int nv, int nJ,
                          hipStream_t st);
-void launch_relayout_blocks(const double* g_vvvo, const double* g_oovo, const double* g_ovov,
-                            const double* g_ooov, const double* g_vvov, const double* F_ov,
-                            const Blocks& b, int no, int nv, hipStream_t st);
+// The paper-order blocks into the internal layouts, in three parts: the
+// (oo|vo), (ov|ov), (oo|ov) and Fock blocks; the (vv|vo) and (vv|ov) blocks for
+// the first virtual index y in [y0, y0 + ny), read from g_vvvo_y = &g_vvvo[y0][0][0][0]
+// and g_vvov_y = &g_vvov[y0][0][0][0]; then the (c, b) copy of Gbc (launch_gcb).
+void launch_relayout_small(const double* g_oovo, const double* g_ovov, const double* g_ooov,
+                           const double* F_ov, const Blocks& b, int no, int nv, hipStream_t st);
+void launch_relayout_vv(const double* g_vvvo_y, const double* g_vvov_y, int y0, int ny,
+                        const Blocks& b, int no, int nv, hipStream_t st);
+void launch_gcb(const Blocks& b, int no, int nv, hipStream_t st);
 // The full triple table, the restricted loop dealt round-robin over nbatch batches.
 void launch_triple_table(int* tri, int no, int nbatch, hipStream_t st);
 void launch_t2N(const double* t2, double* t2N, int no, int nv, hipStream_t st);

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_gcb(const double* __restrict__ Gbc,
   }
 }
 
-static void launch_gcb(const Blocks& bl, int no, int nv, hipStream_t st) {
+void launch_gcb(const Blocks& bl, int no, int nv, hipStream_t st) {
   const unsigned t = nblk(nv, 32);
   hipLaunchKernelGGL(k_gcb, dim3(t * t * no * (nv + no)), dim3(256), 0, st, bl.Gbc, bl.Gcb, nv);
 }
@@ -365,18 +365,21 @@ void launch_build_blocks(const CholeskyScratch& cs, const Blocks& bl, int no, in
 // ---------------------------------------------------------------------------
 // Integral blocks given in the paper's index order -> internal layouts.
 // ---------------------------------------------------------------------------
-__global__ void k_relayout_vv(const double* __restrict__ g_vvvo, const double* __restrict__ g_vvov,
-                              double* __restrict__ Gw, double* __restrict__ Gbc, int no, int nv) {
-  // output index (r, y, d, z) of an nv^3 slab; z fastest
-  const int64_t nv3 = (int64_t)nv * nv * nv;
+__global__ void k_relayout_vv(const double* __restrict__ g_vvvo_y, const double* __restrict__ g_vvov_y,
+                              double* __restrict__ Gw, double* __restrict__ Gbc, int no, int nv,
+                              int y0, int ny) {
+  // output index (r, y, d, z) of an nv^3 slab, z fastest, for y in [y0, y0 + ny);
+  // the inputs start at first index y0
+  const int64_t nv2 = (int64_t)nv * nv, nv3 = nv2 * nv;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (e >= nv3) return;
-  const int y = (int)(e / ((int64_t)nv * nv)), d = (int)((e / nv) % nv), z = (int)(e % nv);
+  if (e >= (int64_t)ny * nv2) return;
+  const int yl = (int)(e / nv2), d = (int)((e / nv) % nv), z = (int)(e % nv);
+  const int64_t out = (int64_t)y0 * nv2 + e;
   // Gw[r][y][u][w] = g_vvvo[y][w][u][r]  (u = d, w = z: the contracted index w fastest)
-  Gw[(int64_t)r * nv3 + e] = g_vvvo[(((int64_t)y * nv + z) * nv + d) * no + r];
+  Gw[(int64_t)r * nv3 + out] = g_vvvo_y[(((int64_t)yl * nv + z) * nv + d) * no + r];
   // Gbc[r][n=y][b=d][c=z] = g_vvov[n][b][r][c]
-  Gbc[(int64_t)r * (nv + no) * nv * nv + e] = g_vvov[(((int64_t)y * nv + d) * no + r) * nv + z];
+  Gbc[(int64_t)r * (nv + no) * nv2 + out] = g_vvov_y[(((int64_t)yl * nv + d) * no + r) * nv + z];
 }
 
 __global__ void k_relayout_small(const double* __restrict__ g_oovo, const double* __restrict__ g_ovov,
@@ -405,17 +408,19 @@ __global__ void k_relayout_small(const double* __restrict__ g_oovo, const double
       F[e] = F_ov[e];
 }
 
-void launch_relayout_blocks(const double* g_vvvo, const double* g_oovo, const double* g_ovov,
-                            const double* g_ooov, const double* g_vvov, const double* F_ov,
-                            const Blocks& b, int no, int nv, hipStream_t st) {
-  const int64_t nv3 = (int64_t)nv * nv * nv;
-  hipLaunchKernelGGL(k_relayout_vv, dim3(nblk(nv3, 256), no), dim3(256), 0, st, g_vvvo, g_vvov,
-                     b.Gw, b.Gbc, no, nv);
+void launch_relayout_small(const double* g_oovo, const double* g_ovov, const double* g_ooov,
+                           const double* F_ov, const Blocks& b, int no, int nv, hipStream_t st) {
   unsigned gx = nblk((int64_t)nv * nv, 256);
   if (gx > 64) gx = 64;
   hipLaunchKernelGGL(k_relayout_small, dim3(gx, no * no), dim3(256), 0, st, g_oovo, g_ovov,
                      g_ooov, F_ov, b.Go, b.Jo, b.Gbc, b.Hs, b.F, no, nv);
-  launch_gcb(b, no, nv, st);
+}
+
+void launch_relayout_vv(const double* g_vvvo_y, const double* g_vvov_y, int y0, int ny,
+                        const Blocks& b, int no, int nv, hipStream_t st) {
+  const int64_t n = (int64_t)ny * nv * nv;
+  hipLaunchKernelGGL(k_relayout_vv, dim3(nblk(n, 256), no), dim3(256), 0, st, g_vvvo_y, g_vvov_y,
+                     b.Gw, b.Gbc, no, nv, y0, ny);
 }
 
 // ---------------------------------------------------------------------------

@@ -164,9 +164,9 @@ def test_errors_are_reported(ctx):
     assert e.value.code == cc3.E_PRECOND
     # the check passes on valid inputs
     ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], flags=cc3.CHECK)
-    # host pointer -> INVAL
+    # a tensor of the wrong dtype -> ValueError in the binding
     with pytest.raises(ValueError):
-        ctx.triples_residual(g["eps"].cpu(), g["L"], g["t1"], g["t2"])
+        ctx.triples_residual(g["eps"].float(), g["L"], g["t1"], g["t2"])
     # bad subset triple
     with pytest.raises(cc3.CC3Error) as e:
         ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], [[1, 2, 0]])
