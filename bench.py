@@ -279,6 +279,8 @@ def main() -> int:
                     help="calls with CC3_ONE_STREAM after the timed region, for kernel durations "
                          "without batch overlap (0: skip)")
     ap.add_argument("--no-cvs", action="store_true", help="skip the CVS worklist timing")
+    ap.add_argument("--no-host-buffers", action="store_true",
+                    help="skip the timing of the call with host-memory arrays")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-molecules", type=int, default=16,
@@ -520,6 +522,28 @@ def main() -> int:
                       "ms_per_call": dtc * 1e3, "full_call_ms": ms, "speedup": ms / (dtc * 1e3)}
         log(f"cvs worklist: {len(core)} of {ntri} triples, {dtc * 1e3:.1f} ms per call "
             f"({ms / (dtc * 1e3):.1f}x faster than the full call)")
+    if not args.no_host_buffers:
+        # the same call with every array in pinned host memory: the PCIe-inclusive rate
+        # (inputs staged into the workspace, outputs copied back, the call waits)
+        h = {k: v.cpu().pin_memory() for k, v in g.items()}
+        h1 = torch.empty((no, nv), dtype=torch.float64).pin_memory()
+        h2 = torch.empty((no, no, nv, nv), dtype=torch.float64).pin_memory()
+        ctx.triples_residual(h["eps"], h["L"], h["t1"], h["t2"], h1, h2)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.triples_residual(h["eps"], h["L"], h["t1"], h["t2"], h1, h2)
+        dth = (time.perf_counter() - t0) / args.steps
+        same = bool(torch.equal(h2, o2.cpu()) and torch.equal(h1, o1.cpu()))
+        in_bytes = sum(v.numel() * 8 for v in h.values())
+        out["host_buffers"] = {
+            "what": "cc3_triples_residual with inputs and outputs in pinned host memory "
+                    "(PCIe transfers inside the timed call)",
+            "value": nominal / dth / 1e12, "unit": "TFLOP/s", "ms_per_call": dth * 1e3,
+            "bytes_in": in_bytes, "bytes_out": (h1.numel() + h2.numel()) * 8,
+            "equal_to_device_call": same}
+        log(f"host buffers: {dth * 1e3:.1f} ms per call ({nominal / dth / 1e12:.2f} TFLOP/s), "
+            f"bit-equal to the device call: {same}")
+        del h, h1, h2
     if args.serve_molecules > 0:
         ctx.close()
         del g, o1, o2

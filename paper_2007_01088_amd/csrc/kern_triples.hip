@@ -671,25 +671,63 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(const E* __restrict__ cubes,
 }
 
 // The (triple, permutation) pairs of a batch whose first occupied index is p, in
-// batch order: at most two per triple, so at most 2 * MAX_BATCH.
+// batch order (triple, then permutation): lz = 6 z + pi, lqr = q no + r; at most two
+// per triple, so at most 2 * MAX_BATCH.  Every thread of the workgroup calls it (it
+// holds barriers); cz is LDS scratch of MAX_BATCH + 1 ints.  Returns the count.
 #define PLIST_MAX (2 * MAX_BATCH)
 __device__ inline int pairs_with_p(const int* __restrict__ tri, int ntri, int p, int no, int* lz,
-                                   int* lqr) {
-  int n = 0;
-  for (int z = 0; z < ntri; ++z) {
+                                   int* lqr, int* cz) {
+  // the number of permutations with first index p of each triple (at most two)
+  for (int z = threadIdx.x; z < ntri; z += blockDim.x) {
     const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
     const int kind = tri_kind(i, j, k);
+    int c = 0;
     for (int pi = 0; pi < 6; ++pi) {
       if (!perm_active(kind, pi)) continue;
       int pp, q, r;
       perm_pqr(pi, i, j, k, pp, q, r);
-      if (pp == p && n < PLIST_MAX) {
-        lz[n] = z * 6 + pi;
-        if (lqr) lqr[n] = q * no + r;
-        ++n;
+      c += pp == p;
+    }
+    cz[z] = c;
+  }
+  __syncthreads();
+  // exclusive prefix sums of the counts (wavefront 0, 64 triples at a time)
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int carry = 0;
+    for (int base = 0; base < ntri; base += 64) {
+      const int z = base + lane;
+      const int v = z < ntri ? cz[z] : 0;
+      int incl = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
       }
+      if (z < ntri) cz[z] = carry + incl - v;
+      carry += __shfl(incl, 63);
+    }
+    if (lane == 0) cz[MAX_BATCH] = carry;
+  }
+  __syncthreads();
+  for (int z = threadIdx.x; z < ntri; z += blockDim.x) {
+    const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+    const int kind = tri_kind(i, j, k);
+    int at = cz[z];
+    for (int pi = 0; pi < 6; ++pi) {
+      if (!perm_active(kind, pi)) continue;
+      int pp, q, r;
+      perm_pqr(pi, i, j, k, pp, q, r);
+      if (pp != p) continue;
+      if (at < PLIST_MAX) {
+        lz[at] = z * 6 + pi;
+        lqr[at] = q * no + r;
+      }
+      ++at;
     }
   }
+  const int n = min(cz[MAX_BATCH], PLIST_MAX);
+  __syncthreads();
   return n;
 }
 
@@ -730,15 +768,14 @@ __global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cub
                                                   double* __restrict__ OtT, int no, int nv,
                                                   int tiles_a) {
   constexpr int NB = 2;
-  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
-  __shared__ int cnt;
+  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX], cz[MAX_BATCH + 1];
+  int cnt;
   __shared__ double lt[4][NB][16][17];  // per wavefront: 16 rows a x 16 c (+1 pad)
   const int p = blockIdx.y;
   const int bp = blockIdx.x / tiles_a;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int a0 = (blockIdx.x % tiles_a) * 64 + 16 * wave;
-  if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
-  __syncthreads();
+  cnt = pairs_with_p(tri, ntri, p, no, lz, lqr, cz);
   const int n = cnt;
   if (n == 0 || a0 >= nv) return;  // no workgroup barrier follows
   const int m = lane & 15, kq = lane >> 4;
@@ -857,11 +894,10 @@ __global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int
                                                 const double* __restrict__ Pvv,
                                                 double* __restrict__ Ot1, double* __restrict__ Ot2,
                                                 int no, int nv, int nchunks) {
-  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
-  __shared__ int cnt;
+  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX], cz[MAX_BATCH + 1];
+  int cnt;
   const int p = blockIdx.z, x = blockIdx.y;
-  if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
-  __syncthreads();
+  cnt = pairs_with_p(tri, ntri, p, no, lz, lqr, cz);
   const int64_t nvl = nv, nv2 = nvl * nvl;
   const int NV1 = nv + 1;
   const int64_t pvs = (int64_t)nvl * NV1;  // one chunk slab
@@ -876,7 +912,7 @@ __global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int
     for (int t = 0; t < n; ++t) {
       if (lqr[t] / no != x) continue;
       const double* pv = Pvv + (int64_t)lz[t] * nchunks * pvs + (int64_t)a * NV1 + d;
-#pragma unroll 4
+#pragma unroll 16
       for (int c = 0; c < nchunks; ++c) s2 += pv[c * pvs];
     }
     Ot2[((int64_t)p * no + x) * nv2 + e] += s2;
@@ -885,6 +921,7 @@ __global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int
     double s1 = 0.0;
     for (int t = 0; t < n; ++t) {
       const double* pv = Pvv + (int64_t)lz[t] * nchunks * pvs + (int64_t)e * NV1 + nv;
+#pragma unroll 16
       for (int c = 0; c < nchunks; ++c) s1 += pv[c * pvs];
     }
     Ot1[(int64_t)p * nvl + e] += s1;
@@ -910,14 +947,13 @@ __global__ __launch_bounds__(ZvCfg::NT) void k_zv(const double* __restrict__ cub
                                                   int tiles_m, int tiles_n) {
   typedef ZvCfg T;
   __shared__ double lds[T::LDS_DOUBLES];
-  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
-  __shared__ int cnt;
+  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX], cz[MAX_BATCH + 1];
+  int cnt;
   const int p = blockIdx.y;
   const int tpp = tiles_m * tiles_n;
   const int b = blockIdx.x / tpp, tile = blockIdx.x % tpp;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
-  if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
-  __syncthreads();
+  cnt = pairs_with_p(tri, ntri, p, no, lz, lqr, cz);
   const int n = cnt;
   if (n == 0) return;
   const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
@@ -1004,11 +1040,10 @@ __global__ __launch_bounds__(256) void k_zo_reduce(const int* __restrict__ tri, 
                                                    const double* __restrict__ Pzo,
                                                    double* __restrict__ Zo, int no, int nv,
                                                    int nbchunks) {
-  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX];
-  __shared__ int cnt;
+  __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX], cz[MAX_BATCH + 1];
+  int cnt;
   const int q = blockIdx.y, p = blockIdx.z;
-  if (threadIdx.x == 0) cnt = pairs_with_p(tri, ntri, p, no, lz, lqr);
-  __syncthreads();
+  cnt = pairs_with_p(tri, ntri, p, no, lz, lqr, cz);
   const int n = cnt;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n == 0 || e >= (int64_t)nv * no) return;
