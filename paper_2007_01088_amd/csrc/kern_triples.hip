@@ -289,13 +289,24 @@ __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
                                              double* __restrict__ cubes, float* __restrict__ cubesF,
                                              uint16_t* __restrict__ YL, int lpP, int no, int nv) {
   __shared__ double Xs[6 * TSZ];
-  const int z = blockIdx.y;
+  // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a contiguous
+  // run of (triple, orbit) items, so that orbits adjacent along a cube row, whose
+  // row segments share cache lines, meet in the same L2.
+  int z, ob;
+  {
+    const int total = gridDim.x * gridDim.y;
+    const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+    const int per = total / 8, rem = total % 8, xcd = lin % 8, pos = lin / 8;
+    const int item = xcd < rem ? xcd * (per + 1) + pos : rem * (per + 1) + (xcd - rem) * per + pos;
+    z = item / gridDim.x;
+    ob = item % gridDim.x;
+  }
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   const int kind = tri_kind(i, j, k);
   const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
   double* cz = cubes + (int64_t)z * NSLOT * nv3;
   int blk[3];
-  decode_block_triple(blockIdx.x, blk[0], blk[1], blk[2]);
+  decode_block_triple(ob, blk[0], blk[1], blk[2]);
   const double eijk = eps[i] + eps[j] + eps[k];
   const double* P0 = cz + SLOT_P0 * nv3;
   const double* P1 = cz + SLOT_P1 * nv3;
