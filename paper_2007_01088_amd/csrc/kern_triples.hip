@@ -307,6 +307,23 @@ __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
   double* cz = cubes + (int64_t)z * NSLOT * nv3;
   int blk[3];
   decode_block_triple(ob, blk[0], blk[1], blk[2]);
+  // With equal blocks some orientations repeat an earlier one: canon[o] is the
+  // first orientation with the same block triple.  Repeats are neither loaded,
+  // combined nor written; reads of a repeated tile go to its first copy.
+  int canon[6];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
+    canon[o] = o;
+#pragma unroll
+    for (int o2 = 4; o2 >= 0; --o2) {
+      if (o2 >= o) continue;
+      int r0, r1, r2;
+      orient(o2, r0, r1, r2);
+      if (blk[r0] == blk[q0] && blk[r1] == blk[q1] && blk[r2] == blk[q2]) canon[o] = o2;
+    }
+  }
   const double eijk = eps[i] + eps[j] + eps[k];
   const double* P0 = cz + SLOT_P0 * nv3;
   const double* P1 = cz + SLOT_P1 * nv3;
@@ -317,6 +334,7 @@ __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
   //    that pass the fastest one (c, b, then a).
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
+    if (canon[o] != o) continue;
     int q0, q1, q2;
     orient(o, q0, q1, q2);
     const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
@@ -334,6 +352,7 @@ __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
   __syncthreads();
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
+    if (canon[o] != o) continue;
     int q0, q1, q2;
     orient(o, q0, q1, q2);
     const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
@@ -354,6 +373,7 @@ __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
     __syncthreads();
 #pragma unroll
     for (int o = 0; o < 6; ++o) {
+      if (canon[o] != o) continue;
       int q0, q1, q2;
       orient(o, q0, q1, q2);
       const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
@@ -371,11 +391,13 @@ __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
   double tt[6][MIXH];
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
+    if (canon[o] != o) continue;
     int q0, q1, q2;
     orient(o, q0, q1, q2);
     const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
-    const int o_acb = orient_of(q0, q2), o_cba = orient_of(q2, q1), o_bac = orient_of(q1, q0);
-    const int o_bca = orient_of(q1, q2), o_cab = orient_of(q2, q0);
+    const int o_acb = canon[orient_of(q0, q2)], o_cba = canon[orient_of(q2, q1)];
+    const int o_bac = canon[orient_of(q1, q0)], o_bca = canon[orient_of(q1, q2)];
+    const int o_cab = canon[orient_of(q2, q0)];
 #pragma unroll
     for (int h = 0; h < MIXH; ++h) {
       const int e = t + MIXT * h;
@@ -398,30 +420,23 @@ __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
   }
   __syncthreads();
 #pragma unroll
-  for (int o = 0; o < 6; ++o)
+  for (int o = 0; o < 6; ++o) {
+    if (canon[o] != o) continue;
 #pragma unroll
     for (int h = 0; h < MIXH; ++h) {
       const int e = t + MIXT * h;
       Xs[o * TSZ + TP(e >> 6, (e >> 3) & 7, e & 7)] = tt[o][h];
     }
+  }
   __syncthreads();
-  // 3. write tau~[a][b][c] (w fastest) and tau~T[a][c][b] (v fastest), skipping
-  //    orientations that repeat an earlier one (equal blocks)
+  // 3. write tau~[a][b][c] (w fastest) and tau~T[a][c][b] (v fastest)
   double* TT = cz + SLOT_TT * nv3;
   double* TTT = cz + SLOT_TTT * nv3;
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
+    if (canon[o] != o) continue;
     int q0, q1, q2;
     orient(o, q0, q1, q2);
-    bool dup = false;
-#pragma unroll
-    for (int o2 = 0; o2 < 6; ++o2) {
-      if (o2 >= o) break;
-      int r0, r1, r2;
-      orient(o2, r0, r1, r2);
-      dup |= (blk[r0] == blk[q0] && blk[r1] == blk[q1] && blk[r2] == blk[q2]);
-    }
-    if (dup) continue;
     const int A0 = blk[q0] * MT, B0 = blk[q1] * MT, C0 = blk[q2] * MT;
 #pragma unroll
     for (int h = 0; h < MIXH; ++h) {
