@@ -240,9 +240,8 @@ __device__ inline void decode_block_triple(int idx, int& A, int& B, int& C) {
   A = idx; B = b; C = c;
 }
 
-// Threads per mix workgroup: each handles MIXH of the 512 elements of an
-// orientation tile.
-constexpr int MIXT = 512, MIXH = 512 / MIXT;
+// Threads per mix workgroup (MIXT, 256 or 512): each handles MIXH = 512 / MIXT of
+// the 512 elements of an orientation tile.
 
 __device__ inline double xval(const double* __restrict__ cz, int kind, int64_t nv, int a, int b,
                               int c) {
@@ -284,23 +283,14 @@ __device__ inline void yl_put(uint16_t* YL, int P, int z, int v, int row, int64_
 // Mixed-all copies (nullable): cubesF, FP32 tau~ and tau~T, [triple][2][nv^3];
 // YL, the split-BF16 k-major views of the split-BF16 Omega GEMM (k_omega_lp),
 // [triple][4][piece][a][kk < Kp] with lpP pieces.
+template <int MIXT>
 __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
                                              const int* __restrict__ tri,
                                              double* __restrict__ cubes, float* __restrict__ cubesF,
                                              uint16_t* __restrict__ YL, int lpP, int no, int nv) {
+  constexpr int MIXH = 512 / MIXT;
   __shared__ double Xs[6 * TSZ];
-  // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a contiguous
-  // run of (triple, orbit) items, so that orbits adjacent along a cube row, whose
-  // row segments share cache lines, meet in the same L2.
-  int z, ob;
-  {
-    const int total = gridDim.x * gridDim.y;
-    const int lin = blockIdx.y * gridDim.x + blockIdx.x;
-    const int per = total / 8, rem = total % 8, xcd = lin % 8, pos = lin / 8;
-    const int item = xcd < rem ? xcd * (per + 1) + pos : rem * (per + 1) + (xcd - rem) * per + pos;
-    z = item / gridDim.x;
-    ob = item % gridDim.x;
-  }
+  const int z = blockIdx.y, ob = blockIdx.x;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   const int kind = tri_kind(i, j, k);
   const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
@@ -475,8 +465,15 @@ void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, floa
                 void* YL, int lpP, int no, int nv, hipStream_t st) {
   const int nb = (nv + MT - 1) / MT;
   const int nbt = nb * (nb + 1) * (nb + 2) / 6;
-  hipLaunchKernelGGL(k_mix, dim3(nbt, ntri), dim3(MIXT), 0, st, eps, tri, cubes, cubesF,
-                     (uint16_t*)YL, lpP, no, nv);
+  // 512 threads, one element per thread and orientation; the form that also writes
+  // the split-BF16 views of tau~ runs with 256 (two elements each), which measured
+  // faster for it at nv = 250
+  if (YL)
+    hipLaunchKernelGGL(k_mix<256>, dim3(nbt, ntri), dim3(256), 0, st, eps, tri, cubes, cubesF,
+                       (uint16_t*)YL, lpP, no, nv);
+  else
+    hipLaunchKernelGGL(k_mix<512>, dim3(nbt, ntri), dim3(512), 0, st, eps, tri, cubes, cubesF,
+                       (uint16_t*)YL, lpP, no, nv);
 }
 
 // tau^{abc}_{ijk} = -X / eps^{abc}_{ijk} for one ordered triple whose six terms were all built
@@ -703,6 +700,27 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(const E* __restrict__ cubes,
 #define PLIST_MAX (2 * MAX_BATCH)
 __device__ inline int pairs_with_p(const int* __restrict__ tri, int ntri, int p, int no, int* lz,
                                    int* lqr, int* cz) {
+  if (ntri <= 8) {  // a short batch: one thread, one barrier
+    if (threadIdx.x == 0) {
+      int n = 0;
+      for (int z = 0; z < ntri; ++z) {
+        const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+        const int kind = tri_kind(i, j, k);
+        for (int pi = 0; pi < 6; ++pi) {
+          if (!perm_active(kind, pi)) continue;
+          int pp, q, r;
+          perm_pqr(pi, i, j, k, pp, q, r);
+          if (pp != p) continue;
+          lz[n] = z * 6 + pi;
+          lqr[n] = q * no + r;
+          ++n;
+        }
+      }
+      cz[MAX_BATCH] = n;
+    }
+    __syncthreads();
+    return cz[MAX_BATCH];
+  }
   // the number of permutations with first index p of each triple (at most two)
   for (int z = threadIdx.x; z < ntri; z += blockDim.x) {
     const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
@@ -935,13 +953,15 @@ __global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int
   const int n = cnt;
   if (o2) {
     double s2 = 0.0;
+    bool any = false;  // uniform: a block (p, x) without pairs leaves Ot2 as it is
     for (int t = 0; t < n; ++t) {
       if (lqr[t] / no != x) continue;
+      any = true;
       const double* pv = Pvv + (int64_t)lz[t] * nchunks * pvs + (int64_t)a * NV1 + d;
 #pragma unroll 16
       for (int c = 0; c < nchunks; ++c) s2 += pv[c * pvs];
     }
-    Ot2[((int64_t)p * no + x) * nv2 + e] += s2;
+    if (any) Ot2[((int64_t)p * no + x) * nv2 + e] += s2;
   }
   if (o1) {
     double s1 = 0.0;
