@@ -408,6 +408,7 @@ def main() -> int:
             m2 = torch.empty_like(o2)
             ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=prec)
             torch.cuda.synchronize()
+            log(f"mixed {name}: untimed call done")
             ctx.profile_enable(True)
             t0 = time.perf_counter()
             for _ in range(args.steps):
@@ -435,6 +436,7 @@ def main() -> int:
             fl = cc3.LOWP_CONTRACT
             ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=prec, flags=fl)
             torch.cuda.synchronize()
+            log(f"mixed {name}: untimed call done")
             ctx.profile_enable(True)
             t0 = time.perf_counter()
             for _ in range(args.steps):
