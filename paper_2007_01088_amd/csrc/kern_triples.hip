@@ -1031,9 +1031,11 @@ __global__ __launch_bounds__(ZvCfg::NT) void k_zv(const double* __restrict__ cub
       }
 }
 
-// Zo partials: per (triple, permutation, 128-row tile of a, b chunk)
-//   Pzo[z][pi][chunk][a][l] = sum_{b in chunk} sum_c U[a,b,c] Jo[l][r][b][c]   (l < no <= 64)
-typedef TileCfg<4, 2, 2, 2, 16> ZoCfg;
+// Zo partials: per (triple, permutation, 128-row tile of a, 16-column tile of l, b chunk)
+//   Pzo[z][pi][chunk][a][l] = sum_{b in chunk} sum_c U[a,b,c] Jo[l][r][b][c]   (l < no)
+// The l extent is no (12 at the benchmark size), so the tile is 128 x 16: eight
+// wavefronts of 16 x 16, and the stage is mostly the streamed U rows.
+typedef TileCfg<8, 1, 1, 1, 16> ZoCfg;
 
 __global__ __launch_bounds__(ZoCfg::NT) void k_zo(const double* __restrict__ cubes,
                                                   const double* __restrict__ Jo,
@@ -1047,8 +1049,10 @@ __global__ __launch_bounds__(ZoCfg::NT) void k_zo(const double* __restrict__ cub
   if (!perm_active(tri_kind(i, j, k), pi)) return;
   int p, q, r;
   perm_pqr(pi, i, j, k, p, q, r);
+  const int tm = (nv + T::BM - 1) / T::BM;
   const int bc = blockIdx.x % nbchunks;
-  const int m0 = (blockIdx.x / nbchunks) * T::BM;
+  const int m0 = ((blockIdx.x / nbchunks) % tm) * T::BM;
+  const int n0 = (blockIdx.x / nbchunks / tm) * T::BN;
   const int bb0 = (int)((int64_t)bc * nv / nbchunks);
   const int bb1 = (int)((int64_t)(bc + 1) * nv / nbchunks);
   if (bb0 >= bb1) return;
@@ -1065,7 +1069,7 @@ __global__ __launch_bounds__(ZoCfg::NT) void k_zo(const double* __restrict__ cub
   };
   d4v acc[T::FM][T::FN];
   zero_acc<T>(acc);
-  k_loop<T>((bb1 - bb0) * cs, m0, 0, ops, acc, lds);
+  k_loop<T>((bb1 - bb0) * cs, m0, n0, ops, acc, lds);
   double* out = Pzo + (((int64_t)z * 6 + pi) * nbchunks + bc) * nvl * no;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
@@ -1076,7 +1080,7 @@ __global__ __launch_bounds__(ZoCfg::NT) void k_zo(const double* __restrict__ cub
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
         const int a = m0 + acc_row<T>(wm, fm, lane, rr);
-        const int l = acc_col<T>(wn, fn, lane);
+        const int l = n0 + acc_col<T>(wn, fn, lane);
         if (a < nv && l < no) out[(int64_t)a * no + l] = acc[fm][fn][rr];
       }
 }
@@ -1117,9 +1121,9 @@ void launch_zo(const double* cubes, const Blocks& b, const int* tri, int ntri, d
   typedef ZoCfg T;
   const int nbc = zo_nbchunks(nv, ntri);
   if (!reduce) {
-    const int tm = (nv + T::BM - 1) / T::BM;
-    hipLaunchKernelGGL(k_zo, dim3(nbc * tm, 6, ntri), dim3(T::NT), 0, st, cubes, b.Jo, tri, Pzo,
-                       no, nv, nbc);
+    const int tm = (nv + T::BM - 1) / T::BM, tn = (no + T::BN - 1) / T::BN;
+    hipLaunchKernelGGL(k_zo, dim3(nbc * tm * tn, 6, ntri), dim3(T::NT), 0, st, cubes, b.Jo, tri,
+                       Pzo, no, nv, nbc);
   } else {
     hipLaunchKernelGGL(k_zo_reduce, dim3(nblk((int64_t)nv * no, 256), no, no), dim3(256), 0, st,
                        tri, ntri, Pzo, Zo, no, nv, nbc);
