@@ -191,7 +191,8 @@ int cc3_t3_block(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps, con
  *   Z~v_{abpd} -= sum_c U^{abc} g_{qdrc},   Z~o_{aqpl} += sum_{bc} U^{abc} g_{lbrc}.
  * Outputs (device, row-major, overwritten or added with CC3_ACCUMULATE):
  *   zv[nv][nv][no][nv] = Z~v_{abid},  zo[nv][no][no][no] = Z~o_{ajil}.
- * Inputs, precision (of the W contractions) and workspace as for
+ * Inputs as for cc3_triples_residual but in device memory only (a host pointer
+ * gives CC3_E_INVAL); precision (of the W contractions) and workspace as for
  * cc3_triples_residual (same cc3_workspace_size).  Supported sizes additionally
  * need no^2 nv^2 < 2^31.  Errors: CC3_E_INVAL, CC3_E_NOMEM, CC3_E_DEVICE,
  * CC3_E_PRECOND (with CC3_CHECK). */
