@@ -297,9 +297,9 @@ def main() -> int:
                          "known traffic, used to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the triple loop would "
-              "shard by triples with one all-reduce of the residual, which this build does not "
-              "launch.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); a multi-GPU run would "
+              "shard the triple loop by triples with one all-reduce of the residual, and is not "
+              "implemented.", file=sys.stderr)
         return 2
 
     if args.serve_molecules > 0 and "GPU_MAX_HW_QUEUES" not in os.environ:
