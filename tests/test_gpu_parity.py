@@ -250,3 +250,40 @@ def test_sampled_parity_full_sizes(ctx, no, nv, nJ, count):
     r1, r2 = O.omega_tilde_subset(d["eps"], d["L"], d["t1"], d["t2"], tri)
     assert_close("Ot1", o1, r1)
     assert_close("Ot2", o2, r2)
+
+
+def test_max_nv_embedding():
+    """The largest supported virtual space, nv = 1024, through every kernel at full size.
+    A small problem (no = 2, nv = 20) is embedded with 1004 decoupled virtual orbitals:
+    zero Cholesky rows and columns, zero t1 and t2, orbital energy 10.  Every integral
+    and amplitude with such an index vanishes, so the result must equal the oracle's
+    small result in its 20 x 20 block and be exactly zero elsewhere."""
+    torch = _torch()
+    from paper_2007_01088_amd import cc3
+    no, nv0, nJ, nv = 2, 20, 6, 1024
+    d = make_inputs(no, nv0, nJ)
+    r1, r2 = O.triples_residual(d["eps"], d["L"], d["t1"], d["t2"])
+    eps = np.concatenate([d["eps"], np.full(nv - nv0, 10.0)])
+    L = np.zeros((nJ, no + nv, no + nv))
+    L[:, :no + nv0, :no + nv0] = d["L"]
+    t1 = np.zeros((no, nv))
+    t1[:, :nv0] = d["t1"]
+    t2 = np.zeros((no, no, nv, nv))
+    t2[:, :, :nv0, :nv0] = d["t2"]
+    say(f"max-nv embedding: no={no} nv={nv} (small block nv={nv0})")
+    c = cc3.Context(0)
+    try:
+        g = {k: torch.from_numpy(v).cuda() for k, v in (("eps", eps), ("L", L), ("t1", t1),
+                                                         ("t2", t2))}
+        o1, o2 = c.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
+        torch.cuda.synchronize()
+        o1, o2 = o1.cpu().numpy(), o2.cpu().numpy()
+    finally:
+        c.close()
+        c._ws = None
+        torch.cuda.empty_cache()
+    assert_close("Omega1 small block", o1[:, :nv0], r1)
+    assert_close("Omega2 small block", o2[:, :, :nv0, :nv0], r2)
+    rest2 = o2.copy()
+    rest2[:, :, :nv0, :nv0] = 0.0
+    assert not o1[:, nv0:].any() and not rest2.any()
