@@ -56,12 +56,13 @@ def assert_close(name, got, ref):
 @pytest.mark.parametrize("no,nv,nJ,t1z", [(4, 20, 60, False), (4, 20, 60, True), (3, 9, 12, False),
                                           (5, 37, 50, False), (6, 130, 40, False),
                                           (16, 16, 40, False), (3, 128, 20, False),
-                                          (35, 8, 16, False), (50, 5, 12, False)])
+                                          (35, 8, 16, False), (50, 5, 12, False),
+                                          (63, 3, 6, False)])
 def test_full_residual_parity(ctx, no, nv, nJ, t1z):
     """Whole call from Cholesky vectors; sizes cover one and two 128-wide tiles and ragged
     8-blocks (nv = 9, 37, 130), one MFMA block (nv = 16), and nv = 128, where the Omega1
     column of the vv GEMM opens a second column tile; no = 35 and 50 take the oo kernel's
-    forms with three and four 16-wide tiles of l."""
+    forms with three and four 16-wide tiles of l; no = 63 is the largest supported."""
     torch = _torch()
     say(f"full residual no={no} nv={nv} nJ={nJ} t1_zero={t1z}")
     d = make_inputs(no, nv, nJ, t1_zero=t1z)
