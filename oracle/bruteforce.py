@@ -1,5 +1,6 @@
 """Brute-force evaluation of the CC3 triples residual (and of the t3-dependent
-intermediates of the Jacobian preparation) over the full T3 tensor.
+intermediates of the Jacobian preparation, and of the triples contributions to the
+transition densities) over the full T3 (and L3) tensors.
 
 TEST INFRASTRUCTURE ONLY (tiny sizes: it stores all nv^3 no^3 amplitudes).
 This is the plain definition the restricted loop of Algorithm 1 reaches up to
@@ -89,3 +90,48 @@ def _full_contravariant(eps, L, t1, t2):
           - 2.0 * np.einsum("ijkbac->ijkabc", tau) + np.einsum("ijkbca->ijkabc", tau)
           + np.einsum("ijkcab->ijkabc", tau))
     return tt, tau, g_ovov, g_ooov, g_vvov, F
+
+
+def _simultaneous_p(W):
+    """P^{abc}_{ijk}: the sum over the six simultaneous permutations of (a,i), (b,j), (c,k)."""
+    return (W + np.einsum("jikbac->ijkabc", W) + np.einsum("kjicba->ijkabc", W)
+            + np.einsum("ikjacb->ijkabc", W) + np.einsum("jkibca->ijkabc", W)
+            + np.einsum("kijcab->ijkabc", W))
+
+
+def _virtual_contravariant(x):
+    return (4.0 * x - 2.0 * np.einsum("ijkacb->ijkabc", x) - 2.0 * np.einsum("ijkcba->ijkabc", x)
+            - 2.0 * np.einsum("ijkbac->ijkabc", x) + np.einsum("ijkbca->ijkabc", x)
+            + np.einsum("ijkcab->ijkabc", x))
+
+
+def transition_density_bruteforce(eps, L, t1, t2, l1, l2, omega):
+    """The triples contributions to D^{m,0} by their plain definition over all ordered
+    index tuples, with full T3 and L3 tensors:
+        L^{abc}_{ijk} = (omega - eps^{abc}_{ijk})^{-1} P^{abc}_{ijk} (L^a_i g_{jbkc}
+                        + L^{ab}_{ij} F_{kc} + sum_d L^{ad}_{jk} g_{ibdc} - sum_l L^{ab}_{lk} g_{iljc})
+        D_cd = 1/2 sum L~^{abc}_{ijk} t^{abd}_{ijk}       D_kc = sum L^{ab}_{ij} t~^{abc}_{ijk}
+        Y^o_{clik} = sum_{jab} L~^{abc}_{ijk} t^{ab}_{lj}  D_ld = - sum_{cik} Y^o_{clik} t^{cd}_{ki}
+        D_lk = - 1/2 sum L~^{abc}_{ijk} t^{abc}_{ijl}
+    Returns (D_cd, D_kc, D_ld, D_lk, Y^o)."""
+    no, _, nv, _ = t2.shape
+    tt, tau, _, _, _, _ = _full_contravariant(eps, L, t1, t2)
+    gt, Ft = transformed_hamiltonian(eps, L, t1)
+    o, v = slice(0, no), slice(no, None)
+    g_ovov, g_ovvv, g_ooov, F = gt[o, v, o, v], gt[o, v, v, v], gt[o, o, o, v], Ft[o, v]
+    C = (np.einsum("ia,jbkc->ijkabc", l1, g_ovov, optimize=True)
+         + np.einsum("ijab,kc->ijkabc", l2, F, optimize=True)
+         + np.einsum("jkad,ibdc->ijkabc", l2, g_ovvv, optimize=True)
+         - np.einsum("lkab,iljc->ijkabc", l2, g_ooov, optimize=True))
+    eo, ev = eps[:no], eps[no:]
+    D = (ev[None, None, None, :, None, None] + ev[None, None, None, None, :, None]
+         + ev[None, None, None, None, None, :] - eo[:, None, None, None, None, None]
+         - eo[None, :, None, None, None, None] - eo[None, None, :, None, None, None])
+    lam = _simultaneous_p(C) / (omega - D)
+    lt = _virtual_contravariant(lam)
+    D_cd = 0.5 * np.einsum("ijkabc,ijkabd->cd", lt, tau, optimize=True)
+    D_kc = np.einsum("ijab,ijkabc->kc", l2, tt, optimize=True)
+    Y = np.einsum("ijkabc,ljab->clik", lt, t2, optimize=True)
+    D_ld = -np.einsum("clik,kicd->ld", Y, t2, optimize=True)
+    D_lk = -0.5 * np.einsum("ijkabc,ijlabc->lk", lt, tau, optimize=True)
+    return D_cd, D_kc, D_ld, D_lk, Y

@@ -8,8 +8,10 @@ It follows Paul, Myhre & Koch, "A new and efficient implementation of CC3"
 (arXiv 2007.01088): Section "Implementation", Algorithm 1 (CC3 ground-state
 equations), the permutation operator P^{abc}_{ijk}, the orbital-energy
 difference, the contravariant amplitudes and the covariant back-transformation;
-and Algorithm 2 (the t3-dependent intermediates of the preparation for the
-Jacobian transformations).
+Algorithm 2 (the t3-dependent intermediates of the preparation for the
+Jacobian transformations); and Algorithm 3 (the triples contributions to the
+transition densities D^{m,0}: the occupied loop for the vv, ov and vo blocks and
+the loop over the virtual indices for the oo block).
 Every step is a numpy einsum over float64 arrays, taken in the order the
 algorithm states; no blocking, fusion or reordering beyond it.
 
@@ -48,7 +50,8 @@ __all__ = [
     "contravariant", "occupied_permutations", "unordered_triples", "omega_tilde",
     "back_transform", "triples_residual", "triples_residual_blocks",
     "omega_tilde_subset", "nominal_flops", "FlopCounter", "jacobian_prep_tilde",
-    "jacobian_prep",
+    "jacobian_prep", "l3_amplitudes", "virtual_triples", "transition_density_occupied",
+    "transition_density_virtual", "transition_density",
 ]
 
 
@@ -148,6 +151,10 @@ class IntegralBlocks:
         self._vvvo = {k: np.ascontiguousarray(g_vvvo[:, :, :, k]) for k in range(self.no)}
         self._vvov = {k: np.ascontiguousarray(g_vvov[:, :, k, :]) for k in range(self.no)}
         return self
+
+    def ovvv(self, i: int) -> np.ndarray:
+        """g_ovvv[b][d][c] at fixed i: g_{ibdc} (Algorithm 3's L3 builder)."""
+        return _e("Jb,Jdc->bdc", self.L_ov[:, i, :], self.L_vv)
 
     def full_vvvo(self) -> np.ndarray:
         return np.stack([self.vvvo(k) for k in range(self.no)], axis=3)
@@ -345,3 +352,166 @@ def jacobian_prep(eps, L, t1, t2, flops: FlopCounter | None = None):
     Lt = t1_transform(L, t1)
     blk = IntegralBlocks(Lt, no)
     return jacobian_prep_tilde(eps, t2, blk, flops=flops)
+
+
+# --------------------------------------------------------------------------
+# Contributions of the triples to the transition densities (Algorithm 3).
+#
+# Readings (each is listed in the design notes): the amplitudes written with t
+# and with tau in the algorithm are the same ground-state amplitudes (t3 by the
+# first statement of Algorithm 1, t2 the doubles); L^a_i, L^{ab}_{ij} are the
+# left-state singles and doubles, L^{ab}_{ij} = L^{ba}_{ji}; omega is the
+# excitation energy; the integrals and F are the T1-transformed ones of
+# Algorithm 1; "for permutations" applies each distinct permutation once, and
+# the all-equal triples (i == j == k, a == b == c) are skipped, their
+# contravariant amplitudes vanishing.  Array layouts: D_cd[c][d], D_kc[k][c],
+# D_ld[l][d], D_lk[l][k], Y^o[c][l][i][k].
+# --------------------------------------------------------------------------
+
+def l3_term(p: int, q: int, r: int, l1: np.ndarray, l2: np.ndarray, blk: IntegralBlocks,
+            F: np.ndarray) -> np.ndarray:
+    """C^{abc}_{pqr} = L^a_p g_{qbrc} + L^{ab}_{pq} F_{rc} + sum_d L^{ad}_{qr} g_{pbdc}
+    - sum_l L^{ab}_{lr} g_{plqc}   (Algorithm 3, second statement, before P)."""
+    return (_e("a,bc->abc", l1[p], blk.g_ovov[q, :, r, :])
+            + _e("ab,c->abc", l2[p, q], F[r])
+            + _e("ad,bdc->abc", l2[q, r], blk.ovvv(p))
+            - _e("lab,lc->abc", l2[:, r], blk.g_ooov[p, :, q, :]))
+
+
+def l3_amplitudes(i: int, j: int, k: int, omega: float, eps: np.ndarray, l1: np.ndarray,
+                  l2: np.ndarray, blk: IntegralBlocks, F: np.ndarray) -> np.ndarray:
+    """L^{abc}_{ijk} = (omega - eps^{abc}_{ijk})^{-1} P^{abc}_{ijk} C^{abc}_{ijk}, with the
+    permutation operator of Algorithm 1."""
+    no = l1.shape[0]
+    X = (l3_term(i, j, k, l1, l2, blk, F)
+         + np.einsum("bac->abc", l3_term(j, i, k, l1, l2, blk, F))
+         + np.einsum("cba->abc", l3_term(k, j, i, l1, l2, blk, F))
+         + np.einsum("acb->abc", l3_term(i, k, j, l1, l2, blk, F))
+         + np.einsum("bca->abc", l3_term(j, k, i, l1, l2, blk, F))
+         + np.einsum("cab->abc", l3_term(k, i, j, l1, l2, blk, F)))
+    ev = eps[no:]
+    D = (ev[:, None, None] + ev[None, :, None] + ev[None, None, :]
+         - eps[i] - eps[j] - eps[k])
+    return X / (omega - D)
+
+
+def transition_density_occupied(eps, t2, l1, l2, omega, blk: IntegralBlocks, F, triples=None):
+    """The loop over i >= j >= k of Algorithm 3: D_cd, D_kc, then D_ld from Y^o.
+
+    Per triple: t3 (Algorithm 1), L3 and its contravariant L~; for each distinct
+    permutation (p,q,r) of (i,j,k)
+        Y^o_{c l p r} += sum_{ab} L~^{abc}_{pqr} t^{ab}_{lq}
+        D_cd          += 1/2 sum_{ab} L~^{abc}_{pqr} t^{abd}_{pqr}
+    then, with t~ the contravariant t3, for each distinct permutation
+        D_{rc}        += sum_{ab} L^{ab}_{pq} t~^{abc}_{pqr};
+    after the loop  D_ld -= sum_{cik} Y^o_{clik} t^{cd}_{ki}.
+    Returns (D_cd, D_kc, D_ld, Y^o)."""
+    no, _, nv, _ = t2.shape
+    D_cd = np.zeros((nv, nv))
+    D_kc = np.zeros((no, nv))
+    Y = np.zeros((nv, no, no, no))
+    if triples is None:
+        triples = unordered_triples(no)
+    for (i, j, k) in triples:
+        i, j, k = int(i), int(j), int(k)
+        if i == j == k:
+            continue
+        tau = t3_amplitudes(i, j, k, eps, t2, blk)
+        lt = contravariant(l3_amplitudes(i, j, k, omega, eps, l1, l2, blk, F))
+        for ((p, q, r), LT), (_, T) in zip(occupied_permutations(i, j, k, lt),
+                                           occupied_permutations(i, j, k, tau)):
+            Y[:, :, p, r] += _e("abc,lab->cl", LT, t2[:, q])
+            D_cd += 0.5 * _e("abc,abd->cd", LT, T)
+        for (p, q, r), TT in occupied_permutations(i, j, k, contravariant(tau)):
+            D_kc[r] += _e("ab,abc->c", l2[p, q], TT)
+    D_ld = -_e("clik,kicd->ld", Y, t2)
+    return D_cd, D_kc, D_ld, Y
+
+
+def virtual_triples(nv: int):
+    """The loop a >= b >= c of Algorithm 3, without the a == b == c triples."""
+    return [(a, b, c) for a in range(nv) for b in range(a + 1) for c in range(b + 1)
+            if not (a == b == c)]
+
+
+# occupied relabelling [i][j][k] that gives a block of the virtual labels (x,y,z) from
+# the block of (a,b,c), by the simultaneous permutational symmetry
+# X^{xyz}_{ijk} = X^{abc}_{sigma(ijk)}:  label order -> einsum source subscripts
+_VPERM = (("abc", "ijk"), ("bac", "jik"), ("cba", "kji"),
+          ("acb", "ikj"), ("bca", "kij"), ("cab", "jki"))
+
+
+def _virtual_perm(block: np.ndarray, src: str) -> np.ndarray:
+    return np.einsum(src + "->ijk", block)
+
+
+def _w_virtual(x: int, y: int, z: int, t2, Gw, blk: IntegralBlocks) -> np.ndarray:
+    """B^{xyz}_{ijk} over all (i,j,k): sum_d t^{xd}_{ij} g_{ydzk} - sum_l t^{xy}_{il} g_{ljzk}."""
+    return (_e("ijd,dk->ijk", t2[:, :, x, :], Gw[y, :, z, :])
+            - _e("il,ljk->ijk", t2[:, :, x, y], blk.g_oovo[:, :, z, :]))
+
+
+def _c_virtual(x: int, y: int, z: int, l1, l2, F, Go, blk: IntegralBlocks) -> np.ndarray:
+    """C^{xyz}_{ijk} over all (i,j,k): L^x_i g_{jykz} + L^{xy}_{ij} F_{kz}
+    + sum_d L^{xd}_{jk} g_{iydz} - sum_l L^{xy}_{lk} g_{iljz}."""
+    return (_e("i,jk->ijk", l1[:, x], blk.g_ovov[:, y, :, z])
+            + _e("ij,k->ijk", l2[:, :, x, y], F[:, z])
+            + _e("jkd,id->ijk", l2[:, :, x, :], Go[:, y, :, z])
+            - _e("lk,ilj->ijk", l2[:, :, x, y], blk.g_ooov[:, :, :, z]))
+
+
+def _p_virtual(build) -> np.ndarray:
+    """P^{abc}_{ijk} for a fixed virtual triple: B^{abc}_{ijk} + B^{bac}_{jik} + B^{cba}_{kji}
+    + B^{acb}_{ikj} + B^{bca}_{jki} + B^{cab}_{kij}, with build(x, y, z) giving B^{xyz} over ijk."""
+    return (build(0, 1, 2) + np.einsum("jik->ijk", build(1, 0, 2))
+            + np.einsum("kji->ijk", build(2, 1, 0)) + np.einsum("ikj->ijk", build(0, 2, 1))
+            + np.einsum("jki->ijk", build(1, 2, 0)) + np.einsum("kij->ijk", build(2, 0, 1)))
+
+
+def transition_density_virtual(eps, t2, l1, l2, omega, blk: IntegralBlocks, F, triples=None):
+    """The loop over a >= b >= c of Algorithm 3: t3 and L3 for the fixed virtual triple and
+    every (i,j,k), L~ by the virtual permutations at fixed (i,j,k) (as occupied
+    relabellings of the block), and for each distinct permutation (x,y,z) of (a,b,c)
+        D_lk -= 1/2 sum_{ij} L~^{xyz}_{ijk} t^{xyz}_{ijl}.
+    Returns D_lk."""
+    no, _, nv, _ = t2.shape
+    Gw = blk.full_vvvo()                                              # g_{bdck}[b][d][c][k]
+    Go = np.stack([blk.ovvv(i) for i in range(no)], axis=0)           # g_{ibdc}[i][b][d][c]
+    eo = eps[:no]
+    Dijk = eo[:, None, None] + eo[None, :, None] + eo[None, None, :]
+    D_lk = np.zeros((no, no))
+    if triples is None:
+        triples = virtual_triples(nv)
+    for (a, b, c) in triples:
+        lab = (int(a), int(b), int(c))
+        if lab[0] == lab[1] == lab[2]:
+            continue
+        ev = eps[no + lab[0]] + eps[no + lab[1]] + eps[no + lab[2]]
+        tau = -_p_virtual(lambda x, y, z: _w_virtual(lab[x], lab[y], lab[z], t2, Gw, blk)) \
+            / (ev - Dijk)
+        lam = _p_virtual(lambda x, y, z: _c_virtual(lab[x], lab[y], lab[z], l1, l2, F, Go, blk)) \
+            / (omega - (ev - Dijk))
+        # L~^{abc}_{ijk} = 4 L^{abc} - 2 L^{acb} - 2 L^{cba} - 2 L^{bac} + L^{bca} + L^{cab}
+        lt = (4.0 * lam - 2.0 * np.einsum("ikj->ijk", lam) - 2.0 * np.einsum("kji->ijk", lam)
+              - 2.0 * np.einsum("jik->ijk", lam) + np.einsum("kij->ijk", lam)
+              + np.einsum("jki->ijk", lam))
+        seen = set()
+        for order, src in _VPERM:
+            xyz = tuple(lab["abc".index(ch)] for ch in order)
+            if xyz in seen:
+                continue
+            seen.add(xyz)
+            D_lk -= 0.5 * _e("ijk,ijl->lk", _virtual_perm(lt, src), _virtual_perm(tau, src))
+    return D_lk
+
+
+def transition_density(eps, L, t1, t2, l1, l2, omega):
+    """Algorithm 3 from Cholesky vectors: the triples contributions (D_cd, D_kc, D_ld, D_lk)
+    to D^{m,0} for the left state (l1, l2, omega)."""
+    no = t1.shape[0]
+    Lt = t1_transform(L, t1)
+    blk = IntegralBlocks(Lt, no)
+    F = fock_ov(L, t1)
+    D_cd, D_kc, D_ld, _ = transition_density_occupied(eps, t2, l1, l2, omega, blk, F)
+    D_lk = transition_density_virtual(eps, t2, l1, l2, omega, blk, F)
+    return D_cd, D_kc, D_ld, D_lk

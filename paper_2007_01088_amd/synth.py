@@ -62,6 +62,21 @@ def make_inputs(no: int, nv: int, nchol: int, tag: int = 0, t1_zero: bool = Fals
     }
 
 
+def make_left_inputs(no: int, nv: int, tag: int = 0) -> dict:
+    """Seeded left-state amplitudes for the transition-density contributions: an
+    excitation energy omega uniform in [0.2, 0.6] (below every triples excitation of
+    make_inputs' orbital energies, which start at 2.1), l1[i][a] ~ N(0, 0.05^2) and
+    l2[i][j][a][b] ~ N(0, (1e-2)^2) with the pair symmetry of t2.  Draw order: omega,
+    l1, l2."""
+    if no < 1 or nv < 1:
+        raise ValueError("sizes must be positive")
+    g = np.random.default_rng([SEED_BASE, 13, int(no), int(nv), int(tag)])
+    omega = float(g.uniform(0.2, 0.6))
+    l1 = g.normal(0.0, 0.05, size=(no, nv))
+    l2 = mirror_pairs(g.normal(0.0, 1e-2, size=(no, no, nv, nv)))
+    return {"omega": omega, "l1": np.ascontiguousarray(l1), "l2": l2}
+
+
 def perturb_t2(t2: np.ndarray, seed: int, scale: float = 1e-4) -> np.ndarray:
     """A solver-iteration-like update: t2 + N(0, scale^2), pair symmetry kept."""
     g = np.random.default_rng([SEED_BASE, 7, int(seed)])

@@ -282,3 +282,85 @@ def test_jacobian_prep_homogeneity_and_special_cases():
     e = make_inputs(1, 5, 7)
     zv1, zo1 = O.jacobian_prep(e["eps"], e["L"], e["t1"], e["t2"])
     assert not zv1.any() and not zo1.any()
+
+
+# --------------------------------------------------------------------------
+# Algorithm 3: the triples contributions to the transition densities.
+# --------------------------------------------------------------------------
+
+def _alg3(no, nv, nJ, t1z=False, scale_l=1.0, zero_l1=False, zero_l2=False, zero_t2=False):
+    from paper_2007_01088_amd.synth import make_left_inputs
+    d = make_inputs(no, nv, nJ, t1_zero=t1z)
+    lf = make_left_inputs(no, nv)
+    l1 = 0.0 * lf["l1"] if zero_l1 else scale_l * lf["l1"]
+    l2 = 0.0 * lf["l2"] if zero_l2 else scale_l * lf["l2"]
+    t2 = 0.0 * d["t2"] if zero_t2 else d["t2"]
+    return d, l1, l2, t2, lf["omega"]
+
+
+@pytest.mark.parametrize("no,nv,nJ,t1z", [(3, 4, 6, False), (4, 5, 8, False), (4, 3, 5, True),
+                                          (2, 6, 9, False), (5, 3, 7, False)])
+def test_transition_density_loops_equal_bruteforce(no, nv, nJ, t1z):
+    """Algorithm 3's two restricted loops (occupied i >= j >= k for D_cd, D_kc, Y^o, D_ld;
+    virtual a >= b >= c for D_lk, with t3 and L3 built for fixed virtual indices) reach the
+    plain definition over all ordered index tuples with full T3 and L3 tensors, whose
+    integrals come from the full four-index T1 transformation."""
+    d, l1, l2, t2, w = _alg3(no, nv, nJ, t1z)
+    got = O.transition_density(d["eps"], d["L"], d["t1"], t2, l1, l2, w)
+    Lt = O.t1_transform(d["L"], d["t1"])
+    blk = O.IntegralBlocks(Lt, no)
+    F = O.fock_ov(d["L"], d["t1"])
+    Y = O.transition_density_occupied(d["eps"], t2, l1, l2, w, blk, F)[3]
+    ref = B.transition_density_bruteforce(d["eps"], d["L"], d["t1"], t2, l1, l2, w)
+    for name, g, r in zip(("D_cd", "D_kc", "D_ld", "D_lk", "Y^o"), list(got) + [Y], ref):
+        assert np.abs(r).max() > 0, name
+        assert rel(g, r) < 1e-12, (name, rel(g, r))
+
+
+@pytest.mark.parametrize("no,nv,nJ", [(4, 6, 10), (6, 4, 8), (3, 9, 12)])
+def test_transition_density_trace_identity(no, nv, nJ):
+    """tr D_vv = (1/2) sum L~ t3 = - tr D_oo: the occupied loop's D_cd and the virtual loop's
+    D_lk (separate t3 and L3 builders) must cancel in the trace."""
+    d, l1, l2, t2, w = _alg3(no, nv, nJ)
+    D_cd, _, _, D_lk = O.transition_density(d["eps"], d["L"], d["t1"], t2, l1, l2, w)
+    tv, to = np.trace(D_cd), np.trace(D_lk)
+    assert abs(tv) > 0
+    assert abs(tv + to) <= 1e-12 * abs(tv), (tv, to)
+
+
+def test_l3_permutational_symmetry():
+    """L^{abc}_{ijk} = L^{bac}_{jik} = L^{cba}_{kji} = L^{acb}_{ikj} = L^{cab}_{kij} = L^{bca}_{jki}
+    (P^{abc}_{ijk} symmetrises the builder), checked on an all-distinct triple."""
+    from paper_2007_01088_amd.synth import make_left_inputs
+    d = make_inputs(4, 5, 8)
+    lf = make_left_inputs(4, 5)
+    blk, F = _blocks(d)
+    args = (lf["omega"], d["eps"], lf["l1"], lf["l2"], blk, F)
+    ref = O.l3_amplitudes(3, 1, 0, *args)
+    for (i, j, k), lab in (((1, 3, 0), "bac"), ((0, 1, 3), "cba"), ((3, 0, 1), "acb"),
+                           ((0, 3, 1), "cab"), ((1, 0, 3), "bca")):
+        other = O.l3_amplitudes(i, j, k, *args)
+        assert rel(np.einsum(lab + "->abc", other), ref) < 1e-13, (i, j, k)
+
+
+def test_transition_density_linearity_and_special_cases():
+    """The densities are linear in the left amplitudes (L3 is), vanish without them or
+    without t2 (t3 = 0), and vanish for a single occupied or virtual orbital (every
+    contravariant L3 with all-equal indices is zero)."""
+    no, nv, nJ = 3, 4, 6
+    d, l1, l2, t2, w = _alg3(no, nv, nJ)
+    full = O.transition_density(d["eps"], d["L"], d["t1"], t2, l1, l2, w)
+    only1 = O.transition_density(d["eps"], d["L"], d["t1"], t2, l1, 0.0 * l2, w)
+    only2 = O.transition_density(d["eps"], d["L"], d["t1"], t2, 0.0 * l1, l2, w)
+    twice = O.transition_density(d["eps"], d["L"], d["t1"], t2, 2.0 * l1, 2.0 * l2, w)
+    for f, a, b, t in zip(full, only1, only2, twice):
+        assert rel(a + b, f) < 1e-12
+        assert rel(t, 2.0 * f) < 1e-12
+    for x in O.transition_density(d["eps"], d["L"], d["t1"], 0.0 * t2, l1, l2, w):
+        assert not np.any(x)
+    for x in O.transition_density(d["eps"], d["L"], d["t1"], t2, 0.0 * l1, 0.0 * l2, w):
+        assert not np.any(x)
+    for (n_o, n_v) in ((1, 4), (3, 1)):
+        d1, a1, a2, b2, w1 = _alg3(n_o, n_v, 5)
+        for x in O.transition_density(d1["eps"], d1["L"], d1["t1"], b2, a1, a2, w1):
+            assert np.abs(x).max() < 1e-18

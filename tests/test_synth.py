@@ -34,3 +34,17 @@ def test_perturb_and_sample():
     assert np.all(s[:, 0] >= s[:, 1]) and np.all(s[:, 1] >= s[:, 2])
     assert not np.any((s[:, 0] == s[:, 1]) & (s[:, 1] == s[:, 2]))
     assert len({tuple(t) for t in s}) == 10
+
+
+def test_left_inputs_deterministic_and_symmetric():
+    from paper_2007_01088_amd.synth import make_left_inputs
+    a = make_left_inputs(4, 9)
+    b = make_left_inputs(4, 9)
+    assert a["omega"] == b["omega"] and 0.2 <= a["omega"] <= 0.6
+    for key in ("l1", "l2"):
+        assert _h(a[key]) == _h(b[key])
+    assert _h(make_left_inputs(4, 9, tag=1)["l2"]) != _h(a["l2"])
+    assert np.array_equal(a["l2"], a["l2"].transpose(1, 0, 3, 2))
+    # omega stays below every triples excitation of make_inputs' orbital energies
+    eps = make_inputs(4, 9, 12)["eps"]
+    assert a["omega"] < 3 * eps[4:].min() - 3 * eps[:4].max()
