@@ -12,8 +12,12 @@ Algorithm 2 (the t3-dependent intermediates of the preparation for the
 Jacobian transformations); and Algorithm 3 (the triples contributions to the
 transition densities D^{m,0}: the occupied loop for the vv, ov and vo blocks and
 the loop over the virtual indices for the oo block).
-Every step is a numpy einsum over float64 arrays, taken in the order the
-algorithm states; no blocking, fusion or reordering beyond it.
+Every step is a numpy einsum over float64 arrays, with no blocking or fusion.
+The residual is written as its definition, a sum over every ordered occupied
+triple (p, q, r) of contributions of the contravariant amplitudes of that
+triple; the ordered triples are visited grouped by their sorted form, whose
+amplitudes are built once (the restricted loop i >= j >= k) and relabelled for
+the other orderings by the permutational symmetry of t3.
 
 Readings of the paper used here (each is listed in the design notes):
   * The T1 transformation (Sec. Theory, H = exp(-T1) H exp(T1)) acts on the
@@ -43,11 +47,14 @@ g_vvov[d][b][k][c] = g_{dbkc}, F[k][c].
 """
 from __future__ import annotations
 
+import itertools
+
 import numpy as np
 
 __all__ = [
     "t1_transform", "IntegralBlocks", "fock_ov", "w_term", "t3_amplitudes",
-    "contravariant", "occupied_permutations", "unordered_triples", "omega_tilde",
+    "contravariant", "orderings", "relabel", "occupied_permutations", "unordered_triples",
+    "omega_tilde",
     "back_transform", "triples_residual", "triples_residual_blocks",
     "omega_tilde_subset", "nominal_flops", "FlopCounter", "jacobian_prep_tilde",
     "jacobian_prep", "l3_amplitudes", "virtual_triples", "transition_density_occupied",
@@ -217,28 +224,35 @@ def contravariant(tau: np.ndarray) -> np.ndarray:
             + np.einsum("cab->abc", tau))
 
 
-def occupied_permutations(i: int, j: int, k: int, tt: np.ndarray):
-    """The distinct occupied permutations (p,q,r) of (i,j,k) with tau~_{pqr} as a view of tau~_{ijk}.
-
-    From the permutational symmetry tau^{abc}_{ijk} = tau^{bac}_{jik} = tau^{cba}_{kji}
-    = tau^{acb}_{ikj} = tau^{cab}_{kij} = tau^{bca}_{jki} (Sec. Implementation), which
-    tau~ shares because its coefficients are the same for every relabelling:
-      (i,j,k): tt[a,b,c]   (j,i,k): tt[b,a,c]   (k,j,i): tt[c,b,a]
-      (i,k,j): tt[a,c,b]   (j,k,i): tt[c,a,b]   (k,i,j): tt[b,c,a]
-    Six terms when i, j, k differ, three when two are equal.
-    """
-    cand = [
-        ((i, j, k), "abc"), ((j, i, k), "bac"), ((k, j, i), "cba"),
-        ((i, k, j), "acb"), ((j, k, i), "cab"), ((k, i, j), "bca"),
-    ]
-    seen = set()
-    out = []
-    for pqr, lab in cand:
-        if pqr in seen:
-            continue
-        seen.add(pqr)
-        out.append((pqr, np.einsum(lab + "->abc", tt)))
+def orderings(i: int, j: int, k: int):
+    """The distinct ordered triples (p, q, r) made of the occupied indices i, j, k, each with
+    the axis permutation perm that gives it: (p, q, r) = ((i, j, k)[perm[0]], ...).  Six when
+    i, j, k differ, three when two are equal, one when all three are."""
+    base = (i, j, k)
+    out, seen = [], set()
+    for perm in itertools.permutations(range(3)):
+        pqr = tuple(base[m] for m in perm)
+        if pqr not in seen:
+            seen.add(pqr)
+            out.append((pqr, perm))
     return out
+
+
+def relabel(block: np.ndarray, perm) -> np.ndarray:
+    """X_{pqr} from X_{ijk} for (p,q,r) = (i,j,k) taken in the order perm.
+
+    By the permutational symmetry of Sec. Implementation, tau^{abc}_{ijk} is unchanged
+    when the pairs (a,i), (b,j), (c,k) are permuted together; so the virtual index paired
+    with the m-th occupied index of (p,q,r) sits on axis perm[m] of X_{ijk}:
+    X_{pqr}[a0, a1, a2] = X_{ijk}[y] with y[perm[m]] = a_m, which is numpy's transpose.
+    The contravariant amplitudes share the symmetry (their coefficients are the same for
+    every relabelling), and so do the left-state amplitudes of Algorithm 3."""
+    return np.transpose(block, perm)
+
+
+def occupied_permutations(i: int, j: int, k: int, tt: np.ndarray):
+    """[((p,q,r), X_{pqr})] over the distinct orderings of (i,j,k), X_{ijk} = tt."""
+    return [(pqr, relabel(tt, perm)) for pqr, perm in orderings(i, j, k)]
 
 
 def unordered_triples(no: int):
@@ -249,26 +263,31 @@ def unordered_triples(no: int):
 
 def omega_tilde(eps: np.ndarray, t2: np.ndarray, blk: IntegralBlocks, F: np.ndarray,
                 triples=None, flops: FlopCounter | None = None):
-    """The contravariant residual contributions of Algorithm 1 from the given unordered triples.
+    """The contravariant residual of the CC3 ground-state equations (Algorithm 1).
 
-    For each distinct permutation (p,q,r) with U = tau~_{pqr}:
-        Ot^a_p     += sum_{bc} U^{abc} g_{qbrc}
-        Ot^{ab}_{pq} += sum_c  U^{abc} F_{rc}
-        Ot^{ab}_{pl} -= sum_c  U^{abc} g_{qlrc}        (all l)
-        Ot^{ad}_{pq} += sum_{bc} U^{abc} g_{dbrc}       (all d)
+    By definition it sums, over every ordered occupied triple (p, q, r) (those with
+    p == q == r contribute nothing: their contravariant amplitudes vanish), with
+    U = tau~_{pqr}:
+        Ot1[p][a]    = sum_{bc} U[a,b,c] g_{qbrc}
+        Ot2[p][q][a][b] = sum_c U[a,b,c] F_{rc}
+        Ot2[p][l][a][b] = - sum_c U[a,b,c] g_{qlrc}       for every l
+        Ot2[p][q][a][d] = sum_{bc} U[a,b,c] g_{dbrc}      for every d
+    (each line adds into the named block).  `triples` lists unordered triples
+    i >= j >= k (default: all of them); each stands for its distinct orderings, whose
+    amplitudes are the relabelled amplitudes of the sorted triple.
     """
     no, _, nv, _ = t2.shape
     Ot1 = np.zeros((no, nv))
     Ot2 = np.zeros((no, no, nv, nv))
     if triples is None:
         triples = unordered_triples(no)
-    for (i, j, k) in triples:
-        i, j, k = int(i), int(j), int(k)
+    for rep in triples:
+        i, j, k = (int(x) for x in rep)
         if i == j == k:
             continue
-        tau = t3_amplitudes(i, j, k, eps, t2, blk, flops)
-        tt = contravariant(tau)
-        for (p, q, r), U in occupied_permutations(i, j, k, tt):
+        tt = contravariant(t3_amplitudes(i, j, k, eps, t2, blk, flops))
+        for (p, q, r), perm in orderings(i, j, k):
+            U = relabel(tt, perm)
             Ot1[p] += _e("abc,bc->a", U, blk.g_ovov[q, :, r, :], flops=flops)
             Ot2[p, q] += _e("abc,c->ab", U, F[r], flops=flops)
             Ot2[p] -= _e("abc,lc->lab", U, blk.g_ooov[q, :, r, :], flops=flops)
@@ -321,26 +340,28 @@ def nominal_flops(no: int, nv: int) -> float:
 
 def jacobian_prep_tilde(eps: np.ndarray, t2: np.ndarray, blk: IntegralBlocks, triples=None,
                         flops: FlopCounter | None = None):
-    """The intermediates of Algorithm 2 from the given unordered triples.
+    """The t3-dependent intermediates of the preparation for the Jacobian transformations
+    (Algorithm 2).
 
-    The same restricted loop, t3 and contravariant t3 as Algorithm 1; then for each
-    distinct permutation (p,q,r) of (i,j,k), with U = tau~_{pqr}:
-        Zv^{ab}_{pd} -= sum_c    U^{abc} g_{qdrc}
-        Zo^{a}_{qpl} += sum_{bc} U^{abc} g_{lbrc}
+    By definition they sum, over every ordered occupied triple (p, q, r), with
+    U = tau~_{pqr} (the amplitudes and their contravariant form of Algorithm 1):
+        Zv[a][b][p][d] -= sum_c    U[a,b,c] g_{qdrc}
+        Zo[a][q][p][l] += sum_{bc} U[a,b,c] g_{lbrc}
     Arrays (row-major): Zv[a][b][i][d] = Z~^v_{abid}, Zo[a][j][i][l] = Z~^o_{ajil}.
+    `triples` lists unordered triples, each standing for its distinct orderings.
     """
     no, _, nv, _ = t2.shape
     Zv = np.zeros((nv, nv, no, nv))
     Zo = np.zeros((nv, no, no, no))
     if triples is None:
         triples = unordered_triples(no)
-    for (i, j, k) in triples:
-        i, j, k = int(i), int(j), int(k)
+    for rep in triples:
+        i, j, k = (int(x) for x in rep)
         if i == j == k:
             continue
-        tau = t3_amplitudes(i, j, k, eps, t2, blk, flops)
-        tt = contravariant(tau)
-        for (p, q, r), U in occupied_permutations(i, j, k, tt):
+        tt = contravariant(t3_amplitudes(i, j, k, eps, t2, blk, flops))
+        for (p, q, r), perm in orderings(i, j, k):
+            U = relabel(tt, perm)
             Zv[:, :, p, :] -= _e("abc,dc->abd", U, blk.g_ovov[q, :, r, :], flops=flops)
             Zo[:, q, p, :] += _e("abc,lbc->al", U, blk.g_ovov[:, :, r, :], flops=flops)
     return Zv, Zo
@@ -396,15 +417,16 @@ def l3_amplitudes(i: int, j: int, k: int, omega: float, eps: np.ndarray, l1: np.
 
 
 def transition_density_occupied(eps, t2, l1, l2, omega, blk: IntegralBlocks, F, triples=None):
-    """The loop over i >= j >= k of Algorithm 3: D_cd, D_kc, then D_ld from Y^o.
+    """The occupied-index loop of Algorithm 3: D_cd, D_kc, then D_ld from Y^o.
 
-    Per triple: t3 (Algorithm 1), L3 and its contravariant L~; for each distinct
-    permutation (p,q,r) of (i,j,k)
-        Y^o_{c l p r} += sum_{ab} L~^{abc}_{pqr} t^{ab}_{lq}
-        D_cd          += 1/2 sum_{ab} L~^{abc}_{pqr} t^{abd}_{pqr}
-    then, with t~ the contravariant t3, for each distinct permutation
-        D_{rc}        += sum_{ab} L^{ab}_{pq} t~^{abc}_{pqr};
-    after the loop  D_ld -= sum_{cik} Y^o_{clik} t^{cd}_{ki}.
+    With tau_{pqr} the ground-state amplitudes (Algorithm 1), L_{pqr} the left-state
+    triples (l3_amplitudes), and L~, tau~ their contravariant forms, the contributions
+    sum over every ordered occupied triple (p, q, r):
+        Y^o[c][l][p][r] += sum_{ab} L~_{pqr}[a,b,c] t2[l][q][a][b]
+        D_cd[c][d]      += 1/2 sum_{ab} L~_{pqr}[a,b,c] tau_{pqr}[a,b,d]
+        D_kc[r][c]      += sum_{ab} l2[p][q][a][b] tau~_{pqr}[a,b,c]
+    and after the sum  D_ld[l][d] = - sum_{cik} Y^o[c][l][i][k] t2[k][i][c][d].
+    `triples` lists unordered triples, each standing for its distinct orderings.
     Returns (D_cd, D_kc, D_ld, Y^o)."""
     no, _, nv, _ = t2.shape
     D_cd = np.zeros((nv, nv))
@@ -412,17 +434,17 @@ def transition_density_occupied(eps, t2, l1, l2, omega, blk: IntegralBlocks, F, 
     Y = np.zeros((nv, no, no, no))
     if triples is None:
         triples = unordered_triples(no)
-    for (i, j, k) in triples:
-        i, j, k = int(i), int(j), int(k)
+    for rep in triples:
+        i, j, k = (int(x) for x in rep)
         if i == j == k:
             continue
         tau = t3_amplitudes(i, j, k, eps, t2, blk)
+        tt = contravariant(tau)
         lt = contravariant(l3_amplitudes(i, j, k, omega, eps, l1, l2, blk, F))
-        for ((p, q, r), LT), (_, T) in zip(occupied_permutations(i, j, k, lt),
-                                           occupied_permutations(i, j, k, tau)):
+        for (p, q, r), perm in orderings(i, j, k):
+            LT, T, TT = relabel(lt, perm), relabel(tau, perm), relabel(tt, perm)
             Y[:, :, p, r] += _e("abc,lab->cl", LT, t2[:, q])
             D_cd += 0.5 * _e("abc,abd->cd", LT, T)
-        for (p, q, r), TT in occupied_permutations(i, j, k, contravariant(tau)):
             D_kc[r] += _e("ab,abc->c", l2[p, q], TT)
     D_ld = -_e("clik,kicd->ld", Y, t2)
     return D_cd, D_kc, D_ld, Y
