@@ -175,6 +175,21 @@ int cc3_triples_residual_subset(cc3_ctx* ctx, int no, int nv, int nchol, const d
                                 double* omega2_tilde, int prec, unsigned flags, void* workspace,
                                 size_t workspace_bytes, cc3_stream_t stream);
 
+/* cc3_triples_residual_subset from integral blocks in the T1-transformed basis
+ * (the same six blocks, layouts and host/device handling as
+ * cc3_triples_residual_blocks) instead of Cholesky vectors: sampled parity and
+ * a triple-partitioned run on integrals the caller holds.  Workspace from
+ * cc3_workspace_size(no, nv, 0, prec, flags).  Errors as for
+ * cc3_triples_residual_subset. */
+int cc3_triples_residual_subset_blocks(cc3_ctx* ctx, int no, int nv, const double* eps,
+                                       const double* g_vvvo, const double* g_oovo,
+                                       const double* g_ovov, const double* g_ooov,
+                                       const double* g_vvov, const double* F_ov, const double* t2,
+                                       const int32_t* triples, int ntriples, double* omega1_tilde,
+                                       double* omega2_tilde, int prec, unsigned flags,
+                                       void* workspace, size_t workspace_bytes,
+                                       cc3_stream_t stream);
+
 /* Debug export of the t3 amplitudes of one ordered triple (i, j, k) (any order,
  * not all equal): tau[a][b][c] = tau^{abc}_{ijk} = -(eps^{abc}_{ijk})^{-1} P^{abc}_{ijk} B^{abc}_{ijk}
  * (Algorithm 1, first statement), written to tau[nv][nv][nv] (device or host); the
@@ -183,6 +198,16 @@ int cc3_triples_residual_subset(cc3_ctx* ctx, int no, int nv, int nchol, const d
 int cc3_t3_block(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps, const double* L,
                  const double* t1, const double* t2, int i, int j, int k, double* tau, int prec,
                  void* workspace, size_t workspace_bytes, cc3_stream_t stream);
+
+/* cc3_t3_block from integral blocks in the T1-transformed basis (the six blocks,
+ * layouts and host/device handling of cc3_triples_residual_blocks; the amplitudes
+ * read g_vvvo and g_oovo, the other four are loaded as by every blocks-form call).
+ * Workspace from cc3_workspace_size(no, nv, 0, prec, 0).  Errors as for cc3_t3_block. */
+int cc3_t3_block_blocks(cc3_ctx* ctx, int no, int nv, const double* eps, const double* g_vvvo,
+                        const double* g_oovo, const double* g_ovov, const double* g_ooov,
+                        const double* g_vvov, const double* F_ov, const double* t2, int i, int j,
+                        int k, double* tau, int prec, void* workspace, size_t workspace_bytes,
+                        cc3_stream_t stream);
 
 /* The t3-dependent intermediates of the preparation for the Jacobian
  * transformations (Sec. "Implementation", Algorithm 2): the same restricted loop,
@@ -199,6 +224,53 @@ int cc3_t3_block(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps, con
 int cc3_jacobian_prep(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps, const double* L,
                       const double* t1, const double* t2, double* zv, double* zo, int prec,
                       unsigned flags, void* workspace, size_t workspace_bytes, cc3_stream_t stream);
+
+/* How the one-shot calls batch the restricted loop for these sizes (host-only,
+ * no context needed): *triples_per_batch receives the unordered triples per
+ * batch, *nbatches the number of batches.  The loop's triples, in lexicographic
+ * order (i >= j >= k, i == j == k excluded), are dealt round-robin: batch b holds
+ * the loop positions b, b + nbatches, b + 2 nbatches, ...  Passing one batch's
+ * triples, in that order, to cc3_triples_residual_subset reproduces the launch
+ * configuration of that batch in the whole call (sampled parity, sharding).
+ * Errors: CC3_E_INVAL (sizes as for cc3_workspace_size, NULL outputs). */
+int cc3_batch_plan(int no, int nv, int nchol, int prec, unsigned flags, int* triples_per_batch,
+                   int* nbatches);
+
+/* Bytes of device workspace for cc3_transition_density at these sizes (host-only).
+ * Supported sizes: 1 <= no <= 63, 1 <= nv <= 400, nchol >= 1.
+ * Errors: CC3_E_INVAL. */
+int cc3_transition_density_workspace_size(int no, int nv, int nchol, size_t* bytes);
+
+/* The triples contributions to the transition density D^{m,0} of one left state
+ * (Sec. "Implementation", Algorithm 3).  With tau the ground-state t3 of
+ * Algorithm 1, the left-state triples
+ *   L^{abc}_{ijk} = (omega - eps^{abc}_{ijk})^{-1} P^{abc}_{ijk} (L^a_i g_{jbkc} + L^{ab}_{ij} F_kc
+ *                   + sum_d L^{ad}_{jk} g_{ibdc} - sum_l L^{ab}_{lk} g_{iljc}),
+ * and L~, tau~ the contravariant combinations (virtual indices permuted at fixed
+ * i, j, k), summed over every ordered occupied triple (p, q, r):
+ *   D_cd[c][d] += 1/2 sum_ab L~_{pqr}[a,b,c] tau_{pqr}[a,b,d]
+ *   D_kc[r][c] += sum_ab l2[p][q][a][b] tau~_{pqr}[a,b,c]
+ *   Y^o[c][l][p][r] += sum_ab L~_{pqr}[a,b,c] t2[l][q][a][b],
+ *   D_ld[l][d] -= sum_{cik} Y^o[c][l][i][k] t2[k][i][c][d],
+ *   D_lk[l][k] -= 1/2 sum_{ij} sum_{abc} L~^{abc}_{ijk} tau^{abc}_{ijl}.
+ * The integrals and F_kc are the T1-transformed ones of cc3_triples_residual.
+ * The occupied-occupied block, which the paper evaluates in a loop over virtual
+ * triples, is evaluated here as the Gram matrices <L~_{ijk}, tau_{ijl}> of the
+ * cubes of each occupied pair (i, j); the loop runs over those pairs.
+ * Inputs (device memory only): eps[no+nv], L[nchol][nmo][nmo], t1[no][nv],
+ * t2[no][no][nv][nv] as for cc3_triples_residual; l1[no][nv] = L^a_i and
+ * l2[no][no][nv][nv] = L^{ab}_{ij} (l2[i][j][a][b] == l2[j][i][b][a]) of the left
+ * state; omega its excitation energy (omega - eps^{abc}_{ijk} must not vanish).
+ * Outputs (device memory, row-major, overwritten or added with CC3_ACCUMULATE):
+ * D_cd[nv][nv], D_kc[no][nv], D_ld[no][nv], D_lk[no][no]; Yo[nv][no][no][no] = Y^o
+ * (may be NULL).  FP64 throughout.  flags: CC3_ACCUMULATE, CC3_DETERMINISTIC.
+ * workspace: at least cc3_transition_density_workspace_size bytes, 256-byte aligned.
+ * Errors: CC3_E_INVAL (sizes, flags, host pointers), CC3_E_NOMEM, CC3_E_DEVICE. */
+int cc3_transition_density(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps,
+                           const double* L, const double* t1, const double* t2, const double* l1,
+                           const double* l2, double omega, double* D_cd, double* D_kc,
+                           double* D_ld, double* D_lk, double* Yo, unsigned flags, void* workspace,
+                           size_t workspace_bytes, cc3_stream_t stream);
 
 /* FLOP per residual call: *nominal = 4 nv^4 no^3 (the paper's asymptotic count,
  * abstract); *executed = the multiply-adds (x2) this library's triple loop

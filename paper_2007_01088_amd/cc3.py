@@ -54,10 +54,23 @@ _residual_blocks = _sig("cc3_triples_residual_blocks",
 _residual_subset = _sig("cc3_triples_residual_subset",
                         [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _vp, _c_int, _dp, _dp,
                          _c_int, ctypes.c_uint, _vp, _c_size, _vp])
+_residual_subset_blocks = _sig("cc3_triples_residual_subset_blocks",
+                               [_vp, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _vp,
+                                _c_int, _dp, _dp, _c_int, ctypes.c_uint, _vp, _c_size, _vp])
+_t3_block_blocks = _sig("cc3_t3_block_blocks",
+                        [_vp, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _c_int,
+                         _c_int, _c_int, _dp, _c_int, _vp, _c_size, _vp])
 _t3_block = _sig("cc3_t3_block", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _c_int, _c_int,
                                   _c_int, _dp, _c_int, _vp, _c_size, _vp])
 _jprep = _sig("cc3_jacobian_prep", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp, _dp,
                                      _c_int, ctypes.c_uint, _vp, _c_size, _vp])
+_td_ws = _sig("cc3_transition_density_workspace_size",
+               [_c_int, _c_int, _c_int, ctypes.POINTER(_c_size)])
+_td = _sig("cc3_transition_density",
+           [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, _dp, _dp,
+            _dp, _dp, _dp, ctypes.c_uint, _vp, _c_size, _vp])
+_batch_plan = _sig("cc3_batch_plan", [_c_int, _c_int, _c_int, _c_int, ctypes.c_uint,
+                                      ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)])
 _flops = _sig("cc3_flops", [_c_int, _c_int, ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double)])
 _cvs = _sig("cc3_cvs_triples", [_c_int, ctypes.POINTER(ctypes.c_int32), _c_int,
@@ -104,7 +117,9 @@ _srv_stats = _sig("cc3_server_get_stats", [_vp, ctypes.POINTER(ServerStats)])
 
 EXPORTED = ["cc3_create", "cc3_destroy", "cc3_last_error", "cc3_workspace_size",
             "cc3_triples_residual", "cc3_triples_residual_blocks", "cc3_triples_residual_subset",
-            "cc3_t3_block", "cc3_flops", "cc3_cvs_triples", "cc3_profile_enable", "cc3_profile_get",
+            "cc3_t3_block", "cc3_triples_residual_subset_blocks", "cc3_t3_block_blocks",
+            "cc3_flops", "cc3_batch_plan",
+            "cc3_transition_density_workspace_size", "cc3_transition_density", "cc3_cvs_triples", "cc3_profile_enable", "cc3_profile_get",
             "cc3_jacobian_prep", "cc3_server_create", "cc3_server_destroy", "cc3_server_footprint",
             "cc3_molecule_register", "cc3_molecule_release", "cc3_submit", "cc3_poll",
             "cc3_wait", "cc3_cancel", "cc3_server_get_stats"]
@@ -159,6 +174,22 @@ def cvs_triples(no: int, core) -> np.ndarray:
         _check(_cvs(no, cp, int(c.size), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                     n.value, ctypes.byref(n)), "cc3_cvs_triples")
     return out
+
+
+def batch_plan(no: int, nv: int, nchol: int, prec: int = FP64, flags: int = 0) -> tuple[int, int]:
+    """(triples per batch, number of batches) of the one-shot calls' triple loop."""
+    b, n = _c_int(0), _c_int(0)
+    _check(_batch_plan(no, nv, nchol, prec, flags, ctypes.byref(b), ctypes.byref(n)),
+           "cc3_batch_plan")
+    return b.value, n.value
+
+
+def batch_triples(no: int, nbatches: int, b: int):
+    """The unordered triples of batch b (int32 [n][3]): loop positions b, b + nbatches, ..."""
+    import numpy as np
+    allt = [(i, j, k) for i in range(no) for j in range(i + 1) for k in range(j + 1)
+            if not (i == j == k)]
+    return np.array(allt[b::nbatches], dtype=np.int32).reshape(-1, 3)
 
 
 def flops(no: int, nv: int) -> tuple[float, float]:
@@ -259,6 +290,39 @@ class Context:
                          prec, ws.data_ptr(), ws.numel(), _stream(stream)), "cc3_t3_block")
         return tau
 
+    def triples_residual_subset_blocks(self, eps, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov,
+                                       t2, triples, prec=FP64, flags=0, stream=None):
+        """Contravariant (Ot1, Ot2) of the listed triples from integral blocks."""
+        import numpy as np
+        no, nv = F_ov.shape
+        tri = np.ascontiguousarray(np.asarray(triples, dtype=np.int32).reshape(-1, 3))
+        o1 = torch.empty((no, nv), dtype=torch.float64, device=t2.device)
+        o2 = torch.empty((no, no, nv, nv), dtype=torch.float64, device=t2.device)
+        nbytes = workspace_size(no, nv, 0, prec, flags)
+        ws = self.workspace(nbytes)
+        _check(_residual_subset_blocks(
+            self._h, no, nv, _any_ptr(eps, "eps"), _any_ptr(g_vvvo, "g_vvvo"),
+            _any_ptr(g_oovo, "g_oovo"), _any_ptr(g_ovov, "g_ovov"), _any_ptr(g_ooov, "g_ooov"),
+            _any_ptr(g_vvov, "g_vvov"), _any_ptr(F_ov, "F_ov"), _any_ptr(t2, "t2"),
+            tri.ctypes.data_as(ctypes.c_void_p), int(tri.shape[0]), _any_ptr(o1, "o1"),
+            _any_ptr(o2, "o2"), prec, flags, ws.data_ptr(), ws.numel(), _stream(stream)),
+            "cc3_triples_residual_subset_blocks")
+        return o1, o2
+
+    def t3_block_blocks(self, eps, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov, t2, i, j, k,
+                        prec=FP64, stream=None):
+        no, nv = F_ov.shape
+        tau = torch.empty((nv, nv, nv), dtype=torch.float64, device=t2.device)
+        nbytes = workspace_size(no, nv, 0, prec, 0)
+        ws = self.workspace(nbytes)
+        _check(_t3_block_blocks(
+            self._h, no, nv, _any_ptr(eps, "eps"), _any_ptr(g_vvvo, "g_vvvo"),
+            _any_ptr(g_oovo, "g_oovo"), _any_ptr(g_ovov, "g_ovov"), _any_ptr(g_ooov, "g_ooov"),
+            _any_ptr(g_vvov, "g_vvov"), _any_ptr(F_ov, "F_ov"), _any_ptr(t2, "t2"), i, j, k,
+            _any_ptr(tau, "tau"), prec, ws.data_ptr(), ws.numel(), _stream(stream)),
+            "cc3_t3_block_blocks")
+        return tau
+
     def jacobian_prep(self, eps, L, t1, t2, zv=None, zo=None, prec=FP64, flags=0, stream=None):
         """Algorithm 2 intermediates: zv[a][b][i][d] = Z~v_{abid}, zo[a][j][i][l] = Z~o_{ajil}."""
         no, nv = t1.shape
@@ -273,6 +337,30 @@ class Context:
                       _ptr(t2, "t2"), _ptr(zv, "zv"), _ptr(zo, "zo"), prec, flags, ws.data_ptr(),
                       ws.numel(), _stream(stream)), "cc3_jacobian_prep")
         return zv, zo
+
+    def transition_density(self, eps, L, t1, t2, l1, l2, omega, flags=0, want_yo=False,
+                           out=None, stream=None):
+        """Algorithm 3: (D_cd, D_kc, D_ld, D_lk[, Yo]) for the left state (l1, l2, omega)."""
+        no, nv = t1.shape
+        nchol = L.shape[0]
+        dev = t2.device
+        if out is None:
+            out = (torch.empty((nv, nv), dtype=torch.float64, device=dev),
+                   torch.empty((no, nv), dtype=torch.float64, device=dev),
+                   torch.empty((no, nv), dtype=torch.float64, device=dev),
+                   torch.empty((no, no), dtype=torch.float64, device=dev),
+                   torch.empty((nv, no, no, no), dtype=torch.float64, device=dev)
+                   if want_yo else None)
+        n = _c_size(0)
+        _check(_td_ws(no, nv, nchol, ctypes.byref(n)), "cc3_transition_density_workspace_size")
+        ws = self.workspace(n.value)
+        dcd, dkc, dld, dlk, yo = out
+        _check(_td(self._h, no, nv, nchol, _ptr(eps, "eps"), _ptr(L, "L"), _ptr(t1, "t1"),
+                   _ptr(t2, "t2"), _ptr(l1, "l1"), _ptr(l2, "l2"), float(omega),
+                   _ptr(dcd, "D_cd"), _ptr(dkc, "D_kc"), _ptr(dld, "D_ld"), _ptr(dlk, "D_lk"),
+                   _ptr(yo, "Yo"), flags, ws.data_ptr(), ws.numel(), _stream(stream)),
+               "cc3_transition_density")
+        return out if want_yo else out[:4]
 
     # ---- kernel timing ---------------------------------------------------
     def profile_enable(self, on: bool = True) -> None:

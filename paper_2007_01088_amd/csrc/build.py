@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libcc3.so")
-SOURCES = ["kern_prep.hip", "kern_triples.hip", "kern_wlp.hip", "cc3_core.cpp", "cc3_api.cpp", "cc3_server.cpp"]
+SOURCES = ["kern_prep.hip", "kern_triples.hip", "kern_wlp.hip", "kern_density.hip", "cc3_core.cpp",
+           "cc3_api.cpp", "cc3_server.cpp", "cc3_density.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -13,12 +13,6 @@
 
 using namespace cc3;
 
-struct cc3_ctx {
-  int device;
-  Profiler prof;
-  Runner run;
-  std::mutex mu;
-};
 
 extern "C" const char* cc3_last_error(void) { return last_error_str(); }
 
@@ -64,6 +58,18 @@ extern "C" int cc3_workspace_size(int no, int nv, int nchol, int prec, unsigned 
   Plan p;
   make_plan_ex(no, nv, nchol, prec, flags, true, 0, &p);
   *bytes = p.total;
+  return CC3_OK;
+}
+
+extern "C" int cc3_batch_plan(int no, int nv, int nchol, int prec, unsigned flags,
+                              int* triples_per_batch, int* nbatches) {
+  if (!triples_per_batch || !nbatches) return fail(CC3_E_INVAL, "cc3_batch_plan: NULL output");
+  int rc = check_sizes(no, nv, nchol, prec);
+  if (rc) return rc;
+  Plan p;
+  make_plan_ex(no, nv, nchol, prec, flags, true, 0, &p);
+  *triples_per_batch = p.batch;
+  *nbatches = (p.ntri + p.batch - 1) / p.batch;
   return CC3_OK;
 }
 
@@ -178,6 +184,64 @@ static int stage_inputs(HostArgs& h, const Plan& p, const Ws& w, void* ws, const
   return h.in(t2, "t2", w.st_t2, o * o * v * v);
 }
 
+// The integral blocks of a blocks-form call (paper index order, device or host)
+// into the internal layouts of the workspace.  Host blocks pass through the cube
+// region: the small ones whole, then slabs of the first virtual index of g_vvvo
+// and g_vvov (as many as fit).
+static int load_blocks(Profiler* pf, HostArgs& h, const Plan& p, const Ws& w, void* ws,
+                       const double* g_vvvo, const double* g_oovo, const double* g_ovov,
+                       const double* g_ooov, const double* g_vvov, const double* F_ov,
+                       hipStream_t st) {
+  const int no = p.no, nv = p.nv;
+  const size_t o = no, v = nv;
+  int rc;
+  {
+    Timer tm(pf, st, FAM_BUILD, 0.0, 0.0);
+    // host blocks pass through the cube region: the small ones whole, then
+    // slabs of the first virtual index of g_vvvo and g_vvov
+    char* cr = (char*)ws + p.off_cubes;
+    const size_t b3 = (o * o * o * v * 8 + 255) & ~(size_t)255;
+    const size_t b2 = (o * o * v * v * 8 + 255) & ~(size_t)255;
+    const size_t b1 = (o * v * 8 + 255) & ~(size_t)255;
+    if ((rc = h.in(g_oovo, "g_oovo", (double*)cr, o * o * o * v))) return rc;
+    if ((rc = h.in(g_ooov, "g_ooov", (double*)(cr + b3), o * o * o * v))) return rc;
+    if ((rc = h.in(g_ovov, "g_ovov", (double*)(cr + 2 * b3), o * o * v * v))) return rc;
+    if ((rc = h.in(F_ov, "F_ov", (double*)(cr + 2 * b3 + b2), o * v))) return rc;
+    launch_relayout_small(g_oovo, g_ovov, g_ooov, F_ov, w.b, no, nv, st);
+    bool hv = false, hw = false;
+    if ((rc = classify_ptr(g_vvvo, "g_vvvo", &hv)) || (rc = classify_ptr(g_vvov, "g_vvov", &hw)))
+      return rc;
+    const size_t slab = o * v * v;  // doubles per first index of g_vvvo and g_vvov
+    int ny = nv;
+    if (hv || hw) {
+      const size_t small = 2 * b3 + b2 + b1, region = p.total - p.off_cubes;
+      const size_t fit = (region - small) / (2 * ((slab * 8 + 255) & ~(size_t)255));
+      ny = (int)std::max<size_t>(1, std::min<size_t>(nv, fit));
+      const char* cap = getenv("CC3_STAGE_Y");  // smaller slabs (tests of the staging)
+      if (cap && atoi(cap) > 0) ny = std::min(ny, atoi(cap));
+    }
+    double* sa = (double*)(cr + 2 * b3 + b2 + b1);
+    double* sb = sa + (size_t)ny * slab;
+    for (int y0 = 0; y0 < nv; y0 += ny) {
+      const int n = std::min(ny, nv - y0);
+      const double* a = g_vvvo + (size_t)y0 * slab;
+      const double* b = g_vvov + (size_t)y0 * slab;
+      if (hv) {
+        HIPCHK(hipMemcpyAsync(sa, a, n * slab * 8, hipMemcpyHostToDevice, st));
+        a = sa;
+      }
+      if (hw) {
+        HIPCHK(hipMemcpyAsync(sb, b, n * slab * 8, hipMemcpyHostToDevice, st));
+        b = sb;
+      }
+      launch_relayout_vv(a, b, y0, n, w.b, no, nv, st);
+    }
+    h.any = h.any || hv || hw;
+    launch_gcb(w.b, no, nv, st);
+  }
+  return CC3_OK;
+}
+
 static int common_checks(cc3_ctx* c, int no, int nv, int nchol, int prec, unsigned flags,
                          void* ws, size_t ws_bytes, Plan* p) {
   if (!c) return fail(CC3_E_INVAL, "ctx is NULL");
@@ -247,85 +311,35 @@ extern "C" int cc3_triples_residual_blocks(cc3_ctx* c, int no, int nv, const dou
   if ((rc = h.out(omega2, "omega2", w.t2N, o * o * v * v, O2))) return rc;
   if (acc && (rc = h.preload(O1))) return rc;
   if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, nullptr, t2, st))) return rc;
-  {
-    Timer tm(&c->prof, st, FAM_BUILD, 0.0, 0.0);
-    // host blocks pass through the cube region: the small ones whole, then
-    // slabs of the first virtual index of g_vvvo and g_vvov
-    char* cr = (char*)ws + p.off_cubes;
-    const size_t b3 = (o * o * o * v * 8 + 255) & ~(size_t)255;
-    const size_t b2 = (o * o * v * v * 8 + 255) & ~(size_t)255;
-    const size_t b1 = (o * v * 8 + 255) & ~(size_t)255;
-    if ((rc = h.in(g_oovo, "g_oovo", (double*)cr, o * o * o * v))) return rc;
-    if ((rc = h.in(g_ooov, "g_ooov", (double*)(cr + b3), o * o * o * v))) return rc;
-    if ((rc = h.in(g_ovov, "g_ovov", (double*)(cr + 2 * b3), o * o * v * v))) return rc;
-    if ((rc = h.in(F_ov, "F_ov", (double*)(cr + 2 * b3 + b2), o * v))) return rc;
-    launch_relayout_small(g_oovo, g_ovov, g_ooov, F_ov, w.b, no, nv, st);
-    bool hv = false, hw = false;
-    if ((rc = classify_ptr(g_vvvo, "g_vvvo", &hv)) || (rc = classify_ptr(g_vvov, "g_vvov", &hw)))
-      return rc;
-    const size_t slab = o * v * v;  // doubles per first index of g_vvvo and g_vvov
-    int ny = nv;
-    if (hv || hw) {
-      const size_t small = 2 * b3 + b2 + b1, region = p.total - p.off_cubes;
-      const size_t fit = (region - small) / (2 * ((slab * 8 + 255) & ~(size_t)255));
-      ny = (int)std::max<size_t>(1, std::min<size_t>(nv, fit));
-      const char* cap = getenv("CC3_STAGE_Y");  // smaller slabs (tests of the staging)
-      if (cap && atoi(cap) > 0) ny = std::min(ny, atoi(cap));
-    }
-    double* sa = (double*)(cr + 2 * b3 + b2 + b1);
-    double* sb = sa + (size_t)ny * slab;
-    for (int y0 = 0; y0 < nv; y0 += ny) {
-      const int n = std::min(ny, nv - y0);
-      const double* a = g_vvvo + (size_t)y0 * slab;
-      const double* b = g_vvov + (size_t)y0 * slab;
-      if (hv) {
-        HIPCHK(hipMemcpyAsync(sa, a, n * slab * 8, hipMemcpyHostToDevice, st));
-        a = sa;
-      }
-      if (hw) {
-        HIPCHK(hipMemcpyAsync(sb, b, n * slab * 8, hipMemcpyHostToDevice, st));
-        b = sb;
-      }
-      launch_relayout_vv(a, b, y0, n, w.b, no, nv, st);
-    }
-    h.any = h.any || hv || hw;
-    launch_gcb(w.b, no, nv, st);
-  }
+  if ((rc = load_blocks(&c->prof, h, p, w, ws, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov, st)))
+    return rc;
   if ((rc = residual_from_blocks(c->run, &c->prof, p, w, eps, t2, O1.dev, O2.dev, acc, st,
                                  acc ? O2.host : nullptr)))
     return rc;
   return h.finish({&O1, &O2});
 }
 
-extern "C" int cc3_triples_residual_subset(cc3_ctx* c, int no, int nv, int nchol,
-                                           const double* eps, const double* L, const double* t1,
-                                           const double* t2, const int32_t* triples, int ntriples,
-                                           double* omega1_tilde, double* omega2_tilde, int prec,
-                                           unsigned flags, void* ws, size_t ws_bytes,
-                                           cc3_stream_t stream) {
-  Plan p;
-  int rc = common_checks(c, no, nv, nchol, prec, flags, ws, ws_bytes, &p);
-  if (rc) return rc;
-  if (nchol < 1) return fail(CC3_E_INVAL, "nchol must be >= 1 for the Cholesky form");
+// Unordered triples i >= j >= k, not all equal, below no.
+static int check_triples(const Plan& p, const int32_t* triples, int ntriples) {
   if (ntriples < 0 || ntriples > p.ntri)
     return fail(CC3_E_INVAL, "ntriples %d out of range [0, %d]", ntriples, p.ntri);
   if (ntriples > 0 && !triples) return fail(CC3_E_INVAL, "triples is NULL");
   for (int t = 0; t < ntriples; ++t) {
     const int i = triples[3 * t], j = triples[3 * t + 1], k = triples[3 * t + 2];
-    if (!(i < no && i >= j && j >= k && k >= 0) || (i == j && j == k))
+    if (!(i < p.no && i >= j && j >= k && k >= 0) || (i == j && j == k))
       return fail(CC3_E_INVAL, "triple %d = (%d,%d,%d) is not an unordered triple i>=j>=k "
-                  "(not all equal) below no=%d", t, i, j, k, no);
+                  "(not all equal) below no=%d", t, i, j, k, p.no);
   }
-  hipStream_t st = (hipStream_t)stream;
-  Ws w = carve(p, ws, nullptr);
-  std::lock_guard<std::mutex> g(c->mu);
-  HostArgs h{st};
-  HostArgs::Out O1, O2;
-  if ((rc = stage_inputs(h, p, w, ws, eps, L, t1, t2))) return rc;
-  if ((rc = h.out(omega1_tilde, "omega1_tilde", w.st_o1, (size_t)no * nv, O1))) return rc;
-  if ((rc = h.out(omega2_tilde, "omega2_tilde", w.t2N, (size_t)no * no * nv * nv, O2))) return rc;
-  if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, L, t2, st))) return rc;
-  if ((rc = prepare_cholesky(&c->prof, p, w, L, t1, st))) return rc;
+  return CC3_OK;
+}
+
+// The contravariant residual of the listed triples, once the integral blocks are in
+// place: Ot <- 0, the batched loop over the list, Ot~2 = Ot2 + OtT^T, outputs.
+static int subset_from_blocks(cc3_ctx* c, const Plan& p, const Ws& w, HostArgs& h,
+                              const double* eps, const double* t2, const int32_t* triples,
+                              int ntriples, HostArgs::Out& O1, HostArgs::Out& O2, hipStream_t st) {
+  const int no = p.no, nv = p.nv;
+  int rc;
   launch_fill(w.Ot1, (int64_t)no * nv, 0.0, st);
   launch_fill(w.Ot2, (int64_t)no * no * nv * nv, 0.0, st);
   launch_fill(w.OtT, (int64_t)no * no * nv * nv, 0.0, st);
@@ -342,6 +356,84 @@ extern "C" int cc3_triples_residual_subset(cc3_ctx* c, int no, int nv, int nchol
   return CC3_OK;
 }
 
+extern "C" int cc3_triples_residual_subset(cc3_ctx* c, int no, int nv, int nchol,
+                                           const double* eps, const double* L, const double* t1,
+                                           const double* t2, const int32_t* triples, int ntriples,
+                                           double* omega1_tilde, double* omega2_tilde, int prec,
+                                           unsigned flags, void* ws, size_t ws_bytes,
+                                           cc3_stream_t stream) {
+  Plan p;
+  int rc = common_checks(c, no, nv, nchol, prec, flags, ws, ws_bytes, &p);
+  if (rc) return rc;
+  if (nchol < 1) return fail(CC3_E_INVAL, "nchol must be >= 1 for the Cholesky form");
+  if ((rc = check_triples(p, triples, ntriples))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Ws w = carve(p, ws, nullptr);
+  std::lock_guard<std::mutex> g(c->mu);
+  HostArgs h{st};
+  HostArgs::Out O1, O2;
+  if ((rc = stage_inputs(h, p, w, ws, eps, L, t1, t2))) return rc;
+  if ((rc = h.out(omega1_tilde, "omega1_tilde", w.st_o1, (size_t)no * nv, O1))) return rc;
+  if ((rc = h.out(omega2_tilde, "omega2_tilde", w.t2N, (size_t)no * no * nv * nv, O2))) return rc;
+  if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, L, t2, st))) return rc;
+  if ((rc = prepare_cholesky(&c->prof, p, w, L, t1, st))) return rc;
+  return subset_from_blocks(c, p, w, h, eps, t2, triples, ntriples, O1, O2, st);
+}
+
+extern "C" int cc3_triples_residual_subset_blocks(
+    cc3_ctx* c, int no, int nv, const double* eps, const double* g_vvvo, const double* g_oovo,
+    const double* g_ovov, const double* g_ooov, const double* g_vvov, const double* F_ov,
+    const double* t2, const int32_t* triples, int ntriples, double* omega1_tilde,
+    double* omega2_tilde, int prec, unsigned flags, void* ws, size_t ws_bytes,
+    cc3_stream_t stream) {
+  Plan p;
+  int rc = common_checks(c, no, nv, 0, prec, flags, ws, ws_bytes, &p);
+  if (rc) return rc;
+  if ((rc = check_triples(p, triples, ntriples))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Ws w = carve(p, ws, nullptr);
+  std::lock_guard<std::mutex> g(c->mu);
+  HostArgs h{st};
+  HostArgs::Out O1, O2;
+  const double* none = nullptr;
+  if ((rc = stage_inputs(h, p, w, ws, eps, none, none, t2))) return rc;
+  if ((rc = h.out(omega1_tilde, "omega1_tilde", w.st_o1, (size_t)no * nv, O1))) return rc;
+  if ((rc = h.out(omega2_tilde, "omega2_tilde", w.t2N, (size_t)no * no * nv * nv, O2))) return rc;
+  if ((flags & CC3_CHECK) && (rc = run_input_check(p, w, eps, nullptr, t2, st))) return rc;
+  if ((rc = load_blocks(&c->prof, h, p, w, ws, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov, st)))
+    return rc;
+  return subset_from_blocks(c, p, w, h, eps, t2, triples, ntriples, O1, O2, st);
+}
+
+// tau^{abc}_{ijk} of one ordered triple once the integral blocks are in place.
+static int t3_from_blocks(const Plan& p, const Ws& w, HostArgs& hs, const double* eps,
+                          const double* t2, int i, int j, int k, HostArgs::Out& T,
+                          hipStream_t st) {
+  const int no = p.no, nv = p.nv;
+  int rc;
+  const int h[3] = {i, j, k};
+  HIPCHK(hipMemcpyAsync(w.tri, h, sizeof h, hipMemcpyHostToDevice, st));
+  launch_t2N(t2, w.t2N, no, nv, st);
+  if (p.prec == CC3_FP64) {
+    launch_wbuild(t2, w.t2N, w.b, w.tri, 1, w.cubes[0], no, nv, true, st);
+  } else {
+    launch_lp_convert(t2, w.b, no, nv, w.lp, st);
+    launch_wbuild_lp(w.lp, w.tri, 1, w.cubes[0], no, nv, true, st);
+  }
+  launch_tau_export(eps, w.tri, w.cubes[0], T.dev, no, nv, st);
+  HIPCHK(hipGetLastError());
+  if ((rc = hs.finish({&T}))) return rc;
+  HIPCHK(hipStreamSynchronize(st));  // the host triple was copied on st
+  return CC3_OK;
+}
+
+static int check_ordered(int no, int i, int j, int k) {
+  if (i < 0 || j < 0 || k < 0 || i >= no || j >= no || k >= no || (i == j && j == k))
+    return fail(CC3_E_INVAL, "(%d,%d,%d) is not an ordered triple of indices < %d, not all equal",
+                i, j, k, no);
+  return CC3_OK;
+}
+
 extern "C" int cc3_t3_block(cc3_ctx* c, int no, int nv, int nchol, const double* eps,
                             const double* L, const double* t1, const double* t2, int i, int j,
                             int k, double* tau, int prec, void* ws, size_t ws_bytes,
@@ -350,9 +442,7 @@ extern "C" int cc3_t3_block(cc3_ctx* c, int no, int nv, int nchol, const double*
   int rc = common_checks(c, no, nv, nchol, prec, 0, ws, ws_bytes, &p);
   if (rc) return rc;
   if (nchol < 1) return fail(CC3_E_INVAL, "nchol must be >= 1 for the Cholesky form");
-  if (i < 0 || j < 0 || k < 0 || i >= no || j >= no || k >= no || (i == j && j == k))
-    return fail(CC3_E_INVAL, "(%d,%d,%d) is not an ordered triple of distinct-enough indices < %d",
-                i, j, k, no);
+  if ((rc = check_ordered(no, i, j, k))) return rc;
   hipStream_t st = (hipStream_t)stream;
   Ws w = carve(p, ws, nullptr);
   std::lock_guard<std::mutex> g(c->mu);
@@ -362,20 +452,32 @@ extern "C" int cc3_t3_block(cc3_ctx* c, int no, int nv, int nchol, const double*
   // a host tau is produced in the second cube buffer set, unused by this call
   if ((rc = hs.out(tau, "tau", w.cubes[1], (size_t)nv * nv * nv, T))) return rc;
   if ((rc = prepare_cholesky(&c->prof, p, w, L, t1, st))) return rc;
-  const int h[3] = {i, j, k};
-  HIPCHK(hipMemcpyAsync(w.tri, h, sizeof h, hipMemcpyHostToDevice, st));
-  launch_t2N(t2, w.t2N, no, nv, st);
-  if (prec == CC3_FP64) {
-    launch_wbuild(t2, w.t2N, w.b, w.tri, 1, w.cubes[0], no, nv, true, st);
-  } else {
-    launch_lp_convert(t2, w.b, no, nv, w.lp, st);
-    launch_wbuild_lp(w.lp, w.tri, 1, w.cubes[0], no, nv, true, st);
-  }
-  launch_tau_export(eps, w.tri, w.cubes[0], T.dev, no, nv, st);
-  HIPCHK(hipGetLastError());
-  if ((rc = hs.finish({&T}))) return rc;
-  HIPCHK(hipStreamSynchronize(st));
-  return CC3_OK;
+  return t3_from_blocks(p, w, hs, eps, t2, i, j, k, T, st);
+}
+
+extern "C" int cc3_t3_block_blocks(cc3_ctx* c, int no, int nv, const double* eps,
+                                   const double* g_vvvo, const double* g_oovo,
+                                   const double* g_ovov, const double* g_ooov,
+                                   const double* g_vvov, const double* F_ov, const double* t2,
+                                   int i, int j, int k, double* tau, int prec, void* ws,
+                                   size_t ws_bytes, cc3_stream_t stream) {
+  Plan p;
+  int rc = common_checks(c, no, nv, 0, prec, 0, ws, ws_bytes, &p);
+  if (rc) return rc;
+  if ((rc = check_ordered(no, i, j, k))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Ws w = carve(p, ws, nullptr);
+  std::lock_guard<std::mutex> g(c->mu);
+  HostArgs hs{st};
+  HostArgs::Out T;
+  const double* none = nullptr;
+  if ((rc = stage_inputs(hs, p, w, ws, eps, none, none, t2))) return rc;
+  // a host tau is produced in the second cube buffer set; host blocks staged through the
+  // cube region have been consumed (earlier on the same stream) when the export writes it
+  if ((rc = hs.out(tau, "tau", w.cubes[1], (size_t)nv * nv * nv, T))) return rc;
+  if ((rc = load_blocks(&c->prof, hs, p, w, ws, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov, st)))
+    return rc;
+  return t3_from_blocks(p, w, hs, eps, t2, i, j, k, T, st);
 }
 
 extern "C" int cc3_jacobian_prep(cc3_ctx* c, int no, int nv, int nchol, const double* eps,
@@ -403,3 +505,4 @@ extern "C" int cc3_jacobian_prep(cc3_ctx* c, int no, int nv, int nchol, const do
   return jacobian_prep_from_blocks(c->run, &c->prof, p, w, eps, t2, zv, zo,
                                    (flags & CC3_ACCUMULATE) != 0, st);
 }
+

@@ -70,7 +70,7 @@ int classify_ptr(const void* p, const char* what, bool* host) {
 // ---------------------------------------------------------------------------
 const char* kFamilies[NFAM] = {"t1_transform", "block_build",    "w_build",       "mix",
                                "omega_contract", "reduce",        "back_transform", "jacobian_prep",
-                               "omega_oo"};
+                               "omega_oo",       "l3_build",      "density_contract"};
 
 hipEvent_t Profiler::take() {
   if (!pool.empty()) {
@@ -205,16 +205,26 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   p->ntri = (int)((size_t)no * (no + 1) * (no + 2) / 6 - no);
   p->cube = v * v * v;
   // triples per batch: enough W-build workgroups per launch to fill 256 CUs
-  // many times over, bounded by a cube-memory budget
+  // many times over, and at least min(no, 16) triples, so that the kernels that
+  // are parallel over the first occupied index p (the oo contraction, the
+  // reductions) find pairs for most p in every batch; bounded by a cube-memory
+  // budget per buffer set (32 GiB by default: 12 triples at nv = 400)
   const size_t wg_per_triple = 3 * v * ((v + 127) / 128) * ((v + 127) / 128);
   int batch = (int)std::max<size_t>(1, (size_t)(12288 + wg_per_triple - 1) / wg_per_triple);
+  batch = std::max(batch, std::min(no, 16));
   const size_t budget =
-      cube_budget ? cube_budget : ((size_t)env_int("CC3_CUBE_BUDGET_MB", 4096) << 20);
+      cube_budget ? cube_budget : ((size_t)env_int("CC3_CUBE_BUDGET_MB", 32768) << 20);
   const size_t per_triple = 5 * p->cube * sizeof(double);
   batch = (int)std::min<size_t>((size_t)batch, std::max<size_t>(1, budget / per_triple));
   batch = env_int("CC3_BATCH", batch);
   batch = std::min(batch, MAX_BATCH);  // bounds the kernels' per-p pair lists
   batch = std::max(1, std::min(batch, std::max(1, p->ntri)));
+  // balanced: the loop is split into ceil(ntri / batch) batches whose sizes differ by at
+  // most one, and `batch` becomes the largest of them
+  if (p->ntri > 0) {
+    const int nb = (p->ntri + batch - 1) / batch;
+    batch = (p->ntri + nb - 1) / nb;
+  }
   p->batch = batch;
   // largest (triples x chunks) product over the batch sizes the loop can see
   size_t tc = 1;
@@ -315,6 +325,16 @@ Ws carve(const Plan& p, void* ws, const Blocks* external_blocks) {
 // ---------------------------------------------------------------------------
 // launch sequences
 // ---------------------------------------------------------------------------
+static int nbatches(const Plan& p) { return (p.ntri + p.batch - 1) / p.batch; }
+
+// Batch g of n triples split into nbatch batches whose sizes differ by at most one
+// (the layout of the dealt triple table): first position and size.
+static void batch_range(int n, int nbatch, int g, int* t0, int* nb) {
+  const int q = n / nbatch, r = n % nbatch;
+  *t0 = g * q + std::min(g, r);
+  *nb = q + (g < r ? 1 : 0);
+}
+
 // Host copy of the device triple table (launch_triple_table): the restricted loop
 // in lexicographic order, dealt round-robin over nbatch batches.
 static void host_triples(int no, int nbatch, std::vector<int>& t) {
@@ -327,13 +347,12 @@ static void host_triples(int no, int nbatch, std::vector<int>& t) {
   nbatch = std::max(1, nbatch);
   t.assign(lex.size(), 0);
   for (int L = 0; L < n; ++L) {
-    const int g = L % nbatch;
-    const int pos = g * (n / nbatch) + std::min(g, n % nbatch) + L / nbatch;
+    int t0, nb;
+    batch_range(n, nbatch, L % nbatch, &t0, &nb);
+    const int pos = t0 + L / nbatch;
     for (int c = 0; c < 3; ++c) t[3 * pos + c] = lex[3 * L + c];
   }
 }
-
-static int nbatches(const Plan& p) { return (p.ntri + p.batch - 1) / p.batch; }
 
 static int kind_of(int i, int j, int k) { return (i == j) ? 1 : (j == k) ? 2 : 0; }
 
@@ -358,10 +377,34 @@ int prepare_cholesky(Profiler* pf, const Plan& p, const Ws& w, const double* L, 
 // host copy is `ht` (for FLOP accounting only).  Batch b runs on runner
 // stream b % 2 with buffer set b % 2; reduction b waits for reduction b - 1.
 // Forks from and joins back to `st`.
+// After a failure inside the batched loop: make `st` wait for whatever the runner
+// streams hold (best effort, errors ignored), so that a caller that synchronises
+// `st` before releasing the workspace also waits for work enqueued there.
+static void join_runner(Runner& rn, hipStream_t st) {
+  if (!rn.ready) return;
+  for (int k = 0; k < NSTREAM; ++k) {
+    if (hipEventRecord(rn.ev_done[k], rn.s[k]) == hipSuccess)
+      (void)hipStreamWaitEvent(st, rn.ev_done[k], 0);
+  }
+  (void)hipGetLastError();
+}
+
+static int triple_loop_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w,
+                            const double* eps, const double* t2, const int* tri, const int* ht,
+                            int n, hipStream_t st);
+
 int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const double* eps,
                 const double* t2, const int* tri, const int* ht, int n, hipStream_t st) {
   int rc = rn.init();
   if (rc) return rc;
+  rc = triple_loop_body(rn, pf, p, w, eps, t2, tri, ht, n, st);
+  if (rc) join_runner(rn, st);
+  return rc;
+}
+
+static int triple_loop_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w,
+                            const double* eps, const double* t2, const int* tri, const int* ht,
+                            int n, hipStream_t st) {
   std::vector<int> kinds;
   launch_t2N(t2, w.t2N, p.no, p.nv, st);
   if (p.prec != CC3_FP64) launch_lp_convert(t2, w.b, p.no, p.nv, w.lp, st);
@@ -381,9 +424,10 @@ int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const doub
   // CC3_ONE_STREAM (or CC3_SERIAL=1 in the environment) keeps every batch on one stream
   static const int env_serial = env_int("CC3_SERIAL", 0);
   const int nstream = (env_serial || (p.flags & CC3_ONE_STREAM)) ? 1 : NSTREAM;
-  int nbatch = 0;
-  for (int t0 = 0; t0 < n; t0 += p.batch, ++nbatch) {
-    const int nb = std::min(p.batch, n - t0);
+  const int ngroups = (n + p.batch - 1) / p.batch;
+  for (int nbatch = 0; nbatch < ngroups; ++nbatch) {
+    int t0, nb;
+    batch_range(n, ngroups, nbatch, &t0, &nb);
     const int k = nbatch % nstream;
     hipStream_t sk = rn.s[k];
     kinds.resize(nb);
@@ -457,12 +501,24 @@ int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, c
 // Algorithm 2 over every unordered triple: the same batched W build and mix as the
 // residual, then per batch the Zo partials on the batch's stream and, chained in
 // batch order, the Zo reduction and the output-stationary Zv contraction.
+static int jacobian_prep_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w,
+                              const double* eps, const double* t2, double* zv, double* zo,
+                              bool accumulate, hipStream_t st);
+
 int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w,
                               const double* eps, const double* t2, double* zv, double* zo,
                               bool accumulate, hipStream_t st) {
-  const int no = p.no, nv = p.nv;
   int rc = rn.init();
   if (rc) return rc;
+  rc = jacobian_prep_body(rn, pf, p, w, eps, t2, zv, zo, accumulate, st);
+  if (rc) join_runner(rn, st);
+  return rc;
+}
+
+static int jacobian_prep_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w,
+                              const double* eps, const double* t2, double* zv, double* zo,
+                              bool accumulate, hipStream_t st) {
+  const int no = p.no, nv = p.nv;
   if (!accumulate) {
     launch_fill(zv, (int64_t)nv * nv * nv * no, 0.0, st);
     launch_fill(zo, (int64_t)nv * no * no * no, 0.0, st);
@@ -477,9 +533,10 @@ int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws&
   static const int env_serial = env_int("CC3_SERIAL", 0);
   const int nstream = (env_serial || (p.flags & CC3_ONE_STREAM)) ? 1 : NSTREAM;
   const int n = p.ntri;
-  int nbatch = 0;
-  for (int t0 = 0; t0 < n; t0 += p.batch, ++nbatch) {
-    const int nb = std::min(p.batch, n - t0);
+  const int ngroups = nbatches(p);
+  for (int nbatch = 0; nbatch < ngroups; ++nbatch) {
+    int t0, nb;
+    batch_range(n, ngroups, nbatch, &t0, &nb);
     const int k = nbatch % nstream;
     hipStream_t sk = rn.s[k];
     kinds.resize(nb);

@@ -31,7 +31,8 @@ int check_dev_ptr(const void* p, const char* what);
 int classify_ptr(const void* p, const char* what, bool* host);
 
 // ---- kernel timing ------------------------------------------------------------
-enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_REDUCE, FAM_BACK, FAM_ZPREP, FAM_OMEGA_OO, NFAM };
+enum { FAM_T1 = 0, FAM_BUILD, FAM_W, FAM_MIX, FAM_OMEGA, FAM_REDUCE, FAM_BACK, FAM_ZPREP, FAM_OMEGA_OO,
+       FAM_L3, FAM_DENSITY, NFAM };
 extern const char* kFamilies[NFAM];
 
 struct TimedLaunch {
@@ -122,3 +123,11 @@ int run_input_check(const Plan& p, const Ws& w, const double* eps, const double*
                     const double* t2, hipStream_t st);
 
 }  // namespace cc3
+
+// A context of the one-shot calls: its device, kernel timing and runner streams.
+struct cc3_ctx {
+  int device;
+  cc3::Profiler prof;
+  cc3::Runner run;
+  std::mutex mu;
+};

@@ -15,9 +15,14 @@ constexpr int MAX_BATCH = 160;
 // triple kinds
 enum { TRI_DISTINCT = 0, TRI_IJ = 1, TRI_JK = 2 };
 
+// The kind of an ordered triple for the W build and mix: equal neighbours in the
+// first two or the last two positions let three of the six P terms repeat.  An
+// all-equal triple (which the residual's loop skips; the transition-density loop
+// needs its t3) takes every term.
 __host__ __device__ inline int tri_kind(int i, int j, int k) {
-  if (i == j) return TRI_IJ;  // i == j > k
-  if (j == k) return TRI_JK;  // i > j == k
+  if (i == j && j == k) return TRI_DISTINCT;
+  if (i == j) return TRI_IJ;  // i == j, k different
+  if (j == k) return TRI_JK;  // j == k, i different
   return TRI_DISTINCT;
 }
 
@@ -127,6 +132,13 @@ void launch_triple_table(int* tri, int no, int nbatch, hipStream_t st);
 void launch_t2N(const double* t2, double* t2N, int no, int nv, hipStream_t st);
 void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
                    double* cubes, int no, int nv, bool all_terms, hipStream_t st);
+// The W build's engine with explicit operands and output strides (doubles between
+// triples, zs, and between the three planes, ss).  mode 0: the t3 terms (X = t2,
+// XN = t2N, G = Gw, H = Go); mode 1: the left-state L3 terms of Algorithm 3 without
+// their outer-product parts (X = l2, XN = l2M, G = Gl, H = Go3).
+void launch_wbuild_ex(int mode, const double* X, const double* XN, const double* G, const double* H,
+                      const int* tri, int ntri, double* cubes, int64_t zs, int64_t ss, int no,
+                      int nv, bool all_terms, hipStream_t st);
 // Mixed-all copies (nullable): cubesF, FP32 tau~ and tau~T, [triple][2][nv^3]; YL,
 // the split-BF16 k-major views of k_omega_lp with lpP pieces
 void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF,
@@ -178,6 +190,15 @@ void launch_zv(const double* cubes, const Blocks& b, const int* tri, int ntri, d
 void launch_zo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pzo,
                double* Zo, int no, int nv, hipStream_t st, bool reduce);
 double zprep_flops(int no, int nv, const int* host_types, int n);
+
+// ---- transition densities (Algorithm 3) ----
+// Slots of the density loop's cubes, slot-major: cubes[slot][z][nv^3].
+enum { D3_P0 = 0, D3_P1 = 1, D3_P2 = 2, D3_TAU = 3, D3_TAUC = 4, D3_LC = 5, D3_NSLOT = 6 };
+// tau, tau~ (lmode false) or L~ (lmode true, with the outer products of the L3
+// statement from l1, l2, Jo, F and the shift omega) from the planes of each triple
+void launch_mix3(bool lmode, const double* eps, const int* tri, int ntri, double* cubes, int64_t ss,
+                 double omega, const double* l1, const double* l2, const double* Jo,
+                 const double* F, int no, int nv, hipStream_t st);
 
 // Algorithmic FLOP of one launch of the two dominant kernels (padding excluded).
 double wbuild_flops(int no, int nv, const int* host_types, int n);

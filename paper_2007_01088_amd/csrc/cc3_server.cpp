@@ -284,6 +284,8 @@ void cc3_server::run() {
         // the failed enqueue may have left work on the slot's streams: drain it
         // before the workspace goes back to the arena
         if (s.st) (void)hipStreamSynchronize(s.st);
+        for (int q = 0; q < NSTREAM; ++q)
+          if (s.rn.ready && s.rn.s[q]) (void)hipStreamSynchronize(s.rn.s[q]);
         (void)hipGetLastError();
         finish(t, rc, err.c_str());
         cv_done.notify_all();

@@ -362,6 +362,30 @@ void launch_build_blocks(const CholeskyScratch& cs, const Blocks& bl, int no, in
   launch_gcb(bl, no, nv, st);
 }
 
+// The blocks of the transition-density loop (Algorithm 3), in one grouped launch:
+// Gw, Go and Jo as for the residual; Go3[p][q][z][l] = g_{plqz} = sum_J Lt_pl L_qz;
+// Gl[p][y][z][d] = g_{pydz} = sum_J L_py Lt_dz, built as [p][y][d][z] into `tmp`
+// (no nv^3 doubles) and transposed per (p, y) slab.
+void launch_build_density_blocks(const CholeskyScratch& cs, double* Gw, double* Go, double* Jo,
+                                 double* Go3, double* Gl, double* tmp, int no, int nv, int nJ,
+                                 hipStream_t st) {
+  const int64_t nv2 = (int64_t)nv * nv, nv3 = nv2 * nv, onv = (int64_t)no * nv;
+  BuildSet set = {};
+  set.K = nJ; set.no = no; set.nv = nv; set.F = nullptr;
+  add_build(set, cs.LvoT, 1, onv, nv, cs.Lvv, nv2, 1, 0, nv, (int)nv2, Gw, nv3, no, BUILD_GW);
+  // tmp[(p,y)][(d,z)] = sum_J Lov[J][p][y] Lvv[J][d][z]
+  add_build(set, cs.Lov, 1, onv, 0, cs.Lvv, nv2, 1, 0, (int)onv, (int)nv2, tmp, 0, 1, BUILD_PLAIN);
+  add_build(set, cs.Lov, 1, onv, 0, cs.Lov, onv, 1, 0, (int)onv, (int)onv, Jo, 0, 1, BUILD_JO);
+  add_build(set, cs.LooT, 1, (int64_t)no * no, 0, cs.LvoT, onv, 1, 0, no * no, (int)onv, Go, 0,
+            1, BUILD_GO);
+  // Go3: m = p*no + l (Loo[J][p][l] = Lt_pl), n = q*nv + z (Lov[J][q][z] = L_qz)
+  add_build(set, cs.Loo, 1, (int64_t)no * no, 0, cs.Lov, onv, 1, 0, no * no, (int)onv, Go3, 0, 1,
+            BUILD_GO);
+  launch_build_set(set, st);
+  const unsigned t = nblk(nv, 32);
+  hipLaunchKernelGGL(k_gcb, dim3(t * t * no * nv), dim3(256), 0, st, tmp, Gl, nv);
+}
+
 // ---------------------------------------------------------------------------
 // Integral blocks given in the paper's index order -> internal layouts.
 // ---------------------------------------------------------------------------

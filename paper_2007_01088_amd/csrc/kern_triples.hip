@@ -39,13 +39,21 @@ enum { SLOT_P0 = 0, SLOT_P1 = 1, SLOT_P2 = 2, SLOT_TT = 3, SLOT_TTT = 4, NSLOT =
 // ---------------------------------------------------------------------------
 typedef TileCfg<4, 2, 2, 4, 16> WCfg;  // 128 x 128 output plane tile, 8 wavefronts, 16 k per stage
 
+// MODE 0: the t3 terms (t2, t2N, Gw, Go as named).  MODE 1: the L3 terms of
+// Algorithm 3, C_pqr[x,y,z] = sum_d L^{xd}_{qr} g_{pydz} - sum_l L^{xy}_{lr} g_{plqz}
+// (+ outer products added by the density mix), with t2 <- l2, t2N <- l2M
+// (l2M[r][y][x][l] = -l2[l][r][x][y]), Gw <- Gl (Gl[p][y][z][d] = g_{pydz}) and
+// Go <- Go3 (Go3[p][q][z][l] = g_{plqz}): the same segments with the roles of the
+// occupied indices permuted.  Plane `plane` of triple z goes to cubes + z zs + plane ss.
+template <int MODE>
 __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ t2,
                                                      const double* __restrict__ t2N,
                                                      const double* __restrict__ Gw,
                                                      const double* __restrict__ Go,
                                                      const int* __restrict__ tri,
-                                                     double* __restrict__ cubes, int no, int nv,
-                                                     int tiles_m, int tiles_n, int all_terms) {
+                                                     double* __restrict__ cubes, int64_t zs,
+                                                     int64_t ss, int no, int nv, int tiles_m,
+                                                     int tiles_n, int all_terms) {
   typedef WCfg T;
   __shared__ double lds[T::LDS_DOUBLES];
   const int tpp = tiles_m * tiles_n;
@@ -75,14 +83,20 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
   //                      + sum_l Go[q2][r2][m][l] t2N[p2][y][n][l]      (K = no)
   // with t2N[p][y][x][l] = -t2[p][l][x][y].  The row stride of a segment is its K.
   // Tile origins (row m0 / n0, k = 0) of the eight operands, as byte pointers:
-  const char* A0 = (const char*)(t2 + ((int64_t)p1 * no + q1) * nv2 + (int64_t)m0 * nv);
-  const char* B0 = (const char*)(Gw + ((int64_t)r1 * nv + y) * nv2 + (int64_t)n0 * nv);
-  const char* A1 = (const char*)(t2N + ((int64_t)p1 * nv + y) * nv * no + (int64_t)m0 * no);
-  const char* B1 = (const char*)(Go + ((int64_t)q1 * no + r1) * nv * no + (int64_t)n0 * no);
-  const char* A2 = (const char*)(Gw + ((int64_t)r2 * nv + y) * nv2 + (int64_t)m0 * nv);
-  const char* B2 = (const char*)(t2 + ((int64_t)p2 * no + q2) * nv2 + (int64_t)n0 * nv);
-  const char* A3 = (const char*)(Go + ((int64_t)q2 * no + r2) * nv * no + (int64_t)m0 * no);
-  const char* B3 = (const char*)(t2N + ((int64_t)p2 * nv + y) * nv * no + (int64_t)n0 * no);
+  // MODE 1 takes the amplitude pair (q, r), the (v v|. .) slab of p and the (o o|o v)
+  // slab of (p, q) where MODE 0 takes (p, q), r and (q, r)
+  const int ax1 = MODE ? q1 : p1, bx1 = MODE ? r1 : q1, g1 = MODE ? p1 : r1;
+  const int an1 = MODE ? r1 : p1, h1a = MODE ? p1 : q1, h1b = MODE ? q1 : r1;
+  const int ax2 = MODE ? q2 : p2, bx2 = MODE ? r2 : q2, g2 = MODE ? p2 : r2;
+  const int an2 = MODE ? r2 : p2, h2a = MODE ? p2 : q2, h2b = MODE ? q2 : r2;
+  const char* A0 = (const char*)(t2 + ((int64_t)ax1 * no + bx1) * nv2 + (int64_t)m0 * nv);
+  const char* B0 = (const char*)(Gw + ((int64_t)g1 * nv + y) * nv2 + (int64_t)n0 * nv);
+  const char* A1 = (const char*)(t2N + ((int64_t)an1 * nv + y) * nv * no + (int64_t)m0 * no);
+  const char* B1 = (const char*)(Go + ((int64_t)h1a * no + h1b) * nv * no + (int64_t)n0 * no);
+  const char* A2 = (const char*)(Gw + ((int64_t)g2 * nv + y) * nv2 + (int64_t)m0 * nv);
+  const char* B2 = (const char*)(t2 + ((int64_t)ax2 * no + bx2) * nv2 + (int64_t)n0 * nv);
+  const char* A3 = (const char*)(Go + ((int64_t)h2a * no + h2b) * nv * no + (int64_t)m0 * no);
+  const char* B3 = (const char*)(t2N + ((int64_t)an2 * nv + y) * nv * no + (int64_t)n0 * no);
   // This thread's part of every stage: k = kt and rows xt + e * RP of both tiles.  Rows
   // past nv repeat row nv - 1 (their outputs are never stored).  Loads go through buffer
   // resources built from the (uniform) stage origin with 32-bit byte offsets per lane.
@@ -166,7 +180,7 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
     __syncthreads();
   }
 
-  double* out = cubes + ((int64_t)z * NSLOT + plane) * nv3 + (int64_t)y * nv2;
+  double* out = cubes + (int64_t)z * zs + (int64_t)plane * ss + (int64_t)y * nv2;
 #pragma unroll
   for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
@@ -179,12 +193,25 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
       }
 }
 
+void launch_wbuild_ex(int mode, const double* X, const double* XN, const double* G, const double* H,
+                      const int* tri, int ntri, double* cubes, int64_t zs, int64_t ss, int no,
+                      int nv, bool all_terms, hipStream_t st) {
+  typedef WCfg T;
+  if (ntri <= 0) return;
+  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + T::BN - 1) / T::BN;
+  if (mode == 0)
+    hipLaunchKernelGGL(k_wbuild<0>, dim3(nv * tm * tn, 3, ntri), dim3(T::NT), 0, st, X, XN, G, H,
+                       tri, cubes, zs, ss, no, nv, tm, tn, all_terms ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_wbuild<1>, dim3(nv * tm * tn, 3, ntri), dim3(T::NT), 0, st, X, XN, G, H,
+                       tri, cubes, zs, ss, no, nv, tm, tn, all_terms ? 1 : 0);
+}
+
 void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
                    double* cubes, int no, int nv, bool all_terms, hipStream_t st) {
-  typedef WCfg T;
-  const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + T::BN - 1) / T::BN;
-  hipLaunchKernelGGL(k_wbuild, dim3(nv * tm * tn, 3, ntri), dim3(T::NT), 0, st, t2, t2N, b.Gw,
-                     b.Go, tri, cubes, no, nv, tm, tn, all_terms ? 1 : 0);
+  const int64_t nv3 = (int64_t)nv * nv * nv;
+  launch_wbuild_ex(0, t2, t2N, b.Gw, b.Go, tri, ntri, cubes, NSLOT * nv3, nv3, no, nv, all_terms,
+                   st);
 }
 
 // t2N[p][y][x][l] = -t2[p][l][x][y]
@@ -474,6 +501,147 @@ void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, floa
   else
     hipLaunchKernelGGL(k_mix<512>, dim3(nbt, ntri), dim3(512), 0, st, eps, tri, cubes, cubesF,
                        (uint16_t*)YL, lpP, no, nv);
+}
+
+// ---------------------------------------------------------------------------
+// Mix of the transition-density loop (Algorithm 3).  Cubes are slot-major,
+// cubes[slot][z][nv^3] (slot stride ss), so that each slot of a batch is one
+// contiguous run of cubes.  LMODE false: from the t3 planes, tau = -X/eps and
+// tau~ (the contravariant combination) into slots D3_TAU, D3_TAUC.  LMODE true:
+// from the L3 planes plus the outer-product terms of the L3 statement,
+//   sum over the six simultaneous permutations (p,q,r; x,y,z) of (i,j,k; a,b,c) of
+//   L^x_p g_{qyrz} + L^{xy}_{pq} F_{rz},
+// L = X / (omega - eps) and its contravariant L~ into slot D3_LC.
+// Same S3-orbit tiling of 8^3 virtual blocks as k_mix; outputs are written in
+// [a][b][c] order straight from the orientation tiles.
+// ---------------------------------------------------------------------------
+__device__ inline double l3_outer(const double* __restrict__ l1, const double* __restrict__ l2,
+                                  const double* __restrict__ Jo, const double* __restrict__ F,
+                                  int no, int64_t nv, int i, int j, int k, int a, int b, int c) {
+  auto term = [&](int p, int q, int r, int x, int y, int z) {
+    return l1[(int64_t)p * nv + x] * Jo[(((int64_t)q * no + r) * nv + y) * nv + z] +
+           l2[(((int64_t)p * no + q) * nv + x) * nv + y] * F[(int64_t)r * nv + z];
+  };
+  return term(i, j, k, a, b, c) + term(j, i, k, b, a, c) + term(k, j, i, c, b, a) +
+         term(i, k, j, a, c, b) + term(j, k, i, b, c, a) + term(k, i, j, c, a, b);
+}
+
+template <bool LMODE>
+__global__ __launch_bounds__(512) void k_mix3(const double* __restrict__ eps,
+                                             const int* __restrict__ tri,
+                                             double* __restrict__ cubes, int64_t ss, double omega,
+                                             const double* __restrict__ l1,
+                                             const double* __restrict__ l2,
+                                             const double* __restrict__ Jo,
+                                             const double* __restrict__ F, int no, int nv) {
+  __shared__ double Xs[6 * TSZ];
+  const int z = blockIdx.y, ob = blockIdx.x;
+  const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
+  const int kind = tri_kind(i, j, k);
+  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
+  const double* P0 = cubes + D3_P0 * ss + (int64_t)z * nv3;
+  const double* P1 = cubes + D3_P1 * ss + (int64_t)z * nv3;
+  const double* P2 = cubes + D3_P2 * ss + (int64_t)z * nv3;
+  int blk[3];
+  decode_block_triple(ob, blk[0], blk[1], blk[2]);
+  int canon[6];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
+    canon[o] = o;
+#pragma unroll
+    for (int o2 = 4; o2 >= 0; --o2) {
+      if (o2 >= o) continue;
+      int r0, r1, r2;
+      orient(o2, r0, r1, r2);
+      if (blk[r0] == blk[q0] && blk[r1] == blk[q1] && blk[r2] == blk[q2]) canon[o] = o2;
+    }
+  }
+  const int t = threadIdx.x;
+  const int u = t >> 6, v = (t >> 3) & 7, w = t & 7;
+  // X on the orbit: the plane sums of k_mix (c, b, then a fastest), plus the outer
+  // products in the L3 form
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    if (canon[o] != o) continue;
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
+    const int a = blk[q0] * MT + u, b = blk[q1] * MT + v, c = blk[q2] * MT + w;
+    double x = 0.0;
+    if (a < nv && b < nv && c < nv) {
+      x = P0[b * nv2 + a * nvl + c] + (kind == TRI_IJ ? P0 : P1)[a * nv2 + b * nvl + c];
+      if (LMODE) x += l3_outer(l1, l2, Jo, F, no, nvl, i, j, k, a, b, c);
+    }
+    Xs[o * TSZ + TP(u, v, w)] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    if (canon[o] != o) continue;
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
+    const int uu = t >> 6, ww = (t >> 3) & 7, vv = t & 7;  // b fastest
+    const int a = blk[q0] * MT + uu, b = blk[q1] * MT + vv, c = blk[q2] * MT + ww;
+    if (a < nv && b < nv && c < nv) {
+      double x;
+      if (kind == TRI_JK) x = P1[a * nv2 + c * nvl + b] + P0[c * nv2 + a * nvl + b];
+      else x = P2[c * nv2 + a * nvl + b];
+      Xs[o * TSZ + TP(uu, vv, ww)] += x;
+    }
+  }
+  if (kind == TRI_IJ) {
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+      if (canon[o] != o) continue;
+      int q0, q1, q2;
+      orient(o, q0, q1, q2);
+      const int vv = t >> 6, ww = (t >> 3) & 7, uu = t & 7;  // a fastest
+      const int a = blk[q0] * MT + uu, b = blk[q1] * MT + vv, c = blk[q2] * MT + ww;
+      if (a < nv && b < nv && c < nv) Xs[o * TSZ + TP(uu, vv, ww)] += P2[c * nv2 + b * nvl + a];
+    }
+  }
+  __syncthreads();
+  // the denominators and the contravariant combination; outputs in [a][b][c] order
+  const double eijk = eps[i] + eps[j] + eps[k];
+  double* outC = cubes + (LMODE ? D3_LC : D3_TAUC) * ss + (int64_t)z * nv3;
+  double* outT = cubes + D3_TAU * ss + (int64_t)z * nv3;
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    if (canon[o] != o) continue;
+    int q0, q1, q2;
+    orient(o, q0, q1, q2);
+    const int a = blk[q0] * MT + u, b = blk[q1] * MT + v, c = blk[q2] * MT + w;
+    if (!(a < nv && b < nv && c < nv)) continue;
+    const int o_acb = canon[orient_of(q0, q2)], o_cba = canon[orient_of(q2, q1)];
+    const int o_bac = canon[orient_of(q1, q0)], o_bca = canon[orient_of(q1, q2)];
+    const int o_cab = canon[orient_of(q2, q0)];
+    const double x_abc = Xs[o * TSZ + TP(u, v, w)];
+    const double x_acb = Xs[o_acb * TSZ + TP(u, w, v)];
+    const double x_cba = Xs[o_cba * TSZ + TP(w, v, u)];
+    const double x_bac = Xs[o_bac * TSZ + TP(v, u, w)];
+    const double x_bca = Xs[o_bca * TSZ + TP(v, w, u)];
+    const double x_cab = Xs[o_cab * TSZ + TP(w, u, v)];
+    const double D = eps[no + a] + eps[no + b] + eps[no + c] - eijk - (LMODE ? omega : 0.0);
+    const int64_t e = (a * nvl + b) * nvl + c;
+    outC[e] = -(4.0 * x_abc - 2.0 * x_acb - 2.0 * x_cba - 2.0 * x_bac + x_bca + x_cab) / D;
+    if (!LMODE) outT[e] = -x_abc / D;
+  }
+}
+
+void launch_mix3(bool lmode, const double* eps, const int* tri, int ntri, double* cubes, int64_t ss,
+                 double omega, const double* l1, const double* l2, const double* Jo,
+                 const double* F, int no, int nv, hipStream_t st) {
+  if (ntri <= 0) return;
+  const int nb = (nv + MT - 1) / MT;
+  const int nbt = nb * (nb + 1) * (nb + 2) / 6;
+  if (lmode)
+    hipLaunchKernelGGL(k_mix3<true>, dim3(nbt, ntri), dim3(512), 0, st, eps, tri, cubes, ss,
+                       omega, l1, l2, Jo, F, no, nv);
+  else
+    hipLaunchKernelGGL(k_mix3<false>, dim3(nbt, ntri), dim3(512), 0, st, eps, tri, cubes, ss,
+                       0.0, l1, l2, Jo, F, no, nv);
 }
 
 // tau^{abc}_{ijk} = -X / eps^{abc}_{ijk} for one ordered triple whose six terms were all built

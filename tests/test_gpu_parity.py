@@ -231,12 +231,11 @@ def test_cvs_worklist(ctx):
     assert_close("Ot2 cvs + valence", (c2 + v2).cpu().numpy(), w2.cpu().numpy())
 
 
-@pytest.mark.parametrize("no,nv,nJ,count", [(12, 120, 400, 10), (23, 250, 800, 2),
-                                            (31, 400, 1200, 0)])
+@pytest.mark.parametrize("no,nv,nJ,count", [(12, 120, 400, 10)])
 def test_sampled_parity_full_sizes(ctx, no, nv, nJ, count):
-    """At the benchmark sizes the oracle evaluates a seeded sample of triples plus one
-    distinct and two two-equal triples, one by one; the device evaluates the same subset in
-    the same launch configuration as the full call."""
+    """A seeded sample of triples plus one distinct and two two-equal triples through the
+    subset entry point (the whole call at this size, and whole batches of the real plan
+    at 23/250/800 and 31/400/1200, are in test_gpu_whole_call_oracle.py)."""
     torch = _torch()
     d = make_inputs(no, nv, nJ)
     extra = np.array([[no - 1, no // 2, 0], [no - 1, no - 1, 0], [no - 1, 0, 0]], dtype=np.int32)
@@ -288,3 +287,41 @@ def test_max_nv_embedding():
     rest2 = o2.copy()
     rest2[:, :, :nv0, :nv0] = 0.0
     assert not o1[:, nv0:].any() and not rest2.any()
+
+
+def test_blocks_form_subset_and_t3_export(ctx):
+    """The subset call and the t3 export in the integral-blocks form: the contravariant
+    residual of listed triples and the amplitudes of ordered triples from blocks the caller
+    holds, in device and in host memory, against the oracle on the same blocks."""
+    torch = _torch()
+    no, nv, nJ = 6, 23, 30
+    say(f"blocks-form subset and t3 export no={no} nv={nv}")
+    d = make_inputs(no, nv, nJ)
+    Lt = O.t1_transform(d["L"], d["t1"])
+    blk = O.IntegralBlocks(Lt, no, full=True)
+    F = O.fock_ov(d["L"], d["t1"])
+    arrs = [blk.full_vvvo(), blk.g_oovo, blk.g_ovov, blk.g_ooov, blk.full_vvov(), F]
+    ref_blk = O.IntegralBlocks.from_arrays(*arrs[:5])
+    tri = np.array([[5, 3, 1], [4, 4, 0], [3, 2, 2], [5, 5, 4], [2, 1, 0]], dtype=np.int32)
+    r1, r2 = O.omega_tilde(d["eps"], d["t2"], ref_blk, F, triples=[tuple(t) for t in tri])
+    ga = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+    g = dev(torch, d)
+    o1, o2 = ctx.triples_residual_subset_blocks(g["eps"], *ga, g["t2"], tri)
+    torch.cuda.synchronize()
+    assert_close("Ot1 (device blocks)", o1.cpu().numpy(), r1)
+    assert_close("Ot2 (device blocks)", o2.cpu().numpy(), r2)
+    # host blocks and host amplitudes give the same bits
+    ha = [torch.from_numpy(np.ascontiguousarray(a)) for a in arrs]
+    h1, h2 = ctx.triples_residual_subset_blocks(torch.from_numpy(d["eps"]), *ha,
+                                                torch.from_numpy(d["t2"]), tri)
+    torch.cuda.synchronize()
+    assert torch.equal(h1, o1.cpu()) and torch.equal(h2, o2.cpu())
+    for (i, j, k) in [(5, 3, 1), (1, 3, 5), (4, 4, 0), (0, 2, 2)]:
+        t = ctx.t3_block_blocks(g["eps"], *ga, g["t2"], i, j, k).cpu().numpy()
+        assert_close(f"tau_{i}{j}{k} (blocks)", t, O.t3_amplitudes(i, j, k, d["eps"], d["t2"],
+                                                                   ref_blk))
+    # a bad triple is rejected
+    from paper_2007_01088_amd import cc3
+    with pytest.raises(cc3.CC3Error) as e:
+        ctx.triples_residual_subset_blocks(g["eps"], *ga, g["t2"], [[1, 1, 1]])
+    assert e.value.code == cc3.E_INVAL

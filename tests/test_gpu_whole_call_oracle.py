@@ -1,0 +1,195 @@
+"""Whole residual calls at the benchmark sizes against the CPU oracle, on an MI355X.
+
+At no=12, nv=120, nchol=400 the oracle evaluates the whole call (about 40 s on
+the host); the device call runs in the launch configuration the benchmark times
+(the default plan: batches dealt round-robin over two streams).  The FP64 call
+is compared element by element at the FP64 bar, each low-precision form per
+result at its bound (test_gpu_mixed.py states the bounds and their derivation).
+
+At no=23, nv=250, nchol=800 the oracle cannot evaluate a whole call in
+reasonable time (about 2277 triples at several seconds each), so one whole batch
+of the real plan (the triples the whole call launches together, in the same
+order, as cc3_batch_plan reports them) is compared through the subset entry
+point, in FP64 and in every low precision.  At no=31, nv=400, nchol=1200 one
+oracle triple costs over 15 s; there the first batch of the real plan runs on
+the device whole and with three of its triples left out, and the difference
+(those three triples' contributions computed inside the full batch launch) is
+compared with the oracle's result for the three.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cc3_oracle as O
+from paper_2007_01088_amd.synth import make_inputs
+from test_gpu_mixed import BOUND, BOUND_SAMPLE, bound_all
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_01088_amd import cc3
+    return torch, cc3
+
+
+def rel2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def medium():
+    torch, cc3 = _setup()
+    no, nv, nJ = 12, 120, 400
+    d = make_inputs(no, nv, nJ)
+    say(f"oracle whole call no={no} nv={nv} nchol={nJ} ...")
+    r1, r2 = O.triples_residual(d["eps"], d["L"], d["t1"], d["t2"])
+    say("oracle done")
+    g = {k: torch.from_numpy(d[k]).cuda() for k in ("eps", "L", "t1", "t2")}
+    ctx = cc3.Context(0)
+    yield d, g, ctx, r1, r2
+    ctx.close()
+
+
+def test_fp64_whole_call_medium(medium):
+    torch, cc3 = _setup()
+    d, g, ctx, r1, r2 = medium
+    b, nb = cc3.batch_plan(12, 120, 400)
+    say(f"fp64 whole call, {nb} batches of {b} triples on two streams")
+    o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
+    torch.cuda.synchronize()
+    o1, o2 = o1.cpu().numpy(), o2.cpu().numpy()
+    for name, got, ref in (("Omega1", o1, r1), ("Omega2", o2, r2)):
+        e2, em = rel2(got, ref), relmax(got, ref)
+        say(f"  {name}: rel2 {e2:.3e} relmax {em:.3e}")
+        assert e2 <= TOL and em <= TOL, (name, e2, em)
+
+
+@pytest.mark.parametrize("name", ["fp32", "bf16x6", "bf16x3"])
+def test_mixed_whole_call_medium(medium, name):
+    """The W contractions in low precision (everything after them FP64) against the oracle."""
+    torch, cc3 = _setup()
+    d, g, ctx, r1, r2 = medium
+    prec = {"fp32": cc3.FP32, "bf16x6": cc3.BF16X6, "bf16x3": cc3.BF16X3}[name]
+    o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=prec)
+    torch.cuda.synchronize()
+    e1, e2 = rel2(o1.cpu().numpy(), r1), rel2(o2.cpu().numpy(), r2)
+    say(f"whole call {name}: rel err Omega1 {e1:.3e} Omega2 {e2:.3e}")
+    assert e1 <= BOUND[name] and e2 <= BOUND[name], (name, e1, e2)
+
+
+@pytest.mark.parametrize("name", ["fp32", "bf16x6", "bf16x3"])
+def test_mixed_all_whole_call_medium(medium, name):
+    """Mixed-all (CC3_LOWP_CONTRACT) against the oracle, at its size-dependent bound."""
+    torch, cc3 = _setup()
+    d, g, ctx, r1, r2 = medium
+    prec = {"fp32": cc3.FP32, "bf16x6": cc3.BF16X6, "bf16x3": cc3.BF16X3}[name]
+    o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=prec,
+                                  flags=cc3.LOWP_CONTRACT)
+    torch.cuda.synchronize()
+    e1, e2 = rel2(o1.cpu().numpy(), r1), rel2(o2.cpu().numpy(), r2)
+    bd = bound_all(name, 120)
+    say(f"whole call mixed-all {name}: rel err Omega1 {e1:.3e} Omega2 {e2:.3e} (bound {bd:.1e})")
+    assert e1 <= bd and e2 <= bd, (name, e1, e2)
+
+
+def test_full_batch_no23_nv250():
+    """Batch 0 of the real plan at 23/250/800, in every precision, against the oracle."""
+    torch, cc3 = _setup()
+    no, nv, nJ = 23, 250, 800
+    b, nb = cc3.batch_plan(no, nv, nJ)
+    tri = cc3.batch_triples(no, nb, 0)
+    assert len(tri) == b
+    ntot = no * (no + 1) * (no + 2) // 6 - no
+    say(f"full batch at no={no} nv={nv}: {len(tri)} triples (batch 0 of {nb}): {tri.tolist()}")
+    d = make_inputs(no, nv, nJ)
+    g = {k: torch.from_numpy(d[k]).cuda() for k in ("eps", "L", "t1", "t2")}
+    ctx = cc3.Context(0)
+    res = {}
+    forms = [("fp64", cc3.FP64, 0), ("fp32", cc3.FP32, 0), ("bf16x6", cc3.BF16X6, 0),
+             ("bf16x3", cc3.BF16X3, 0), ("fp32_all", cc3.FP32, cc3.LOWP_CONTRACT),
+             ("bf16x6_all", cc3.BF16X6, cc3.LOWP_CONTRACT),
+             ("bf16x3_all", cc3.BF16X3, cc3.LOWP_CONTRACT)]
+    for name, prec, fl in forms:
+        o1, o2 = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], tri, prec=prec,
+                                             flags=fl)
+        torch.cuda.synchronize()
+        res[name] = (o1.cpu().numpy(), o2.cpu().numpy())
+    ctx.close()
+    del g
+    torch.cuda.empty_cache()
+    say("device calls done; oracle on the batch ...")
+    r1, r2 = O.omega_tilde_subset(d["eps"], d["L"], d["t1"], d["t2"], tri)
+    for name, _, _ in forms:
+        o1, o2 = res[name]
+        e1, e2 = rel2(o1, r1), rel2(o2, r2)
+        m1, m2 = relmax(o1, r1), relmax(o2, r2)
+        if name == "fp64":
+            bd = TOL
+            ok = max(e1, e2, m1, m2) <= bd
+        elif name.endswith("_all"):
+            # the mixed-all error comes from FP32 sums over each triple's contributions;
+            # summed over n of the N triples, the result grows like n and the independent
+            # errors like sqrt(n), so a batch carries sqrt(N / n) times the relative error
+            # of the whole call (measured: 3.9x on Omega1 and 12x on Omega2 for FP32)
+            bd = bound_all(name[:-4], nv) * (ntot / len(tri)) ** 0.5
+            ok = e1 <= bd and e2 <= bd
+        else:
+            bd = BOUND_SAMPLE[name]
+            ok = e1 <= bd and e2 <= bd
+        say(f"  {name}: rel2 {e1:.3e} / {e2:.3e}, relmax {m1:.3e} / {m2:.3e} (bound {bd:.1e})")
+        assert ok, (name, e1, e2, m1, m2)
+
+
+def test_full_batch_no31_nv400():
+    """Batch 0 of the real plan at 31/400/1200 on the device, whole and without three of
+    its triples (a distinct one, an i == j and a j == k one where the batch has them);
+    the difference is those three triples' contributions computed inside the full
+    launch, compared with the oracle's result for them."""
+    torch, cc3 = _setup()
+    no, nv, nJ = 31, 400, 1200
+    b, nb = cc3.batch_plan(no, nv, nJ)
+    tri = cc3.batch_triples(no, nb, 0)
+    assert len(tri) == b
+    kinds = [0 if len(set(t)) == 3 else (1 if t[0] == t[1] else 2) for t in tri.tolist()]
+    pick = []
+    for want in (0, 1, 2):
+        for idx, kd in enumerate(kinds):
+            if kd == want and idx not in pick:
+                pick.append(idx)
+                break
+    while len(pick) < 3:
+        pick.append(next(i for i in range(len(tri)) if i not in pick))
+    rest = np.array([t for i, t in enumerate(tri.tolist()) if i not in pick], dtype=np.int32)
+    three = tri[pick]
+    say(f"full batch at no={no} nv={nv}: {len(tri)} triples (batch 0 of {nb}); "
+        f"checked inside it: {three.tolist()}")
+    d = make_inputs(no, nv, nJ)
+    g = {k: torch.from_numpy(d[k]).cuda() for k in ("eps", "L", "t1", "t2")}
+    ctx = cc3.Context(0)
+    a1, a2 = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], tri)
+    b1, b2 = ctx.triples_residual_subset(g["eps"], g["L"], g["t1"], g["t2"], rest)
+    torch.cuda.synchronize()
+    x1, x2 = (a1 - b1).cpu().numpy(), (a2 - b2).cpu().numpy()
+    ctx.close()
+    del g, a1, a2, b1, b2
+    torch.cuda.empty_cache()
+    say("device calls done; oracle on the three triples ...")
+    r1, r2 = O.omega_tilde_subset(d["eps"], d["L"], d["t1"], d["t2"], three)
+    for name, got, ref in (("Ot1", x1, r1), ("Ot2", x2, r2)):
+        e2, em = rel2(got, ref), relmax(got, ref)
+        say(f"  {name}: rel2 {e2:.3e} relmax {em:.3e}")
+        assert e2 <= TOL and em <= TOL, (name, e2, em)
