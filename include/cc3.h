@@ -190,6 +190,29 @@ int cc3_triples_residual_subset_blocks(cc3_ctx* ctx, int no, int nv, const doubl
                                        void* workspace, size_t workspace_bytes,
                                        cc3_stream_t stream);
 
+/* cc3_triples_residual without a workspace argument and without any device
+ * allocation, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * workspace is a static device array of the library (256 MiB per GPU, reserved
+ * when the library's code is loaded on that GPU and held until the process ends);
+ * the call runs every batch on `stream` and records no events.  Arguments, results
+ * and arithmetic are those of cc3_triples_residual, except: all six arrays must be
+ * device memory of the context's GPU; flags may be CC3_ACCUMULATE,
+ * CC3_LOWP_CONTRACT, CC3_DETERMINISTIC (CC3_ONE_STREAM is implied); the plan takes
+ * fewer triples per batch where needed to fit the array (the result is the same to
+ * rounding, 1e-11 relative in FP64).  Every call on one GPU uses that GPU's one
+ * array: calls whose device work overlaps (different streams, different contexts
+ * on the same GPU) race and corrupt each other's results; calls ordered on one
+ * stream are safe.  The array keeps the last call's contents; the call clears what
+ * must start at zero itself.
+ * Errors: CC3_E_INVAL (sizes, flags, host pointers), CC3_E_NOMEM (the workspace at
+ * one triple per batch exceeds 256 MiB: roughly nv above 70 at no = 10),
+ * CC3_E_DEVICE. */
+int cc3_triples_residual_noalloc(cc3_ctx* ctx, int no, int nv, int nchol, const double* eps,
+                                 const double* L, const double* t1, const double* t2,
+                                 double* omega1, double* omega2, int prec, unsigned flags,
+                                 cc3_stream_t stream);
+
 /* Debug export of the t3 amplitudes of one ordered triple (i, j, k) (any order,
  * not all equal): tau[a][b][c] = tau^{abc}_{ijk} = -(eps^{abc}_{ijk})^{-1} P^{abc}_{ijk} B^{abc}_{ijk}
  * (Algorithm 1, first statement), written to tau[nv][nv][nv] (device or host); the

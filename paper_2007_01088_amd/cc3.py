@@ -64,6 +64,9 @@ _t3_block = _sig("cc3_t3_block", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _d
                                   _c_int, _dp, _c_int, _vp, _c_size, _vp])
 _jprep = _sig("cc3_jacobian_prep", [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp, _dp,
                                      _c_int, ctypes.c_uint, _vp, _c_size, _vp])
+_residual_noalloc = _sig("cc3_triples_residual_noalloc",
+                         [_vp, _c_int, _c_int, _c_int, _dp, _dp, _dp, _dp, _dp, _dp, _c_int,
+                          ctypes.c_uint, _vp])
 _td_ws = _sig("cc3_transition_density_workspace_size",
                [_c_int, _c_int, _c_int, ctypes.POINTER(_c_size)])
 _td = _sig("cc3_transition_density",
@@ -118,7 +121,7 @@ _srv_stats = _sig("cc3_server_get_stats", [_vp, ctypes.POINTER(ServerStats)])
 EXPORTED = ["cc3_create", "cc3_destroy", "cc3_last_error", "cc3_workspace_size",
             "cc3_triples_residual", "cc3_triples_residual_blocks", "cc3_triples_residual_subset",
             "cc3_t3_block", "cc3_triples_residual_subset_blocks", "cc3_t3_block_blocks",
-            "cc3_flops", "cc3_batch_plan",
+            "cc3_flops", "cc3_batch_plan", "cc3_triples_residual_noalloc",
             "cc3_transition_density_workspace_size", "cc3_transition_density", "cc3_cvs_triples", "cc3_profile_enable", "cc3_profile_get",
             "cc3_jacobian_prep", "cc3_server_create", "cc3_server_destroy", "cc3_server_footprint",
             "cc3_molecule_register", "cc3_molecule_release", "cc3_submit", "cc3_poll",
@@ -242,6 +245,17 @@ class Context:
                          _any_ptr(omega2, "omega2"), prec, flags, ws.data_ptr(), ws.numel(),
                          _stream(stream)),
                "cc3_triples_residual")
+        return omega1, omega2
+
+    def triples_residual_noalloc(self, eps, L, t1, t2, omega1, omega2, prec=FP64, flags=0,
+                                 stream=None):
+        """cc3_triples_residual_noalloc: no workspace argument, no device allocation (the
+        library's static scratch array); device tensors only, outputs given by the caller."""
+        no, nv = t1.shape
+        _check(_residual_noalloc(self._h, no, nv, L.shape[0], _ptr(eps, "eps"), _ptr(L, "L"),
+                                 _ptr(t1, "t1"), _ptr(t2, "t2"), _ptr(omega1, "omega1"),
+                                 _ptr(omega2, "omega2"), prec, flags, _stream(stream)),
+               "cc3_triples_residual_noalloc")
         return omega1, omega2
 
     def triples_residual_blocks(self, eps, g_vvvo, g_oovo, g_ovov, g_ooov, g_vvov, F_ov, t2,

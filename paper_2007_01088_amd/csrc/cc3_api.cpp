@@ -16,12 +16,54 @@ using namespace cc3;
 
 extern "C" const char* cc3_last_error(void) { return last_error_str(); }
 
+// ---------------------------------------------------------------------------
+// The workspace of the allocation-free residual (cc3_triples_residual_noalloc):
+// a static device array of this library, one copy per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address, per device, comes from hipGetSymbolAddress at
+// context creation and is the only form in which host code uses it.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = (size_t)256 << 20;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[SCRATCH_MAX_DEVICES];
+
+// With `device` current: look up this device's copy of the array once.
+static int scratch_setup(int device) {
+  if (device >= SCRATCH_MAX_DEVICES)
+    return fail(CC3_E_INVAL, "device %d beyond the %d devices the scratch table holds", device,
+                SCRATCH_MAX_DEVICES);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return CC3_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(CC3_E_DEVICE, "hipGetSymbolAddress of the scratch array failed on device %d: %s",
+                device, hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return CC3_OK;
+}
+
+static void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return device >= 0 && device < SCRATCH_MAX_DEVICES ? g_scratch_ptr[device] : nullptr;
+}
+
 extern "C" int cc3_create(cc3_ctx** out, int device) {
   if (!out) return fail(CC3_E_INVAL, "cc3_create: out is NULL");
   int n = 0;
   HIPCHK(hipGetDeviceCount(&n));
   if (device < 0 || device >= n)
     return fail(CC3_E_INVAL, "cc3_create: device %d out of range (%d devices)", device, n);
+  {
+    int prev = 0;
+    HIPCHK(hipGetDevice(&prev));
+    HIPCHK(hipSetDevice(device));
+    const int rc = scratch_setup(device);
+    (void)hipSetDevice(prev);
+    if (rc) return rc;
+  }
   cc3_ctx* c = new cc3_ctx();
   c->device = device;
   *out = c;
@@ -506,3 +548,43 @@ extern "C" int cc3_jacobian_prep(cc3_ctx* c, int no, int nv, int nchol, const do
                                    (flags & CC3_ACCUMULATE) != 0, st);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free residual
+// ---------------------------------------------------------------------------
+extern "C" int cc3_triples_residual_noalloc(cc3_ctx* c, int no, int nv, int nchol,
+                                            const double* eps, const double* L, const double* t1,
+                                            const double* t2, double* omega1, double* omega2,
+                                            int prec, unsigned flags, cc3_stream_t stream) {
+  if (!c) return fail(CC3_E_INVAL, "ctx is NULL");
+  int rc = check_sizes(no, nv, nchol, prec);
+  if (rc) return rc;
+  if (nchol < 1) return fail(CC3_E_INVAL, "nchol must be >= 1 for the Cholesky form");
+  if (flags & ~(unsigned)(CC3_ACCUMULATE | CC3_ONE_STREAM | CC3_LOWP_CONTRACT | CC3_DETERMINISTIC))
+    return fail(CC3_E_INVAL, "flags 0x%x: the allocation-free call accepts CC3_ACCUMULATE, "
+                "CC3_ONE_STREAM, CC3_LOWP_CONTRACT and CC3_DETERMINISTIC", flags);
+  if ((flags & CC3_LOWP_CONTRACT) && prec == CC3_FP64)
+    return fail(CC3_E_INVAL, "CC3_LOWP_CONTRACT needs a low precision (FP32, BF16X3, BF16X6)");
+  HIPCHK(hipSetDevice(c->device));
+  const void* ptrs[] = {eps, L, t1, t2, omega1, omega2};
+  const char* names[] = {"eps", "L", "t1", "t2", "omega1", "omega2"};
+  for (int i = 0; i < 6; ++i)
+    if ((rc = check_dev_ptr(ptrs[i], names[i]))) return rc;
+  void* ws = scratch_ptr(c->device);
+  if (!ws) return fail(CC3_E_DEVICE, "the scratch array of device %d was not set up", c->device);
+  // the plan of the one-shot call, with fewer triples per batch until it fits the array
+  Plan p;
+  make_plan_ex(no, nv, nchol, prec, flags, true, 0, &p);
+  const size_t per_triple = 5 * p.cube * sizeof(double);
+  for (int b = p.batch - 1; p.total > SCRATCH_BYTES && b >= 1; --b)
+    make_plan_ex(no, nv, nchol, prec, flags, true, (size_t)b * per_triple, &p);
+  if (p.total > SCRATCH_BYTES)
+    return fail(CC3_E_NOMEM, "no=%d nv=%d nchol=%d needs %zu bytes of workspace at one triple per "
+                "batch; the allocation-free call has %zu", no, nv, nchol, p.total, SCRATCH_BYTES);
+  p.flags |= PLAN_CALLER_STREAM;
+  hipStream_t st = (hipStream_t)stream;
+  Ws w = carve(p, ws, nullptr);
+  std::lock_guard<std::mutex> g(c->mu);
+  if ((rc = prepare_cholesky(nullptr, p, w, L, t1, st))) return rc;
+  return residual_from_blocks(c->run, nullptr, p, w, eps, t2, omega1, omega2,
+                              (flags & CC3_ACCUMULATE) != 0, st);
+}

@@ -395,6 +395,7 @@ static int triple_loop_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w
 
 int triple_loop(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, const double* eps,
                 const double* t2, const int* tri, const int* ht, int n, hipStream_t st) {
+  if (p.flags & PLAN_CALLER_STREAM) return triple_loop_body(rn, pf, p, w, eps, t2, tri, ht, n, st);
   int rc = rn.init();
   if (rc) return rc;
   rc = triple_loop_body(rn, pf, p, w, eps, t2, tri, ht, n, st);
@@ -419,17 +420,21 @@ static int triple_loop_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w
     for (int k = 0; k < 2; ++k)
       launch_lp_zero_pad(w.cubesX[k], (int64_t)p.batch * 4 * lpP * p.nv, p.nv, st);
   }
-  HIPCHK(hipEventRecord(rn.ev_fork, st));
-  for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
+  // PLAN_CALLER_STREAM: every batch on the caller's stream, no runner streams or events
+  const bool own = (p.flags & PLAN_CALLER_STREAM) != 0;
+  if (!own) {
+    HIPCHK(hipEventRecord(rn.ev_fork, st));
+    for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
+  }
   // CC3_ONE_STREAM (or CC3_SERIAL=1 in the environment) keeps every batch on one stream
   static const int env_serial = env_int("CC3_SERIAL", 0);
-  const int nstream = (env_serial || (p.flags & CC3_ONE_STREAM)) ? 1 : NSTREAM;
+  const int nstream = (own || env_serial || (p.flags & CC3_ONE_STREAM)) ? 1 : NSTREAM;
   const int ngroups = (n + p.batch - 1) / p.batch;
   for (int nbatch = 0; nbatch < ngroups; ++nbatch) {
     int t0, nb;
     batch_range(n, ngroups, nbatch, &t0, &nb);
     const int k = nbatch % nstream;
-    hipStream_t sk = rn.s[k];
+    hipStream_t sk = own ? st : rn.s[k];
     kinds.resize(nb);
     for (int t = 0; t < nb; ++t)
       kinds[t] = kind_of(ht[3 * (t0 + t)], ht[3 * (t0 + t) + 1], ht[3 * (t0 + t) + 2]);
@@ -456,7 +461,7 @@ static int triple_loop_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w
       else
         launch_omega(w.cubes[k], w.b, tb, nb, w.Pvv[k], p.no, p.nv, sk);
     }
-    if (nbatch > 0) HIPCHK(hipStreamWaitEvent(sk, rn.ev_red[(nbatch - 1) % nstream], 0));
+    if (nbatch > 0 && !own) HIPCHK(hipStreamWaitEvent(sk, rn.ev_red[(nbatch - 1) % nstream], 0));
     {
       Timer tm(pf, sk, FAM_OMEGA_OO, omega_oo_flops(p.no, p.nv, kinds.data(), nb), 0.0);
       launch_omega_oo(w.cubes[k], w.b, tb, nb, w.OtT, p.no, p.nv, sk);
@@ -465,11 +470,13 @@ static int triple_loop_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w
       Timer tm(pf, sk, FAM_REDUCE, 0.0, 0.0);
       launch_reduce(tb, nb, w.Pvv[k], w.Ot1, w.Ot2, p.no, p.nv, sk);
     }
-    HIPCHK(hipEventRecord(rn.ev_red[k], sk));
+    if (!own) HIPCHK(hipEventRecord(rn.ev_red[k], sk));
   }
-  for (int k = 0; k < NSTREAM; ++k) {
-    HIPCHK(hipEventRecord(rn.ev_done[k], rn.s[k]));
-    HIPCHK(hipStreamWaitEvent(st, rn.ev_done[k], 0));
+  if (!own) {
+    for (int k = 0; k < NSTREAM; ++k) {
+      HIPCHK(hipEventRecord(rn.ev_done[k], rn.s[k]));
+      HIPCHK(hipStreamWaitEvent(st, rn.ev_done[k], 0));
+    }
   }
   HIPCHK(hipGetLastError());
   return CC3_OK;

@@ -12,6 +12,10 @@ namespace cc3 {
 // the per-p pair lists of the kernels hold 2 * MAX_BATCH entries.
 constexpr int MAX_BATCH = 160;
 
+// Internal plan flag (beside the public CC3_* flags): the triple loop runs every
+// batch on the caller's stream and records no events (the allocation-free entry point).
+constexpr unsigned PLAN_CALLER_STREAM = 1u << 30;
+
 // triple kinds
 enum { TRI_DISTINCT = 0, TRI_IJ = 1, TRI_JK = 2 };
 
