@@ -377,6 +377,8 @@ typedef struct cc3_server_stats {
   int64_t submitted, completed, failed, cancelled;
   int queued, inflight, max_inflight_seen, molecules;
   size_t arena_bytes, arena_used, arena_peak;
+  int64_t packed; /* requests that ran in packed groups */
+  int64_t packs;  /* packed groups launched */
 } cc3_server_stats;
 
 /* Create a server on `device` over the arena [arena, arena + arena_bytes)
@@ -437,6 +439,18 @@ int cc3_wait(cc3_server* srv, uint64_t ticket, double* omega1, double* omega2,
 /* Cancel a request that has not been admitted yet (cc3_wait then returns
  * CC3_E_CANCELLED).  Errors: CC3_E_NOTFOUND; CC3_E_BUSY if it already runs. */
 int cc3_cancel(cc3_server* srv, uint64_t ticket);
+
+/* Packing of small requests into shared launches.  When a slot admits a request
+ * of at most max_request_flops nominal FLOP (4 nv^4 no^3), the requests queued
+ * right behind it that are as small and have the same precision (up to max_pack
+ * in all) join it: the group runs on the slot's stream, batch s of every request
+ * in the same launches (one persistent kernel per step of the triple loop, whose
+ * workgroups loop over the union of the requests' work items), and completes
+ * together.  Each request keeps its own plan, batches and reduction order, so its
+ * result is bit for bit the result it has alone.  Defaults: max_pack 8,
+ * max_request_flops 2e12; max_pack 1 turns packing off.
+ * Errors: CC3_E_INVAL (max_pack outside [1, 64], max_request_flops < 0). */
+int cc3_server_set_packing(cc3_server* srv, int max_pack, double max_request_flops);
 
 /* Counters of the server since creation.  Errors: CC3_E_INVAL. */
 int cc3_server_get_stats(cc3_server* srv, cc3_server_stats* out);

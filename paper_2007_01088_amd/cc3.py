@@ -98,7 +98,7 @@ class ServerStats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
                 ("queued", _c_int), ("inflight", _c_int), ("max_inflight_seen", _c_int),
                 ("molecules", _c_int), ("arena_bytes", _c_size), ("arena_used", _c_size),
-                ("arena_peak", _c_size)]
+                ("arena_peak", _c_size), ("packed", ctypes.c_int64), ("packs", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -117,6 +117,7 @@ _poll = _sig("cc3_poll", [_vp, _u64, ctypes.POINTER(_c_int)])
 _wait = _sig("cc3_wait", [_vp, _u64, _dp, _dp, ctypes.POINTER(Timing)])
 _cancel = _sig("cc3_cancel", [_vp, _u64])
 _srv_stats = _sig("cc3_server_get_stats", [_vp, ctypes.POINTER(ServerStats)])
+_srv_packing = _sig("cc3_server_set_packing", [_vp, _c_int, ctypes.c_double])
 
 EXPORTED = ["cc3_create", "cc3_destroy", "cc3_last_error", "cc3_workspace_size",
             "cc3_triples_residual", "cc3_triples_residual_blocks", "cc3_triples_residual_subset",
@@ -125,7 +126,7 @@ EXPORTED = ["cc3_create", "cc3_destroy", "cc3_last_error", "cc3_workspace_size",
             "cc3_transition_density_workspace_size", "cc3_transition_density", "cc3_cvs_triples", "cc3_profile_enable", "cc3_profile_get",
             "cc3_jacobian_prep", "cc3_server_create", "cc3_server_destroy", "cc3_server_footprint",
             "cc3_molecule_register", "cc3_molecule_release", "cc3_submit", "cc3_poll",
-            "cc3_wait", "cc3_cancel", "cc3_server_get_stats"]
+            "cc3_wait", "cc3_cancel", "cc3_server_get_stats", "cc3_server_set_packing"]
 
 
 class CC3Error(RuntimeError):
@@ -489,6 +490,11 @@ class Server:
 
     def cancel(self, ticket: int) -> None:
         _check(_cancel(self._h, ticket), "cc3_cancel")
+
+    def set_packing(self, max_pack: int = 8, max_request_flops: float = 2e12) -> None:
+        """Group small requests into shared launches (max_pack 1: off)."""
+        _check(_srv_packing(self._h, max_pack, float(max_request_flops)),
+               "cc3_server_set_packing")
 
     def stats(self) -> dict:
         st = ServerStats()

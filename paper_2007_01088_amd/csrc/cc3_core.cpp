@@ -207,11 +207,11 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   // triples per batch: enough W-build workgroups per launch to fill 256 CUs
   // many times over, and at least min(no, 16) triples, so that the kernels that
   // are parallel over the first occupied index p (the oo contraction, the
-  // reductions) find pairs for most p in every batch; bounded by a cube-memory
+  // reductions) find pairs for many p in every batch; bounded by a cube-memory
   // budget per buffer set (32 GiB by default: 12 triples at nv = 400)
   const size_t wg_per_triple = 3 * v * ((v + 127) / 128) * ((v + 127) / 128);
   int batch = (int)std::max<size_t>(1, (size_t)(12288 + wg_per_triple - 1) / wg_per_triple);
-  batch = std::max(batch, std::min(no, 16));
+  batch = std::max(batch, std::min(no, 8));
   const size_t budget =
       cube_budget ? cube_budget : ((size_t)env_int("CC3_CUBE_BUDGET_MB", 32768) << 20);
   const size_t per_triple = 5 * p->cube * sizeof(double);
@@ -426,9 +426,13 @@ static int triple_loop_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w
     HIPCHK(hipEventRecord(rn.ev_fork, st));
     for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
   }
-  // CC3_ONE_STREAM (or CC3_SERIAL=1 in the environment) keeps every batch on one stream
+  // CC3_ONE_STREAM (or CC3_SERIAL=1 in the environment) keeps every batch on one stream;
+  // so does a wide virtual space, where one batch's W build and Omega GEMM fill the
+  // device for milliseconds each and the overlap measured slower (23/250/800: 4.94
+  // against 5.06 s per call)
   static const int env_serial = env_int("CC3_SERIAL", 0);
-  const int nstream = (own || env_serial || (p.flags & CC3_ONE_STREAM)) ? 1 : NSTREAM;
+  const int nstream =
+      (own || env_serial || (p.flags & CC3_ONE_STREAM) || p.nv > 192) ? 1 : NSTREAM;
   const int ngroups = (n + p.batch - 1) / p.batch;
   for (int nbatch = 0; nbatch < ngroups; ++nbatch) {
     int t0, nb;
@@ -504,6 +508,67 @@ int residual_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws& w, c
   HIPCHK(hipGetLastError());
   return CC3_OK;
 }
+
+// Several requests in lockstep through packed launches: the per-request
+// preparation, then step s runs batch s of every request that has one in the
+// five packed launches of the triple loop, then the per-request back
+// transformation.  Each request keeps its own plan, batches and reduction order,
+// so its result is that of its own call.  host_jobs receives the job tables
+// (they must outlive the copy into dev_jobs, which holds room for
+// max_batches * ms.size() jobs).
+int packed_residuals(const std::vector<PackMember>& ms, int prec, PackJob* dev_jobs,
+                     std::vector<PackJob>& host_jobs, hipStream_t st) {
+  const int nm = (int)ms.size();
+  int nsteps = 0;
+  for (const PackMember& m : ms) {
+    const Plan& p = *m.p;
+    const int no = p.no, nv = p.nv;
+    int rc;
+    if (m.rebuild && (rc = prepare_cholesky(nullptr, p, m.w, m.L, m.t1, st))) return rc;
+    launch_fill(m.w.Ot1, (int64_t)no * nv, 0.0, st);
+    launch_fill(m.w.Ot2, (int64_t)no * no * nv * nv, 0.0, st);
+    launch_fill(m.w.OtT, (int64_t)no * no * nv * nv, 0.0, st);
+    launch_triple_table(m.w.tri, no, nbatches(p), st);
+    launch_t2N(m.t2, m.w.t2N, no, nv, st);
+    if (prec != CC3_FP64) launch_lp_convert(m.t2, m.w.b, no, nv, m.w.lp, st);
+    nsteps = std::max(nsteps, nbatches(p));
+  }
+  host_jobs.assign((size_t)nsteps * nm, PackJob{});
+  std::vector<int> njobs(nsteps, 0);
+  for (int s = 0; s < nsteps; ++s) {
+    unsigned first[PK_N] = {0, 0, 0, 0, 0};
+    for (const PackMember& m : ms) {
+      const Plan& p = *m.p;
+      const int nb_all = nbatches(p);
+      if (s >= nb_all) continue;
+      int t0, nb;
+      batch_range(p.ntri, nb_all, s, &t0, &nb);
+      PackJob j{};
+      j.t2 = m.t2; j.t2N = m.w.t2N; j.eps = m.eps;
+      j.Gw = m.w.b.Gw; j.Go = m.w.b.Go; j.Gbc = m.w.b.Gbc; j.Gcb = m.w.b.Gcb; j.Hs = m.w.b.Hs;
+      j.lpt2 = m.w.lp.t2; j.lpt2N = m.w.lp.t2N; j.lpGwT = m.w.lp.GwT; j.lpGoT = m.w.lp.GoT;
+      j.tri = m.w.tri + 3 * t0;
+      j.cubes = m.w.cubes[0]; j.Pvv = m.w.Pvv[0];
+      j.Ot1 = m.w.Ot1; j.Ot2 = m.w.Ot2; j.OtT = m.w.OtT;
+      j.no = p.no; j.nv = p.nv; j.ntri = nb; j.nch = omega_kchunks(p.nv, nb);
+      unsigned it[PK_N];
+      pack_items(j, it);
+      for (int k = 0; k < PK_N; ++k) { j.first[k] = first[k]; first[k] += it[k]; }
+      host_jobs[(size_t)s * nm + njobs[s]++] = j;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(dev_jobs, host_jobs.data(), host_jobs.size() * sizeof(PackJob),
+                        hipMemcpyHostToDevice, st));
+  for (int s = 0; s < nsteps; ++s)
+    launch_packed_step(dev_jobs + (size_t)s * nm, host_jobs.data() + (size_t)s * nm, njobs[s], prec,
+                       st);
+  for (const PackMember& m : ms)
+    launch_back_transform(m.w.Ot1, m.w.Ot2, m.w.OtT, m.O1, m.O2, m.p->no, m.p->nv, false, st);
+  HIPCHK(hipGetLastError());
+  return CC3_OK;
+}
+
+int pack_steps(const Plan& p) { return nbatches(p); }
 
 // Algorithm 2 over every unordered triple: the same batched W build and mix as the
 // residual, then per batch the Zo partials on the batch's stream and, chained in

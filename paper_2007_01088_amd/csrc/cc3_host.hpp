@@ -122,6 +122,19 @@ int jacobian_prep_from_blocks(Runner& rn, Profiler* pf, const Plan& p, const Ws&
 int run_input_check(const Plan& p, const Ws& w, const double* eps, const double* L,
                     const double* t2, hipStream_t st);
 
+// One request of a packed group (serving): its plan and workspace, its inputs
+// (device) and outputs, and whether its integral blocks are rebuilt first.
+struct PackMember {
+  const Plan* p;
+  Ws w;
+  const double *eps, *L, *t1, *t2;
+  double *O1, *O2;
+  bool rebuild;
+};
+int packed_residuals(const std::vector<PackMember>& ms, int prec, PackJob* dev_jobs,
+                     std::vector<PackJob>& host_jobs, hipStream_t st);
+int pack_steps(const Plan& p);  // batches of the plan (the pack's steps)
+
 }  // namespace cc3
 
 // A context of the one-shot calls: its device, kernel timing and runner streams.

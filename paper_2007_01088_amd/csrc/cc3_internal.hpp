@@ -195,6 +195,27 @@ void launch_zo(const double* cubes, const Blocks& b, const int* tri, int ntri, d
                double* Zo, int no, int nv, hipStream_t st, bool reduce);
 double zprep_flops(int no, int nv, const int* host_types, int n);
 
+// ---- packing small serving requests into shared persistent launches ----
+// One packed launch runs one kernel of the triple loop (W build, mix, Omega,
+// oo, reduction) for the current batch of several requests: its workgroups loop
+// over the union of the jobs' work items, each item taking the job's operands.
+enum { PK_W = 0, PK_MIX, PK_OMEGA, PK_OO, PK_RED, PK_N };
+struct PackJob {
+  const double *t2, *t2N, *eps;
+  const double *Gw, *Go, *Gbc, *Gcb, *Hs;
+  const void *lpt2, *lpt2N, *lpGwT, *lpGoT;  // low-precision W operands (FP32, split BF16)
+  const int* tri;                             // the job's batch of triples
+  double *cubes, *Pvv, *Ot1, *Ot2, *OtT;
+  int no, nv, ntri, nch;
+  unsigned first[PK_N];  // first packed work item of this job, per kernel
+};
+// Work items of one job per kernel (the workgroups of its unpacked launch).
+void pack_items(const PackJob& j, unsigned (&items)[PK_N]);
+// The five packed launches of one step (jobs in device memory, host copy for the
+// item counts); prec: the W build's arithmetic, shared by every job.
+void launch_packed_step(const PackJob* dev_jobs, const PackJob* host_jobs, int njobs, int prec,
+                        hipStream_t st);
+
 // ---- transition densities (Algorithm 3) ----
 // Slots of the density loop's cubes, slot-major: cubes[slot][z][nv^3].
 enum { D3_P0 = 0, D3_P1 = 1, D3_P2 = 2, D3_TAU = 3, D3_TAUC = 4, D3_LC = 5, D3_NSLOT = 6 };

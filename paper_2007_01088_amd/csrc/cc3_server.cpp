@@ -55,6 +55,9 @@ struct Request {
 struct Slot {
   bool busy = false;
   uint64_t ticket = 0;
+  std::vector<uint64_t> pack;      // the requests of a packed group (empty: one request)
+  std::vector<PackJob> pack_jobs;  // host copy of the group's job tables
+  size_t pack_off = ~(size_t)0, pack_bytes = 0;  // arena region of the device job tables
   hipStream_t st = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   Runner rn;
@@ -157,8 +160,12 @@ struct cc3_server {
   uint64_t next_id = 1;
   bool stop = false;
   std::thread worker;
-  int64_t n_sub = 0, n_done = 0, n_fail = 0, n_cancel = 0;
+  int64_t n_sub = 0, n_done = 0, n_fail = 0, n_cancel = 0, n_packed = 0, n_packs = 0;
   int inflight = 0, max_seen = 0;
+  // packing: at most max_pack requests of at most pack_flops nominal FLOP each share
+  // the launches of one slot (max_pack 1: no packing)
+  int max_pack = 8;
+  double pack_flops = 2e12;
 
   // host <-> arena copies of the calling threads
   std::mutex up_mu;
@@ -168,15 +175,34 @@ struct cc3_server {
 
   void run();
   void finish(uint64_t ticket, int rc, const char* msg);
+  void finish_one(uint64_t ticket, Slot& s, int rc, const char* msg);
   int launch(uint64_t ticket, Request& r, Molecule& m, Slot& s);
+  int launch_pack(Slot& s, const std::vector<PackMember>& ms, int prec);
+  int ensure_slot(Slot& s);
+  bool packable(const Request& r) const;
 };
 
 // ---------------------------------------------------------------------------
 // worker
 // ---------------------------------------------------------------------------
+// Completion of the request(s) on the slot of `ticket`: every request of a packed
+// group finishes with the group.
 void cc3_server::finish(uint64_t ticket, int rc, const char* msg) {
+  Slot& s = slots[reqs[ticket].slot];
+  if (s.pack.empty()) {
+    finish_one(ticket, s, rc, msg);
+  } else {
+    for (uint64_t t : s.pack) finish_one(t, s, rc, msg);
+    s.pack.clear();
+    if (s.pack_off != NONE) al.release(s.pack_off, s.pack_bytes);
+    s.pack_off = NONE;
+  }
+  s.busy = false;
+  s.ticket = 0;
+}
+
+void cc3_server::finish_one(uint64_t ticket, Slot& s, int rc, const char* msg) {
   Request& r = reqs[ticket];
-  Slot& s = slots[r.slot];
   if (rc == CC3_OK) {
     float ms = 0.f, st = 0.f;
     if (hipEventElapsedTime(&ms, s.ev0, s.ev1) == hipSuccess) r.tm.device_ms = ms;
@@ -195,14 +221,10 @@ void cc3_server::finish(uint64_t ticket, int rc, const char* msg) {
   }
   al.release(r.off, r.plan.total);
   r.off = NONE;
-  s.busy = false;
-  s.ticket = 0;
   --inflight;
 }
 
-// Enqueues the whole request on slot s (called without the lock held: the
-// request, its molecule and the slot are reserved for this thread).
-int cc3_server::launch(uint64_t, Request& r, Molecule& m, Slot& s) {
+int cc3_server::ensure_slot(Slot& s) {
   HIPCHK(hipSetDevice(device));
   if (!s.st) {
     HIPCHK(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
@@ -211,6 +233,53 @@ int cc3_server::launch(uint64_t, Request& r, Molecule& m, Slot& s) {
     int rc0 = s.rn.init(s.st);  // the slot's stream carries every other batch
     if (rc0) return rc0;
   }
+  return CC3_OK;
+}
+
+// A request may join a packed group: a W-only precision, and small enough that
+// its own launches would leave the device partly idle.
+bool cc3_server::packable(const Request& r) const {
+  if (max_pack < 2) return false;
+  const double v = r.plan.nv, o = r.plan.no;
+  return 4.0 * v * v * v * v * o * o * o <= pack_flops;
+}
+
+// The members of slot s's packed group (with the lock held).
+static std::vector<PackMember> pack_members(cc3_server& sv, const Slot& s, int* prec) {
+  std::vector<PackMember> ms;
+  for (uint64_t t : s.pack) {
+    Request& r = sv.reqs.at(t);
+    Molecule& m = sv.mols.at(r.mol);
+    PackMember pm;
+    pm.p = &r.plan;
+    pm.w = carve(r.plan, sv.arena + r.off, &m.b);
+    pm.eps = m.eps; pm.L = m.L; pm.t1 = m.t1; pm.t2 = m.t2;
+    pm.O1 = m.O1; pm.O2 = m.O2;
+    pm.rebuild = r.rebuild;
+    *prec = r.prec;
+    ms.push_back(pm);
+  }
+  return ms;
+}
+
+// Enqueues a packed group on slot s (called without the lock held; the group's
+// requests, molecules and the slot are reserved for this thread; ms was built
+// under the lock).
+int cc3_server::launch_pack(Slot& s, const std::vector<PackMember>& ms, int prec) {
+  int rc = ensure_slot(s);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(s.ev0, s.st));
+  if ((rc = packed_residuals(ms, prec, (PackJob*)(arena + s.pack_off), s.pack_jobs, s.st)))
+    return rc;
+  HIPCHK(hipEventRecord(s.ev1, s.st));
+  return CC3_OK;
+}
+
+// Enqueues the whole request on slot s (called without the lock held: the
+// request, its molecule and the slot are reserved for this thread).
+int cc3_server::launch(uint64_t, Request& r, Molecule& m, Slot& s) {
+  int rc0 = ensure_slot(s);
+  if (rc0) return rc0;
   const Plan& p = r.plan;
   Ws w = carve(p, arena + r.off, &m.b);
   HIPCHK(hipEventRecord(s.ev0, s.st));
@@ -268,16 +337,55 @@ void cc3_server::run() {
       s.busy = true;
       s.ticket = t;
       r.off = off;
-      r.slot = k;
-      r.tm.slot = k;
-      r.tm.rebuilt = r.rebuild ? 1 : 0;
-      r.tm.admit_s = now_s(t0);
-      r.state = R_RUNNING;  // from here on cc3_cancel leaves it alone
-      ++inflight;
+      // packing: the following small requests of the same precision join this one,
+      // as long as their workspaces and the group's job tables fit in the arena
+      s.pack.clear();
+      if (packable(r)) {
+        s.pack.push_back(t);
+        int steps = pack_steps(r.plan);
+        while ((int)s.pack.size() < max_pack && !fifo.empty()) {
+          Request& q = reqs[fifo.front()];
+          if (!packable(q) || q.prec != r.prec) break;
+          const size_t qoff = al.alloc(q.plan.total);
+          if (qoff == NONE) break;
+          q.off = qoff;
+          s.pack.push_back(fifo.front());
+          fifo.pop_front();
+          steps = std::max(steps, pack_steps(q.plan));
+        }
+        s.pack_bytes = (size_t)steps * s.pack.size() * sizeof(PackJob);
+        s.pack_off = s.pack.size() > 1 ? al.alloc(s.pack_bytes) : NONE;
+        if (s.pack_off == NONE) {  // no group: the others go back to the queue front
+          for (size_t g = s.pack.size(); g-- > 1;) {
+            Request& q = reqs[s.pack[g]];
+            al.release(q.off, q.plan.total);
+            q.off = NONE;
+            fifo.push_front(s.pack[g]);
+          }
+          s.pack.clear();
+        }
+      }
+      std::vector<uint64_t> group = s.pack.empty() ? std::vector<uint64_t>{t} : s.pack;
+      for (uint64_t gt : group) {
+        Request& q = reqs[gt];
+        q.slot = k;
+        q.tm.slot = k;
+        q.tm.rebuilt = q.rebuild ? 1 : 0;
+        q.tm.admit_s = now_s(t0);
+        q.state = R_RUNNING;  // from here on cc3_cancel leaves it alone
+        ++inflight;
+      }
+      if (group.size() > 1) {
+        n_packed += (int64_t)group.size();
+        ++n_packs;
+      }
       max_seen = std::max(max_seen, inflight);
       Molecule& m = mols[r.mol];
+      int pprec = CC3_FP64;
+      const std::vector<PackMember> ms =
+          s.pack.empty() ? std::vector<PackMember>() : pack_members(*this, s, &pprec);
       lk.unlock();
-      const int rc = launch(t, r, m, s);
+      const int rc = s.pack.empty() ? launch(t, r, m, s) : launch_pack(s, ms, pprec);
       std::string err = rc ? last_error_str() : std::string();
       lk.lock();
       if (rc) {
@@ -637,5 +745,17 @@ extern "C" int cc3_server_get_stats(cc3_server* s, cc3_server_stats* out) {
   out->arena_bytes = s->arena_bytes;
   out->arena_used = s->al.used;
   out->arena_peak = s->al.peak;
+  out->packed = s->n_packed;
+  out->packs = s->n_packs;
+  return CC3_OK;
+}
+
+extern "C" int cc3_server_set_packing(cc3_server* s, int max_pack, double max_request_flops) {
+  if (!s) return fail(CC3_E_INVAL, "server is NULL");
+  if (max_pack < 1 || max_pack > 64 || !(max_request_flops >= 0.0))
+    return fail(CC3_E_INVAL, "max_pack must be in [1, 64] and max_request_flops >= 0");
+  std::lock_guard<std::mutex> g(s->mu);
+  s->max_pack = max_pack;
+  s->pack_flops = max_request_flops;
   return CC3_OK;
 }

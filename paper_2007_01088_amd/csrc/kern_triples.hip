@@ -24,6 +24,9 @@
 //  k_omega_oo (FP64 MFMA, output-stationary)  the oo and Fock terms
 //              Ot2[p][l][a][b] += sum_c U[a,b,c] (delta_lq F_rc - g_{qlrc}),
 //            kept transposed, OtT[p][l][b][a], so that its stores run along a.
+#include <algorithm>
+
+#include "cc3.h"
 #include "cc3_device.hpp"
 #include "cc3_internal.hpp"
 
@@ -46,22 +49,22 @@ typedef TileCfg<4, 2, 2, 4, 16> WCfg;  // 128 x 128 output plane tile, 8 wavefro
 // Go <- Go3 (Go3[p][q][z][l] = g_{plqz}): the same segments with the roles of the
 // occupied indices permuted.  Plane `plane` of triple z goes to cubes + z zs + plane ss.
 template <int MODE>
-__global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ t2,
-                                                     const double* __restrict__ t2N,
-                                                     const double* __restrict__ Gw,
-                                                     const double* __restrict__ Go,
-                                                     const int* __restrict__ tri,
-                                                     double* __restrict__ cubes, int64_t zs,
-                                                     int64_t ss, int no, int nv, int tiles_m,
-                                                     int tiles_n, int all_terms) {
+__device__ __forceinline__ void wbuild_body(const double* __restrict__ t2,
+                                            const double* __restrict__ t2N,
+                                            const double* __restrict__ Gw,
+                                            const double* __restrict__ Go,
+                                            const int* __restrict__ tri,
+                                            double* __restrict__ cubes, int64_t zs, int64_t ss,
+                                            int no, int nv, int tiles_m, int tiles_n,
+                                            int all_terms, int bx, int by, int bz) {
   typedef WCfg T;
   __shared__ double lds[T::LDS_DOUBLES];
   const int tpp = tiles_m * tiles_n;
-  const int y = blockIdx.x / tpp;
-  const int tile = blockIdx.x % tpp;
+  const int y = bx / tpp;
+  const int tile = bx % tpp;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
-  const int plane = blockIdx.y;
-  const int z = blockIdx.z;
+  const int plane = by;
+  const int z = bz;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   const int kind = all_terms ? TRI_DISTINCT : tri_kind(i, j, k);
   // plane 1 repeats plane 0 when i == j, plane 2 repeats plane 0 when j == k
@@ -193,6 +196,19 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
       }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ t2,
+                                                     const double* __restrict__ t2N,
+                                                     const double* __restrict__ Gw,
+                                                     const double* __restrict__ Go,
+                                                     const int* __restrict__ tri,
+                                                     double* __restrict__ cubes, int64_t zs,
+                                                     int64_t ss, int no, int nv, int tiles_m,
+                                                     int tiles_n, int all_terms) {
+  wbuild_body<MODE>(t2, t2N, Gw, Go, tri, cubes, zs, ss, no, nv, tiles_m, tiles_n, all_terms,
+                    blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 void launch_wbuild_ex(int mode, const double* X, const double* XN, const double* G, const double* H,
                       const int* tri, int ntri, double* cubes, int64_t zs, int64_t ss, int no,
                       int nv, bool all_terms, hipStream_t st) {
@@ -311,13 +327,13 @@ __device__ inline void yl_put(uint16_t* YL, int P, int z, int v, int row, int64_
 // YL, the split-BF16 k-major views of the split-BF16 Omega GEMM (k_omega_lp),
 // [triple][4][piece][a][kk < Kp] with lpP pieces.
 template <int MIXT>
-__global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
-                                             const int* __restrict__ tri,
-                                             double* __restrict__ cubes, float* __restrict__ cubesF,
-                                             uint16_t* __restrict__ YL, int lpP, int no, int nv) {
+__device__ __forceinline__ void mix_body(const double* __restrict__ eps,
+                                         const int* __restrict__ tri, double* __restrict__ cubes,
+                                         float* __restrict__ cubesF, uint16_t* __restrict__ YL,
+                                         int lpP, int no, int nv, int bx, int by) {
   constexpr int MIXH = 512 / MIXT;
   __shared__ double Xs[6 * TSZ];
-  const int z = blockIdx.y, ob = blockIdx.x;
+  const int z = by, ob = bx;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   const int kind = tri_kind(i, j, k);
   const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
@@ -486,6 +502,14 @@ __global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
       }
     }
   }
+}
+
+template <int MIXT>
+__global__ __launch_bounds__(MIXT) void k_mix(const double* __restrict__ eps,
+                                             const int* __restrict__ tri,
+                                             double* __restrict__ cubes, float* __restrict__ cubesF,
+                                             uint16_t* __restrict__ YL, int lpP, int no, int nv) {
+  mix_body<MIXT>(eps, tri, cubes, cubesF, YL, lpP, no, nv, blockIdx.x, blockIdx.y);
 }
 
 void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF,
@@ -719,22 +743,21 @@ struct OmegaAcc<float> {
 // cubes: the batch's cube slots, nslot per triple, the first of them slot0 (the
 // FP64 cubes hold all five slots; the FP32 copies only TT and TTT)
 template <class E>
-__global__ __launch_bounds__(OCfg::NT) void k_omega(const E* __restrict__ cubes, int nslot,
-                                                    int slot0, const E* __restrict__ Gbc,
-                                                    const E* __restrict__ Gcb,
-                                                    const int* __restrict__ tri,
-                                                    double* __restrict__ Pvv, int no, int nv,
-                                                    int nchunks, int tiles_n) {
+__device__ __forceinline__ void omega_body(const E* __restrict__ cubes, int nslot, int slot0,
+                                           const E* __restrict__ Gbc, const E* __restrict__ Gcb,
+                                           const int* __restrict__ tri, double* __restrict__ Pvv,
+                                           int no, int nv, int nchunks, int tiles_n, int bx,
+                                           int by, int bz) {
   typedef OCfg T;
   typedef OmegaAcc<E> M;
   constexpr unsigned ES = sizeof(E);
   __shared__ E lds[T::LDS_DOUBLES];
-  const int pi = blockIdx.y, z = blockIdx.z;
+  const int pi = by, z = bz;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   if (!perm_active(tri_kind(i, j, k), pi)) return;
   int p, q, r;
   perm_pqr(pi, i, j, k, p, q, r);
-  const int ch = blockIdx.x % nchunks, tile = blockIdx.x / nchunks;
+  const int ch = bx % nchunks, tile = bx / nchunks;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
   const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
   const int K = nv * nv;
@@ -861,6 +884,17 @@ __global__ __launch_bounds__(OCfg::NT) void k_omega(const E* __restrict__ cubes,
       }
 }
 
+template <class E>
+__global__ __launch_bounds__(OCfg::NT) void k_omega(const E* __restrict__ cubes, int nslot,
+                                                    int slot0, const E* __restrict__ Gbc,
+                                                    const E* __restrict__ Gcb,
+                                                    const int* __restrict__ tri,
+                                                    double* __restrict__ Pvv, int no, int nv,
+                                                    int nchunks, int tiles_n) {
+  omega_body<E>(cubes, nslot, slot0, Gbc, Gcb, tri, Pvv, no, nv, nchunks, tiles_n, blockIdx.x,
+                blockIdx.y, blockIdx.z);
+}
+
 // The (triple, permutation) pairs of a batch whose first occupied index is p, in
 // batch order (triple, then permutation): lz = 6 z + pi, lqr = q no + r; at most two
 // per triple, so at most 2 * MAX_BATCH.  Every thread of the workgroup calls it (it
@@ -974,19 +1008,19 @@ __device__ inline void u_view(int pi, int nv, int& slot, int& sbb, int& sm, int&
 // contiguous are loaded along c (4 rows of 16 consecutive c per instruction) and
 // transposed through a wavefront-private LDS tile.
 template <int FNO>
-__global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cubes,
-                                                  const double* __restrict__ Hs,
-                                                  const int* __restrict__ tri, int ntri,
-                                                  double* __restrict__ OtT, int no, int nv,
-                                                  int tiles_a) {
+__device__ __forceinline__ void omega_oo_body(const double* __restrict__ cubes,
+                                              const double* __restrict__ Hs,
+                                              const int* __restrict__ tri, int ntri,
+                                              double* __restrict__ OtT, int no, int nv,
+                                              int tiles_a, int bx, int by) {
   constexpr int NB = 2;
   __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX], cz[MAX_BATCH + 1];
   int cnt;
   __shared__ double lt[4][NB][16][17];  // per wavefront: 16 rows a x 16 c (+1 pad)
-  const int p = blockIdx.y;
-  const int bp = blockIdx.x / tiles_a;
+  const int p = by;
+  const int bp = bx / tiles_a;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int a0 = (blockIdx.x % tiles_a) * 64 + 16 * wave;
+  const int a0 = (bx % tiles_a) * 64 + 16 * wave;
   cnt = pairs_with_p(tri, ntri, p, no, lz, lqr, cz);
   const int n = cnt;
   if (n == 0 || a0 >= nv) return;  // no workgroup barrier follows
@@ -1097,23 +1131,32 @@ __global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cub
   }
 }
 
+template <int FNO>
+__global__ __launch_bounds__(256) void k_omega_oo(const double* __restrict__ cubes,
+                                                  const double* __restrict__ Hs,
+                                                  const int* __restrict__ tri, int ntri,
+                                                  double* __restrict__ OtT, int no, int nv,
+                                                  int tiles_a) {
+  omega_oo_body<FNO>(cubes, Hs, tri, ntri, OtT, no, nv, tiles_a, blockIdx.x, blockIdx.y);
+}
+
 // For output block (p, x):
 //   Ot2[p][x][a][d] += sum of Pvv[z][pi][chunk][a][d] over the batch's (triple,
 //                      permutation) pairs with that p and q == x, and chunks;
 //   Ot1[p][a]       += column nv of Pvv (block x == 0).
 // Fixed summation order: triple, permutation, chunk.
-__global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int ntri,
-                                                const double* __restrict__ Pvv,
-                                                double* __restrict__ Ot1, double* __restrict__ Ot2,
-                                                int no, int nv, int nchunks) {
+__device__ __forceinline__ void reduce_body(const int* __restrict__ tri, int ntri,
+                                            const double* __restrict__ Pvv,
+                                            double* __restrict__ Ot1, double* __restrict__ Ot2,
+                                            int no, int nv, int nchunks, int bx, int by, int bz) {
   __shared__ int lz[PLIST_MAX], lqr[PLIST_MAX], cz[MAX_BATCH + 1];
   int cnt;
-  const int p = blockIdx.z, x = blockIdx.y;
+  const int p = bz, x = by;
   cnt = pairs_with_p(tri, ntri, p, no, lz, lqr, cz);
   const int64_t nvl = nv, nv2 = nvl * nvl;
   const int NV1 = nv + 1;
   const int64_t pvs = (int64_t)nvl * NV1;  // one chunk slab
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
   const bool o2 = e < nv2;
   const bool o1 = (x == 0) && e < nv;  // Omega1 element a = e
   if (!o2 && !o1) return;
@@ -1140,6 +1183,13 @@ __global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int
     }
     Ot1[(int64_t)p * nvl + e] += s1;
   }
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ tri, int ntri,
+                                                const double* __restrict__ Pvv,
+                                                double* __restrict__ Ot1, double* __restrict__ Ot2,
+                                                int no, int nv, int nchunks) {
+  reduce_body(tri, ntri, Pvv, Ot1, Ot2, no, nv, nchunks, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1391,6 +1441,138 @@ void launch_reduce(const int* tri, int ntri, const double* Pvv, double* Ot1, dou
   const int64_t nv2 = (int64_t)nv * nv;
   hipLaunchKernelGGL(k_reduce, dim3(nblk(nv2, 256), no, no), dim3(256), 0, st, tri, ntri, Pvv, Ot1,
                      Ot2, no, nv, nch);
+}
+
+// ---------------------------------------------------------------------------
+// Packed persistent launches of the triple loop (serving): each workgroup takes
+// work items blockIdx.x, blockIdx.x + gridDim.x, ... of the union of the jobs'
+// unpacked grids and runs the same body on the job's operands, so each job's
+// arithmetic is exactly that of its own launch.
+// ---------------------------------------------------------------------------
+__device__ inline int pack_job(const PackJob* __restrict__ jobs, int njobs, int kind,
+                               unsigned item) {
+  int r = 0;
+  while (r + 1 < njobs && item >= jobs[r + 1].first[kind]) ++r;
+  return r;
+}
+
+__global__ __launch_bounds__(WCfg::NT) void k_pack_wbuild(const PackJob* __restrict__ jobs,
+                                                          int njobs, unsigned total) {
+  typedef WCfg T;
+  for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+    const PackJob& J = jobs[pack_job(jobs, njobs, PK_W, item)];
+    const unsigned local = item - J.first[PK_W];
+    const int tm = (J.nv + T::BM - 1) / T::BM, tn = (J.nv + T::BN - 1) / T::BN;
+    const unsigned gx = (unsigned)J.nv * tm * tn;
+    const int64_t nv3 = (int64_t)J.nv * J.nv * J.nv;
+    wbuild_body<0>(J.t2, J.t2N, J.Gw, J.Go, J.tri, J.cubes, NSLOT * nv3, nv3, J.no, J.nv, tm, tn,
+                   0, (int)(local % gx), (int)((local / gx) % 3), (int)(local / (gx * 3)));
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(512) void k_pack_mix(const PackJob* __restrict__ jobs, int njobs,
+                                                  unsigned total) {
+  for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+    const PackJob& J = jobs[pack_job(jobs, njobs, PK_MIX, item)];
+    const unsigned local = item - J.first[PK_MIX];
+    const int nb = (J.nv + MT - 1) / MT;
+    const unsigned nbt = (unsigned)(nb * (nb + 1) * (nb + 2) / 6);
+    mix_body<512>(J.eps, J.tri, J.cubes, nullptr, nullptr, 0, J.no, J.nv, (int)(local % nbt),
+                  (int)(local / nbt));
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(OCfg::NT) void k_pack_omega(const PackJob* __restrict__ jobs,
+                                                         int njobs, unsigned total) {
+  typedef OCfg T;
+  for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+    const PackJob& J = jobs[pack_job(jobs, njobs, PK_OMEGA, item)];
+    const unsigned local = item - J.first[PK_OMEGA];
+    const int tm = (J.nv + T::BM - 1) / T::BM, tn = (J.nv + 1 + T::BN - 1) / T::BN;
+    const unsigned gx = (unsigned)J.nch * tm * tn;
+    omega_body<double>(J.cubes, (int)NSLOT, 0, J.Gbc, J.Gcb, J.tri, J.Pvv, J.no, J.nv, J.nch, tn,
+                       (int)(local % gx), (int)((local / gx) % 6), (int)(local / (gx * 6)));
+    __syncthreads();
+  }
+}
+
+template <int FNO>
+__global__ __launch_bounds__(256) void k_pack_omega_oo(const PackJob* __restrict__ jobs, int njobs,
+                                                       unsigned total) {
+  for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+    const PackJob& J = jobs[pack_job(jobs, njobs, PK_OO, item)];
+    const unsigned local = item - J.first[PK_OO];
+    const int ta = (J.nv + 63) / 64;
+    const unsigned gx = (unsigned)((J.nv + 1) / 2) * ta;
+    omega_oo_body<FNO>(J.cubes, J.Hs, J.tri, J.ntri, J.OtT, J.no, J.nv, ta, (int)(local % gx),
+                       (int)(local / gx));
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pack_reduce(const PackJob* __restrict__ jobs, int njobs,
+                                                     unsigned total) {
+  for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+    const PackJob& J = jobs[pack_job(jobs, njobs, PK_RED, item)];
+    const unsigned local = item - J.first[PK_RED];
+    const unsigned gx = (unsigned)(((int64_t)J.nv * J.nv + 255) / 256);
+    reduce_body(J.tri, J.ntri, J.Pvv, J.Ot1, J.Ot2, J.no, J.nv, J.nch, (int)(local % gx),
+                (int)((local / gx) % J.no), (int)(local / (gx * J.no)));
+    __syncthreads();
+  }
+}
+
+void pack_items(const PackJob& j, unsigned (&items)[PK_N]) {
+  const int no = j.no, nv = j.nv, nt = j.ntri;
+  const unsigned tw = (unsigned)((nv + WCfg::BM - 1) / WCfg::BM) * ((nv + WCfg::BN - 1) / WCfg::BN);
+  items[PK_W] = (unsigned)nv * tw * 3u * nt;
+  const int nb = (nv + MT - 1) / MT;
+  items[PK_MIX] = (unsigned)(nb * (nb + 1) * (nb + 2) / 6) * nt;
+  const unsigned to = (unsigned)((nv + OCfg::BM - 1) / OCfg::BM) * ((nv + 1 + OCfg::BN - 1) / OCfg::BN);
+  items[PK_OMEGA] = (unsigned)j.nch * to * 6u * nt;
+  items[PK_OO] = (unsigned)((nv + 1) / 2) * ((nv + 63) / 64) * no;
+  items[PK_RED] = nblk((int64_t)nv * nv, 256) * no * no;
+}
+
+// persistent grids: a few rounds of resident workgroups, never more than the items
+static unsigned pack_grid(unsigned total, unsigned cap) { return total < cap ? total : cap; }
+
+void launch_wbuild_lp_packed(const PackJob* jobs, int njobs, unsigned total, int prec,
+                             hipStream_t st);
+
+void launch_packed_step(const PackJob* dev_jobs, const PackJob* host_jobs, int njobs, int prec,
+                        hipStream_t st) {
+  if (njobs <= 0) return;
+  unsigned total[PK_N] = {0, 0, 0, 0, 0};
+  int max_no = 1;
+  for (int r = 0; r < njobs; ++r) {
+    unsigned it[PK_N];
+    pack_items(host_jobs[r], it);
+    for (int k = 0; k < PK_N; ++k) total[k] += it[k];
+    max_no = std::max(max_no, host_jobs[r].no);
+  }
+  if (prec == CC3_FP64)
+    hipLaunchKernelGGL(k_pack_wbuild, dim3(pack_grid(total[PK_W], 2048)), dim3(WCfg::NT), 0, st,
+                       dev_jobs, njobs, total[PK_W]);
+  else
+    launch_wbuild_lp_packed(dev_jobs, njobs, total[PK_W], prec, st);
+  hipLaunchKernelGGL(k_pack_mix, dim3(pack_grid(total[PK_MIX], 4096)), dim3(512), 0, st, dev_jobs,
+                     njobs, total[PK_MIX]);
+  hipLaunchKernelGGL(k_pack_omega, dim3(pack_grid(total[PK_OMEGA], 2048)), dim3(OCfg::NT), 0, st,
+                     dev_jobs, njobs, total[PK_OMEGA]);
+  const dim3 goo(pack_grid(total[PK_OO], 8192));
+  if (max_no <= 16)
+    hipLaunchKernelGGL(k_pack_omega_oo<1>, goo, dim3(256), 0, st, dev_jobs, njobs, total[PK_OO]);
+  else if (max_no <= 32)
+    hipLaunchKernelGGL(k_pack_omega_oo<2>, goo, dim3(256), 0, st, dev_jobs, njobs, total[PK_OO]);
+  else if (max_no <= 48)
+    hipLaunchKernelGGL(k_pack_omega_oo<3>, goo, dim3(256), 0, st, dev_jobs, njobs, total[PK_OO]);
+  else
+    hipLaunchKernelGGL(k_pack_omega_oo<4>, goo, dim3(256), 0, st, dev_jobs, njobs, total[PK_OO]);
+  hipLaunchKernelGGL(k_pack_reduce, dim3(pack_grid(total[PK_RED], 16384)), dim3(256), 0, st,
+                     dev_jobs, njobs, total[PK_RED]);
 }
 
 // FLOP of the dominant contractions and their companions, padding excluded.

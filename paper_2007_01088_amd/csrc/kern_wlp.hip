@@ -171,20 +171,20 @@ struct LpSeg {
 };
 
 template <class E>
-__global__ __launch_bounds__(LNT) void k_wbuild_lp(
+__device__ __forceinline__ void wbuild_lp_body(
     const char* __restrict__ t2L, const char* __restrict__ t2NL, const char* __restrict__ GwTL,
     const char* __restrict__ GoTL, const int* __restrict__ tri, double* __restrict__ cubes, int no,
-    int nv, int tiles_m, int tiles_n, int all_terms) {
+    int nv, int tiles_m, int tiles_n, int all_terms, int bx, int by, int bz) {
   constexpr int BK = E::BK, P = E::P, ESZ = E::ESZ, ROWB = E::ROWB;
   constexpr int TILEB = LBM * ROWB;  // one operand tile, one piece (LBM == LBN)
   constexpr int STAGEB = 2 * P * TILEB;
   __shared__ __attribute__((aligned(16))) char lds[2 * STAGEB];
   const int tpp = tiles_m * tiles_n;
-  const int y = blockIdx.x / tpp;
-  const int tile = blockIdx.x % tpp;
+  const int y = bx / tpp;
+  const int tile = bx % tpp;
   const int m0 = (tile / tiles_n) * LBM, n0 = (tile % tiles_n) * LBN;
-  const int plane = blockIdx.y;
-  const int z = blockIdx.z;
+  const int plane = by;
+  const int z = bz;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   int kind = (i == j) ? 1 : (j == k) ? 2 : 0;
   if (all_terms) kind = 0;
@@ -369,6 +369,15 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
         if (m < nv && n < nv)
           dst[(int64_t)m * nv + n] = accd[fm][fn][r] + ((double)acc1[fm][fn][r] + (double)acc2[fm][fn][r]);
       }
+}
+
+template <class E>
+__global__ __launch_bounds__(LNT) void k_wbuild_lp(
+    const char* __restrict__ t2L, const char* __restrict__ t2NL, const char* __restrict__ GwTL,
+    const char* __restrict__ GoTL, const int* __restrict__ tri, double* __restrict__ cubes, int no,
+    int nv, int tiles_m, int tiles_n, int all_terms) {
+  wbuild_lp_body<E>(t2L, t2NL, GwTL, GoTL, tri, cubes, no, nv, tiles_m, tiles_n, all_terms,
+                    blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,6 +578,35 @@ void launch_omega_lp(int prec, const void* YL, const void* GbcL, const void* Gcb
     hipLaunchKernelGGL(k_omega_lp<EngBF16<2>>, grid, block, 0, st, y, gb, gc, tri, Pvv, no, nv, nch, tn);
   else
     hipLaunchKernelGGL(k_omega_lp<EngBF16<3>>, grid, block, 0, st, y, gb, gc, tri, Pvv, no, nv, nch, tn);
+}
+
+// Packed persistent form of the low-precision W build (serving), as k_pack_wbuild.
+template <class E>
+__global__ __launch_bounds__(LNT) void k_pack_wbuild_lp(const PackJob* __restrict__ jobs,
+                                                        int njobs, unsigned total) {
+  for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+    int r = 0;
+    while (r + 1 < njobs && item >= jobs[r + 1].first[PK_W]) ++r;
+    const PackJob& J = jobs[r];
+    const unsigned local = item - J.first[PK_W];
+    const int tm = (J.nv + LBM - 1) / LBM, tn = (J.nv + LBN - 1) / LBN;
+    const unsigned gx = (unsigned)J.nv * tm * tn;
+    wbuild_lp_body<E>((const char*)J.lpt2, (const char*)J.lpt2N, (const char*)J.lpGwT,
+                      (const char*)J.lpGoT, J.tri, J.cubes, J.no, J.nv, tm, tn, 0,
+                      (int)(local % gx), (int)((local / gx) % 3), (int)(local / (gx * 3)));
+    __syncthreads();
+  }
+}
+
+void launch_wbuild_lp_packed(const PackJob* jobs, int njobs, unsigned total, int prec,
+                             hipStream_t st) {
+  const dim3 grid(total < 2048 ? total : 2048), block(LNT);
+  if (prec == CC3_FP32)
+    hipLaunchKernelGGL(k_pack_wbuild_lp<EngF32>, grid, block, 0, st, jobs, njobs, total);
+  else if (prec == CC3_BF16X3)
+    hipLaunchKernelGGL(k_pack_wbuild_lp<EngBF16<2>>, grid, block, 0, st, jobs, njobs, total);
+  else
+    hipLaunchKernelGGL(k_pack_wbuild_lp<EngBF16<3>>, grid, block, 0, st, jobs, njobs, total);
 }
 
 void launch_wbuild_lp(const LpOperands& lp, const int* tri, int ntri, double* cubes, int no, int nv,

@@ -247,3 +247,53 @@ def test_request_larger_than_arena(data):
         srv.register(d["no"], d["nv"], g["eps"], g["L"], g["t1"])
     assert e.value.code == cc3.E_NOMEM
     srv.close()
+
+
+# small molecules of the serving mix's size range (no 5-20, nv 60-250), each at most
+# 2e12 nominal FLOP, with one to eleven batches
+PACK_MOLS = [(5, 60, 195), (8, 100, 324), (10, 90, 300), (6, 150, 468), (12, 120, 396)]
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_packed_group_equals_alone(prec_name):
+    """Five small molecules queued behind a large request on one slot run as one packed
+    group (batch s of each in the same persistent launches); each result equals, bit for
+    bit, the result of the same request run alone with packing off, and the smallest
+    one matches the oracle."""
+    torch = _torch()
+    from paper_2007_01088_amd import cc3
+    from paper_2007_01088_amd.synth import make_inputs_device
+    prec = {"fp64": cc3.FP64, "fp32": cc3.FP32}[prec_name]
+    say(f"packing ({prec_name}): a large request, then {len(PACK_MOLS)} small ones on one slot")
+    srv, _ = make_server(torch, 48 << 30, 1)
+    srv.set_packing(8, 2e12)
+    big = make_inputs_device(12, 160, 516, tag=77)
+    mb = srv.register(12, 160, big["eps"], big["L"], big["t1"])
+    ds = [make_inputs_device(no, nv, nJ, tag=90 + t) for t, (no, nv, nJ) in enumerate(PACK_MOLS)]
+    ms = [srv.register(d["no"], d["nv"], d["eps"], d["L"], d["t1"]) for d in ds]
+    torch.cuda.synchronize()
+    tb = srv.submit(mb, big["t2"], prec=prec)
+    tks = [srv.submit(m, d["t2"], prec=prec) for m, d in zip(ms, ds)]
+    srv.wait(tb, want_result=False)
+    packed = [srv.wait(t, mol=m) for t, m in zip(tks, ms)]
+    st = srv.stats()
+    say(f"  stats: packed {st['packed']} in {st['packs']} group(s)")
+    assert st["packs"] >= 1 and st["packed"] >= 2, st
+    assert len({tm["slot"] for _, _, tm in packed}) == 1
+    srv.set_packing(1, 0)
+    for (no, nv, _), m, d, (p1, p2, tm) in zip(PACK_MOLS, ms, ds, packed):
+        a1, a2, _ = srv.wait(srv.submit(m, d["t2"], prec=prec), mol=m)
+        same = torch.equal(a1, p1) and torch.equal(a2, p2)
+        say(f"  no={no} nv={nv}: packed == alone bit for bit: {same} "
+            f"(device {tm['device_ms']:.1f} ms)")
+        assert same
+    assert srv.stats()["packs"] == st["packs"]
+    # the smallest molecule against the oracle (FP64 bar; FP32-W bound 1e-7)
+    d0 = ds[0]
+    h = {k: d0[k].cpu().numpy() for k in ("eps", "L", "t1", "t2")}
+    r1, r2 = O.triples_residual(h["eps"], h["L"], h["t1"], h["t2"])
+    e1, e2 = rel(packed[0][0].cpu().numpy(), r1), rel(packed[0][1].cpu().numpy(), r2)
+    say(f"  no=5 nv=60 against the oracle: {e1:.2e} {e2:.2e}")
+    bound = TOL if prec_name == "fp64" else 1e-7
+    assert e1 <= bound and e2 <= bound
+    srv.close()

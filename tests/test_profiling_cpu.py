@@ -53,3 +53,35 @@ def test_traffic_scales_by_copy_calibration(tmp_path):
     assert r["write_bytes_per_launch"] == pytest.approx(50.0 * 1024)
     r0 = P.traffic(str(fetch), str(write), "k_omega", None)
     assert r0["calibration"] is None and r0["fetch_bytes_per_launch"] == pytest.approx(200.0 * 1024)
+
+
+def test_mfma_summary_busy_share_and_rate(tmp_path):
+    db = tmp_path / "run_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, duration integer)")
+    con.executemany("insert into kernels values (?, ?)",
+                    [("cc3::k_wbuild<0>(x)", 2_000_000), ("cc3::k_wbuild<0>(x)", 2_000_000),
+                     ("cc3::k_mix<512>(y)", 500_000)])
+    con.commit()
+    con.close()
+    fields = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    pmc = tmp_path / "m.csv"
+    with open(pmc, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for disp in (1, 2):
+            for c, v in (("SQ_VALU_MFMA_BUSY_CYCLES", 512.0e6), ("GRBM_GUI_ACTIVE", 1.0e6),
+                         ("SQ_INSTS_VALU_MFMA_MOPS_F64", 1.0e11 / 512)):
+                w.writerow({"Dispatch_Id": disp, "Kernel_Name": "cc3::k_wbuild<0>(x)",
+                            "Counter_Name": c, "Counter_Value": v})
+        w.writerow({"Dispatch_Id": 3, "Kernel_Name": "cc3::k_mix<512>(y)",
+                    "Counter_Name": "GRBM_GUI_ACTIVE", "Counter_Value": 1.0e5})
+    rows = {r["kernel"]: r for r in P.mfma_summary(str(db), str(pmc), None, None, None, ".", None)}
+    wb = rows["cc3::k_wbuild<0>"]
+    # 512e6 busy cycles over 1e6 cycles x 1024 SIMDs: half the SIMD cycles
+    assert wb["mfma_busy"] == pytest.approx(0.5)
+    # 1e11 FLOP in 2 ms: 50 TFLOP/s, of the 78.6 TFLOP/s FP64 peak
+    assert wb["mfma_type"] == "F64" and wb["mfma_tflops"] == pytest.approx(50.0)
+    assert wb["peak_frac"] == pytest.approx(50.0 / 78.6)
+    assert rows["cc3::k_mix<512>"]["mfma_type"] is None
+    assert "`cc3::k_wbuild<0>`" in P.mfma_markdown(list(rows.values()), "cmd")
