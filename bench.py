@@ -117,7 +117,8 @@ def _pct(x, q):
 
 
 def serve(n_mol: int, n_calls: int, prec_name: str, slots: int, load: float,
-          small_arena_gb: float, seed: int = 5) -> dict:
+          small_arena_gb: float, seed: int = 5, max_pack: int = 8,
+          pack_flops: float = 2e12) -> dict:
     """Serving mix: molecules with no ~ U[5,20], nv ~ U[60,250], Cholesky rank
     3(no+nv), each issuing `n_calls` closed-loop residual calls (the next call
     goes out when the previous result is back, with t2 perturbed as by a solver
@@ -140,6 +141,7 @@ def serve(n_mol: int, n_calls: int, prec_name: str, slots: int, load: float,
         f"arena {arena_bytes / 2**30:.1f} GiB")
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
     srv = cc3.Server(arena, max_inflight=slots)
+    srv.set_packing(max_pack, pack_flops)
     mols, t2s = [], []
     resident = 0
     for m, (no, nv, nJ) in enumerate(mix):
@@ -223,6 +225,8 @@ def serve(n_mol: int, n_calls: int, prec_name: str, slots: int, load: float,
         "device_ms_p50": _pct(dev_ms, 50), "device_ms_p99": _pct(dev_ms, 99),
         "aggregate_tflops": flop_done / makespan / 1e12, "makespan_s": makespan,
         "max_inflight_seen": st["max_inflight_seen"], "arena_peak_gib": st["arena_peak"] / 2**30,
+        "packing": {"max_pack": max_pack, "max_request_flops": pack_flops,
+                    "requests_packed": st["packed"], "groups": st["packs"]},
     }
     log(f"serving: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms, "
         f"{res['aggregate_tflops']:.2f} TFLOP/s aggregate")
@@ -235,6 +239,7 @@ def serve(n_mol: int, n_calls: int, prec_name: str, slots: int, load: float,
         nbytes = int(small_arena_gb * 2**30) & ~255
         arena = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         srv = cc3.Server(arena, max_inflight=slots)
+        srv.set_packing(max_pack, pack_flops)
         sub, used, tr_max = [], 0, 0
         for m, (no, nv, nJ) in enumerate(mix):
             r, tr = srv.footprint(no, nv, nJ, prec)
@@ -298,6 +303,8 @@ def main() -> int:
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-small-arena-gb", type=float, default=8.0)
+    ap.add_argument("--serve-pack", type=int, default=8,
+                    help="largest packed group of small serving requests (1: no packing)")
     ap.add_argument("--serve-only", action="store_true",
                     help="print the serving measurement as the JSON line (no residual timing)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -321,7 +328,7 @@ def main() -> int:
 
     if args.serve_only:
         res = serve(args.serve_molecules, args.serve_calls, args.serve_prec, args.serve_slots,
-                    args.serve_load, args.serve_small_arena_gb)
+                    args.serve_load, args.serve_small_arena_gb, max_pack=args.serve_pack)
         print(json.dumps({
             "metric": "Serving p50/p99 latency (ms) and aggregate TFLOP/s (4nv^4no^3/call)",
             "value": res["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": res["requests"],
@@ -562,7 +569,8 @@ def main() -> int:
         del g, o1, o2
         torch.cuda.empty_cache()
         out["serving"] = serve(args.serve_molecules, args.serve_calls, args.serve_prec,
-                               args.serve_slots, args.serve_load, args.serve_small_arena_gb)
+                               args.serve_slots, args.serve_load, args.serve_small_arena_gb,
+                               max_pack=args.serve_pack)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(no, nv, nchol, args.cpu_budget)

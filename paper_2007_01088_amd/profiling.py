@@ -104,11 +104,16 @@ PEAKS = {"F64": 78.6, "F32": 157.3, "BF16": 2516.6}
 
 def mfma_summary(trace_db: str, mfma_csv: str, fetch_csv: str | None, write_csv: str | None,
                  lds_csv: str | None, kernel_re: str, calib_bytes: float | None,
-                 simds: int = 1024) -> list[dict]:
+                 simds: int = 1024, xcds: int = 8) -> list[dict]:
     """Per kernel: average duration (kernel trace), MFMA busy share of the SIMD cycles
-    (SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs)), FLOP counted by the MFMA
-    units (SQ_INSTS_VALU_MFMA_MOPS_* x 512) and their rate, HBM bytes per dispatch
-    (calibrated FETCH_SIZE / WRITE_SIZE) and the LDS bank-conflict share."""
+    (SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / XCDs x SIMDs)), FLOP counted by the
+    MFMA units (SQ_INSTS_VALU_MFMA_MOPS_* x 512) and their rate, HBM bytes per dispatch
+    (calibrated FETCH_SIZE / WRITE_SIZE), the LDS bank-conflict share of the LDS-active
+    cycles and the share of wave cycles spent waiting on LDS instructions.
+
+    rocprofv3 reports GRBM_GUI_ACTIVE summed over the XCDs: a fill kernel of 164.6 us
+    reads 3.22e6 cycles, 8 x 2.44 GHz x its duration, so the per-XCD (chip) cycle count
+    is GRBM_GUI_ACTIVE / 8 on MI355X."""
     dur = {r["kernel"]: r for r in kernel_stats(trace_db)}
     mf = _per_dispatch(mfma_csv)
     tr = {}
@@ -139,7 +144,7 @@ def mfma_summary(trace_db: str, mfma_csv: str, fetch_csv: str | None, write_csv:
         avg_us = dur[k]["avg_us"] if k in dur else None
         rate = flops[kind] / (avg_us * 1e-6) / 1e12 if avg_us and flops[kind] else None
         row = {"kernel": k, "dispatches": n, "avg_us": avg_us,
-               "mfma_busy": busy / (gui * simds) if gui else None,
+               "mfma_busy": busy / (gui / xcds * simds) if gui else None,
                "mfma_type": kind if flops[kind] else None,
                "mfma_flop_per_dispatch": flops[kind],
                "mfma_tflops": rate, "peak_frac": rate / PEAKS[kind] if rate else None}
@@ -149,6 +154,9 @@ def mfma_summary(trace_db: str, mfma_csv: str, fetch_csv: str | None, write_csv:
             conf = sum(d.get("SQ_LDS_BANK_CONFLICT", 0.0) for d in lds[k].values())
             act = sum(d.get("SQ_LDS_IDX_ACTIVE", 0.0) for d in lds[k].values())
             row["lds_bank_conflict_share"] = conf / act if act else None
+            wait = sum(d.get("SQ_WAIT_INST_LDS", 0.0) for d in lds[k].values())
+            wave = sum(d.get("SQ_WAVE_CYCLES", 0.0) for d in lds[k].values())
+            row["lds_wait_share"] = wait / wave if wave else None
         out.append(row)
     out.sort(key=lambda r: -(r["avg_us"] or 0) * r["dispatches"])
     return out
@@ -159,8 +167,8 @@ def mfma_markdown(rows: list[dict], cmd: str | None) -> str:
     if cmd:
         lines += ["Commands:", "", "    " + cmd, ""]
     lines += ["| kernel | dispatches | avg (us) | MFMA busy | MFMA FLOP / dispatch | counted TFLOP/s "
-              "| of dtype peak | HBM read / written per dispatch | LDS bank conflicts |",
-              "|---|---|---|---|---|---|---|---|---|"]
+              "| of dtype peak | HBM read / written per dispatch | LDS bank conflicts | LDS wait |",
+              "|---|---|---|---|---|---|---|---|---|---|"]
     for r in rows:
         def f(x, fmt):
             return format(x, fmt) if x is not None else "-"
@@ -172,7 +180,8 @@ def mfma_markdown(rows: list[dict], cmd: str | None) -> str:
             f"{f(r['mfma_flop_per_dispatch'], '.3e')} {r['mfma_type'] or ''} | "
             f"{f(r['mfma_tflops'], '.1f')} | "
             f"{f(r['peak_frac'] * 100 if r['peak_frac'] else None, '.1f')}% | {rb} | "
-            f"{f(r.get('lds_bank_conflict_share', None), '.3f')} |")
+            f"{f(r.get('lds_bank_conflict_share', None), '.3f')} | "
+            f"{f(r.get('lds_wait_share', None), '.3f')} |")
     return "\n".join(lines) + "\n"
 
 

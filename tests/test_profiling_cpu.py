@@ -70,7 +70,7 @@ def test_mfma_summary_busy_share_and_rate(tmp_path):
         w = csv.DictWriter(f, fieldnames=fields)
         w.writeheader()
         for disp in (1, 2):
-            for c, v in (("SQ_VALU_MFMA_BUSY_CYCLES", 512.0e6), ("GRBM_GUI_ACTIVE", 1.0e6),
+            for c, v in (("SQ_VALU_MFMA_BUSY_CYCLES", 512.0e6), ("GRBM_GUI_ACTIVE", 8.0e6),
                          ("SQ_INSTS_VALU_MFMA_MOPS_F64", 1.0e11 / 512)):
                 w.writerow({"Dispatch_Id": disp, "Kernel_Name": "cc3::k_wbuild<0>(x)",
                             "Counter_Name": c, "Counter_Value": v})
@@ -78,7 +78,8 @@ def test_mfma_summary_busy_share_and_rate(tmp_path):
                     "Counter_Name": "GRBM_GUI_ACTIVE", "Counter_Value": 1.0e5})
     rows = {r["kernel"]: r for r in P.mfma_summary(str(db), str(pmc), None, None, None, ".", None)}
     wb = rows["cc3::k_wbuild<0>"]
-    # 512e6 busy cycles over 1e6 cycles x 1024 SIMDs: half the SIMD cycles
+    # GRBM_GUI_ACTIVE is summed over the 8 XCDs: 512e6 busy cycles over 1e6 chip cycles
+    # x 1024 SIMDs is half the SIMD cycles
     assert wb["mfma_busy"] == pytest.approx(0.5)
     # 1e11 FLOP in 2 ms: 50 TFLOP/s, of the 78.6 TFLOP/s FP64 peak
     assert wb["mfma_type"] == "F64" and wb["mfma_tflops"] == pytest.approx(50.0)
