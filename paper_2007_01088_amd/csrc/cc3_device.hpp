@@ -111,36 +111,46 @@ struct StageMap {
 };
 
 // Global -> registers for one (X x BK) stage of an operand; x0/k0 the tile origin.
+// Elements outside the operand load its first element instead, and bit e of zm
+// tells which elements are inside: their zero is applied by store_stage, after
+// the current stage's MFMAs, so that the loads stay in flight during them.
 template <int X, int BK, int E, int NT>
-__device__ inline void load_stage(const Opnd& o, int x0, int k0, double (&r)[E], int tid) {
+__device__ inline void load_stage(const Opnd& o, int x0, int k0, double (&r)[E], unsigned& zm,
+                                  int tid) {
   const StageMap<X, BK, NT> mp(o.xfast, tid);
   const double* base = o.p + ((int64_t)x0 * o.sx + (int64_t)k0 * o.sk);
   const int off0 = mp.x_t * o.sx + mp.k_t * o.sk;
   const int step = mp.dx * o.sx + mp.dk * o.sk;
   const bool interior = (x0 + X <= o.xlim) && (k0 + BK <= o.klim);
+  zm = 0u;
   if (interior) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const bool in = (e * NT + tid) < X * BK;
-      r[e] = in ? base[off0 + e * step] : 0.0;
+      r[e] = *(in ? base + off0 + e * step : o.p);
+      zm |= in ? (1u << e) : 0u;
     }
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int x = x0 + mp.x_t + e * mp.dx, k = k0 + mp.k_t + e * mp.dk;
       const bool in = (e * NT + tid) < X * BK && x < o.xlim && k < o.klim;
-      r[e] = in ? base[off0 + e * step] : 0.0;
+      r[e] = *(in ? base + off0 + e * step : o.p);
+      zm |= in ? (1u << e) : 0u;
     }
   }
 }
 
-// Registers -> swizzled k-major LDS tile (same element mapping as load_stage).
+// Registers -> swizzled k-major LDS tile (same element mapping as load_stage);
+// elements outside the operand (zm bit clear) are stored as zero.
 template <int X, int BK, int E, int NT, int LD>
-__device__ inline void store_stage(bool xfast, const double (&r)[E], double* s, int tid) {
+__device__ inline void store_stage(bool xfast, const double (&r)[E], unsigned zm, double* s,
+                                   int tid) {
   const StageMap<X, BK, NT> mp(xfast, tid);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    if ((e * NT + tid) < X * BK) s[lds_idx<BK>(mp.k_t + e * mp.dk, mp.x_t + e * mp.dx, LD)] = r[e];
+    if ((e * NT + tid) < X * BK)
+      s[lds_idx<BK>(mp.k_t + e * mp.dk, mp.x_t + e * mp.dx, LD)] = ((zm >> e) & 1u) ? r[e] : 0.0;
   }
 }
 
@@ -197,17 +207,18 @@ __device__ inline void k_loop(int nsteps, int m0, int n0, Ops ops, d4v (&acc)[T:
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % T::WM, wn = wave / T::WM;
   double ra[T::EA], rb[T::EB];
+  unsigned za = 0u, zb = 0u;
   Opnd A, B;
   int k0;
   if (nsteps <= 0) return;
   auto fetch = [&](int s) {
     ops(s, A, B, k0);
-    load_stage<T::BM, T::BK, T::EA, T::NT>(A, m0, k0, ra, tid);
-    load_stage<T::BN, T::BK, T::EB, T::NT>(B, n0, k0, rb, tid);
+    load_stage<T::BM, T::BK, T::EA, T::NT>(A, m0, k0, ra, za, tid);
+    load_stage<T::BN, T::BK, T::EB, T::NT>(B, n0, k0, rb, zb, tid);
   };
   fetch(0);
-  store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(A.xfast, ra, lds, tid);
-  store_stage<T::BN, T::BK, T::EB, T::NT, T::LDB>(B.xfast, rb, lds + T::BK * T::LDA, tid);
+  store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(A.xfast, ra, za, lds, tid);
+  store_stage<T::BN, T::BK, T::EB, T::NT, T::LDB>(B.xfast, rb, zb, lds + T::BK * T::LDA, tid);
   __syncthreads();
   for (int s = 0; s < nsteps; ++s) {
     double* cur = lds + (s & 1) * T::STAGE;
@@ -216,8 +227,8 @@ __device__ inline void k_loop(int nsteps, int m0, int n0, Ops ops, d4v (&acc)[T:
     if (more) fetch(s + 1);
     mfma_stage<T>(cur, cur + T::BK * T::LDA, acc, lane, wm, wn);
     if (more) {
-      store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(A.xfast, ra, nxt, tid);
-      store_stage<T::BN, T::BK, T::EB, T::NT, T::LDB>(B.xfast, rb, nxt + T::BK * T::LDA, tid);
+      store_stage<T::BM, T::BK, T::EA, T::NT, T::LDA>(A.xfast, ra, za, nxt, tid);
+      store_stage<T::BN, T::BK, T::EB, T::NT, T::LDB>(B.xfast, rb, zb, nxt + T::BK * T::LDA, tid);
     }
     __syncthreads();
   }

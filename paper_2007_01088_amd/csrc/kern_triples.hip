@@ -118,6 +118,7 @@ __device__ __forceinline__ void wbuild_body(const double* __restrict__ t2,
   double ra[T::EA], rb[T::EB];
   int lseg = 0, lk0 = 0;  // the next stage to load
   int ks_load = 0;         // MFMA k-steps of 4 that hold data in the stage just loaded
+  bool zin = true;         // this lane's k of the stage just loaded lies inside its segment
   auto fetch = [&]() {
     const char *pa, *pb;
     if (lseg == 0) { pa = A0; pb = B0; }
@@ -127,26 +128,23 @@ __device__ __forceinline__ void wbuild_body(const double* __restrict__ t2,
     const int ld = (lseg & 1) ? no : nv;
     const BufRsrc sa = buf_rsrc(pa + lk0 * 8), sb = buf_rsrc(pb + lk0 * 8);
     const bool in = lk0 + kt < ld;                    // the segment's last stage may be partial
-    const int kc = in ? kt : ld - 1 - lk0;           // k past K reads a valid element, then 0
+    const int kc = in ? kt : ld - 1 - lk0;           // k past K reads a valid element
+    // The zero of k past K is applied when the stage is stored: a select here would
+    // wait for the loads before the current stage's MFMAs instead of after them.
 #pragma unroll
-    for (int e = 0; e < T::EA; ++e) {
-      const double v = buf_load_f64(sa, (unsigned)(rowa[e] * ld + kc) * 8u);
-      ra[e] = in ? v : 0.0;
-    }
+    for (int e = 0; e < T::EA; ++e) ra[e] = buf_load_f64(sa, (unsigned)(rowa[e] * ld + kc) * 8u);
 #pragma unroll
-    for (int e = 0; e < T::EB; ++e) {
-      const double v = buf_load_f64(sb, (unsigned)(rowb[e] * ld + kc) * 8u);
-      rb[e] = in ? v : 0.0;
-    }
+    for (int e = 0; e < T::EB; ++e) rb[e] = buf_load_f64(sb, (unsigned)(rowb[e] * ld + kc) * 8u);
+    zin = in;
     ks_load = min(T::BK, ld - lk0 + 3) / 4;  // a segment's last stage may be part zeros
     lk0 += T::BK;
     if (lk0 >= ld) { lk0 = 0; ++lseg; }
   };
   auto store = [&](double* st) {
 #pragma unroll
-    for (int e = 0; e < T::EA; ++e) st[lda + e * RP] = ra[e];
+    for (int e = 0; e < T::EA; ++e) st[lda + e * RP] = zin ? ra[e] : 0.0;
 #pragma unroll
-    for (int e = 0; e < T::EB; ++e) st[ldb + e * RP] = rb[e];
+    for (int e = 0; e < T::EB; ++e) st[ldb + e * RP] = zin ? rb[e] : 0.0;
   };
   d4v acc[T::FM][T::FN];
   zero_acc<T>(acc);
@@ -811,30 +809,33 @@ __device__ __forceinline__ void omega_body(const E* __restrict__ cubes, int nslo
   }
   const unsigned ask8 = (unsigned)ask * ES;
   E ra[T::EA], rb[T::EB];
+  // which loaded elements lie inside K (bit e for A, one flag for B); the zero of the
+  // others is applied at the LDS store, after the current stage's MFMAs, so that the
+  // loads stay in flight during them
+  unsigned amask = ~0u;
+  bool inb = true;
   auto fetch = [&](int s) {
     const int k0 = s * T::BK;
     const BufRsrc sa = buf_rsrc(A0 + (int64_t)k0 * ask), sb = buf_rsrc(B0 + k0);
     const int kl = K - 1 - k0;  // last valid k of this stage (only the last stage is partial)
+    amask = 0u;
 #pragma unroll
     for (int e = 0; e < T::EA; ++e) {
       const bool in = ak[e] <= kl;
-      const int kc = in ? ak[e] : kl;
-      const E v = M::load(sa, aoff[e] + (unsigned)kc * ask8);
-      ra[e] = in ? v : E(0);
+      const int kc = in ? ak[e] : kl;  // k past K reads a valid element
+      ra[e] = M::load(sa, aoff[e] + (unsigned)kc * ask8);
+      amask |= in ? (1u << e) : 0u;
     }
-    const bool inb = kt <= kl;
+    inb = kt <= kl;
     const unsigned kb = (unsigned)(inb ? kt : kl) * ES;
 #pragma unroll
-    for (int e = 0; e < T::EB; ++e) {
-      const E v = M::load(sb, boff[e] + kb);
-      rb[e] = inb ? v : E(0);
-    }
+    for (int e = 0; e < T::EB; ++e) rb[e] = M::load(sb, boff[e] + kb);
   };
   auto store = [&](E* st) {
 #pragma unroll
-    for (int e = 0; e < T::EA; ++e) st[alds[e]] = ra[e];
+    for (int e = 0; e < T::EA; ++e) st[alds[e]] = ((amask >> e) & 1u) ? ra[e] : E(0);
 #pragma unroll
-    for (int e = 0; e < T::EB; ++e) st[blds[e]] = rb[e];
+    for (int e = 0; e < T::EB; ++e) st[blds[e]] = inb ? rb[e] : E(0);
   };
   typename M::V acc[T::FM][T::FN];
 #pragma unroll
