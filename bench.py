@@ -102,7 +102,14 @@ def cpu_baseline(no: int, nv: int, nchol: int, budget_s: float) -> dict:
     total_w = sum(weight(t) for t in alltri)
     t_call = t_prep + t_loop * total_w / done_w
     nominal = O.nominal_flops(no, nv)
+    cpu = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": nominal / t_call / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu, "host_cpus": os.cpu_count(),
             "sample": f"{n} of {len(alltri)} unordered triples (seeded) plus the full integral "
                       f"preparation, {t_prep + t_loop:.1f} s measured, extrapolated to one call "
                       f"({t_call:.1f} s) by per-triple cost weights",

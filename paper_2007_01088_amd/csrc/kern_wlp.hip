@@ -128,26 +128,23 @@ constexpr int LWM = 4, LWN = 2, LFM = 2, LFN = 4;
 constexpr int LNT = 64 * LWM * LWN;
 constexpr int LBM = 16 * LWM * LFM, LBN = 16 * LWN * LFN;  // 128 x 128
 
-// Engine traits.  An LDS tile is row-major [x][k] with rows of BK elements plus
-// 16 bytes of padding (rows of 80 or 144 bytes: the 16 rows read by one
-// fragment load spread over the banks).  Tiles load as 16-byte chunks, CH per
-// thread per piece per operand.
-// FLUSH: each LDS stage (32 k) is accumulated in FP32 from zero and then added
-// into an FP64 accumulator, so the FP32 rounding of the MFMA outputs applies to
-// 32-term partial sums rather than to the running sum over the whole K range.
-// Used where the split is fine enough for that rounding to dominate the error
-// (FP32 and the 3-piece BF16 split); the 2-piece split is limited by its
-// operands and keeps one FP32 accumulator per term.
+// Engine traits.  FLUSH: each LDS stage (32 k) is accumulated in FP32 from zero
+// and then added into an FP64 accumulator, so the FP32 rounding of the MFMA
+// outputs applies to 32-term partial sums rather than to the running sum over
+// the whole K range.  Used where the split is fine enough for that rounding to
+// dominate the error (FP32 and the 3-piece BF16 split); the 2-piece split is
+// limited by its operands and keeps one FP32 accumulator per term.
+// MINW: waves per SIMD the W kernel is built for (4: two workgroups per CU).
 struct EngF32 {
   static constexpr int BK = 32, P = 1, NPROD = 1, ESZ = 4;
-  static constexpr int ROWB = BK * ESZ + 16;  // bytes per LDS row
   static constexpr bool FLUSH = true;
+  static constexpr int MINW = 4;
 };
 template <int P_>
 struct EngBF16 {
   static constexpr int BK = 32, P = P_, NPROD = (P_ == 2 ? 3 : 6), ESZ = 2;
-  static constexpr int ROWB = BK * ESZ + 16;
   static constexpr bool FLUSH = (P_ == 3);
+  static constexpr int MINW = (P_ == 2 ? 4 : 2);
 };
 
 // the piece pairs of the split products
@@ -161,24 +158,203 @@ __device__ inline void prod_pair(int P, int t, int& pa, int& pb) {
   }
 }
 
-struct LpSeg {
-  const char* a;  // piece 0 base of the A rows (row x at a + x * a_rs bytes)
-  const char* b;
-  int64_t a_rs, b_rs;   // row strides in bytes
-  int64_t a_ps, b_ps;   // piece strides in bytes
-  int ksteps;           // K steps of BK
-  int kreal;            // K before padding (the products past it are zero)
+// ---------------------------------------------------------------------------
+// The tile engine.  Operands are row-major (row, k) with k contiguous and
+// zero-padded to a multiple of 32, in P pieces.  A stage holds 32 k of the
+// 128 A rows and 128 B rows of every piece.  It goes from global memory to LDS
+// directly: a buffer load with the LDS flag writes 16 bytes per lane at
+// consecutive LDS addresses (1 KB per instruction), so the tile needs no
+// staging registers and no LDS stores.  Each LDS row holds the RB bytes of one
+// row and one stage as 16-byte chunks, XOR-swizzled by the row (lp_chunk) so
+// that the 16 rows of one fragment read fall in different banks; the lane that
+// fills LDS slot s loads the global chunk that the swizzle puts there.  Two
+// stage buffers, one barrier per stage: the loads of stage s + 1 are issued
+// before the MFMAs of stage s and waited for after them.
+// ---------------------------------------------------------------------------
+template <class E>
+struct LpTile {
+  static constexpr int P = E::P, ESZ = E::ESZ;
+  static constexpr int RB = E::BK * ESZ;         // bytes of one row in one stage
+  static constexpr int CPR = RB / 16;            // 16-byte chunks per row (8 or 4)
+  static constexpr int TILEB = LBM * RB;         // one operand piece of one stage
+  static constexpr int NI = TILEB / (LNT * 16);  // loads per lane per operand piece
+  static constexpr int STAGEB = 2 * P * TILEB;
+  static_assert(LBM == LBN && NI * LNT * 16 == TILEB, "tile shape");
 };
+
+// LDS chunk of logical chunk c of row `row` (an involution in c)
+template <class E>
+__device__ inline int lp_chunk(int row, int c) {
+  if constexpr (LpTile<E>::CPR == 8) return c ^ ((row >> 1) & 7);
+  else return c ^ ((row >> 2) & 3);
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// One K segment of a product: piece-0 operand origins (row 0, k = 0), piece
+// strides and row strides in bytes, and its number of stages.
+struct LpSeg {
+  const char *a, *b;
+  int64_t aps, bps;
+  unsigned ars, brs;
+  int nst;
+};
+
+// The rows this lane loads: for load i of an operand piece, LDS slot
+// s = (8 i + wave) 64 + lane holds row s / CPR and the swizzled chunk of s % CPR.
+template <class E>
+struct LpLanes {
+  int row[LpTile<E>::NI];
+  unsigned cb[LpTile<E>::NI];  // byte offset of the chunk within the row's stage
+  __device__ LpLanes(int wave, int lane) {
+    typedef LpTile<E> L;
+#pragma unroll
+    for (int i = 0; i < L::NI; ++i) {
+      const int s = (8 * i + wave) * 64 + lane;
+      row[i] = s / L::CPR;
+      cb[i] = (unsigned)lp_chunk<E>(row[i], s % L::CPR) * 16u;
+    }
+  }
+};
+
+// Issue the direct loads of stage `st` of segment `sg` into the stage buffer
+// `buf`; ar / br: this lane's A and B row indices (already mapped to operand rows)
+template <class E>
+__device__ __forceinline__ void lp_load_stage(const LpSeg& sg, int st, char* buf,
+                                              const unsigned* cb, const int* ar, const int* br,
+                                              int wave) {
+  typedef LpTile<E> L;
+  const int64_t ko = (int64_t)st * L::RB;
+#pragma unroll
+  for (int pc = 0; pc < L::P; ++pc) {
+    const BufRsrc ra = buf_rsrc(sg.a + pc * sg.aps + ko), rb = buf_rsrc(sg.b + pc * sg.bps + ko);
+#pragma unroll
+    for (int i = 0; i < L::NI; ++i) {
+      char* la = buf + pc * L::TILEB + (8 * i + wave) * 1024;
+      char* lb = buf + (L::P + pc) * L::TILEB + (8 * i + wave) * 1024;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)la, 16,
+                                               (unsigned)ar[i] * sg.ars + cb[i], 0, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr_t)lb, 16,
+                                               (unsigned)br[i] * sg.brs + cb[i], 0, 0, 0);
+    }
+  }
+}
+
+// The loads of this lane have reached LDS, then every lane's have.
+__device__ __forceinline__ void lp_stage_ready() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+}
+
+// acc += A B over one LDS stage.  BF16: one k = 32 MFMA per product; lane
+// supplies A[m = l%16][k = 8 (l/16) .. + 7] (chunk l/16 of its row).  FP32: the
+// lane reads chunk 4 h + l/16 (four consecutive k) of its row and supplies its
+// element j to the k-step (h, j) of the 16x16x4 MFMA; A and B use the same k
+// assignment, so the eight k-steps cover the stage's 32 k once each.
+template <class E>
+__device__ __forceinline__ void lp_mfma_stage(const char* buf, f4v (&acc)[LFM][LFN], int lane,
+                                              int wm, int wn) {
+  typedef LpTile<E> L;
+  const int g = lane >> 4, r16 = lane & 15;
+  if constexpr (E::P == 1) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f4v a[LFM];
+#pragma unroll
+      for (int fm = 0; fm < LFM; ++fm) {
+        const int row = (wm * LFM + fm) * 16 + r16;
+        a[fm] = *(const f4v*)(buf + row * L::RB + lp_chunk<E>(row, 4 * h + g) * 16);
+      }
+      // one B fragment at a time (registers: the FP64 accumulator of FLUSH is large)
+#pragma unroll
+      for (int fn = 0; fn < LFN; ++fn) {
+        const int row = (wn * LFN + fn) * 16 + r16;
+        const f4v b = *(const f4v*)(buf + L::TILEB + row * L::RB + lp_chunk<E>(row, 4 * h + g) * 16);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int fm = 0; fm < LFM; ++fm)
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm][j], b[j], acc[fm][fn], 0, 0, 0);
+      }
+    }
+  } else {
+    bf8v a[L::P][LFM], b[L::P][LFN];
+#pragma unroll
+    for (int pc = 0; pc < L::P; ++pc) {
+#pragma unroll
+      for (int fm = 0; fm < LFM; ++fm) {
+        const int row = (wm * LFM + fm) * 16 + r16;
+        a[pc][fm] = *(const bf8v*)(buf + pc * L::TILEB + row * L::RB + lp_chunk<E>(row, g) * 16);
+      }
+#pragma unroll
+      for (int fn = 0; fn < LFN; ++fn) {
+        const int row = (wn * LFN + fn) * 16 + r16;
+        b[pc][fn] = *(const bf8v*)(buf + (L::P + pc) * L::TILEB + row * L::RB +
+                                   lp_chunk<E>(row, g) * 16);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < E::NPROD; ++t) {
+      int pa, pb;
+      prod_pair(L::P, t, pa, pb);
+#pragma unroll
+      for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < LFN; ++fn)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa][fm], b[pb][fn], acc[fm][fn], 0, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void lp_zero(f4v (&acc)[LFM][LFN]) {
+#pragma unroll
+  for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < LFN; ++fn) acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+}
+__device__ __forceinline__ void lp_flush(f4v (&acc)[LFM][LFN], d4v (&accd)[LFM][LFN]) {
+#pragma unroll
+  for (int fm = 0; fm < LFM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < LFN; ++fn) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accd[fm][fn][r] += (double)acc[fm][fn][r];
+      acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// W build in low precision
+// ---------------------------------------------------------------------------
+// The stages of one K segment `cur` into acc (with FLUSH into accd); the last
+// one prefetches the first stage of `nxt` when has_next.  sidx counts the
+// stages of the plane (it selects the stage buffer).  The segments are passed
+// by value and chosen statically by the caller, so that they stay in registers.
+template <class E>
+__device__ __forceinline__ void wlp_seg(const LpSeg cur, const LpSeg nxt, bool has_next, int& sidx,
+                                        char* lds, const unsigned* cb, const int* ar,
+                                        const int* br, int wave, int lane, int wm, int wn,
+                                        f4v (&acc)[LFM][LFN], d4v (&accd)[LFM][LFN]) {
+  typedef LpTile<E> L;
+  for (int st = 0; st < cur.nst; ++st, ++sidx) {
+    char* cbuf = lds + (sidx & 1) * L::STAGEB;
+    char* nbuf = lds + ((sidx + 1) & 1) * L::STAGEB;
+    if (st + 1 < cur.nst) lp_load_stage<E>(cur, st + 1, nbuf, cb, ar, br, wave);
+    else if (has_next) lp_load_stage<E>(nxt, 0, nbuf, cb, ar, br, wave);
+    lp_mfma_stage<E>(cbuf, acc, lane, wm, wn);
+    if constexpr (E::FLUSH) lp_flush(acc, accd);
+    lp_stage_ready();
+  }
+}
 
 template <class E>
 __device__ __forceinline__ void wbuild_lp_body(
     const char* __restrict__ t2L, const char* __restrict__ t2NL, const char* __restrict__ GwTL,
     const char* __restrict__ GoTL, const int* __restrict__ tri, double* __restrict__ cubes, int no,
     int nv, int tiles_m, int tiles_n, int all_terms, int bx, int by, int bz) {
-  constexpr int BK = E::BK, P = E::P, ESZ = E::ESZ, ROWB = E::ROWB;
-  constexpr int TILEB = LBM * ROWB;  // one operand tile, one piece (LBM == LBN)
-  constexpr int STAGEB = 2 * P * TILEB;
-  __shared__ __attribute__((aligned(16))) char lds[2 * STAGEB];
+  typedef LpTile<E> L;
+  constexpr int ESZ = E::ESZ;
+  __shared__ __attribute__((aligned(16))) char lds[2 * L::STAGEB];
   const int tpp = tiles_m * tiles_n;
   const int y = bx / tpp;
   const int tile = bx % tpp;
@@ -196,163 +372,53 @@ __device__ __forceinline__ void wbuild_lp_body(
   else { p1 = i; q1 = k; r1 = j; p2 = j; q2 = k; r2 = i; }
 
   const int64_t dk = kpad(nv), lk = kpad(no), v = nv, o = no;
-  // piece strides (elements) of the four arrays
-  const int64_t ps_t2 = o * o * v * dk, ps_t2N = o * v * v * lk, ps_Gw = o * v * v * dk,
-                ps_Go = o * o * v * lk;
+  // piece strides (bytes) of the four arrays
+  const int64_t ps_t2 = o * o * v * dk * ESZ, ps_t2N = o * v * v * lk * ESZ,
+                ps_Gw = o * v * v * dk * ESZ, ps_Go = o * o * v * lk * ESZ;
+  const unsigned rv = (unsigned)(dk * ESZ), ro = (unsigned)(lk * ESZ);
   // segments: term 1 vv, term 1 oo, term 2 vv, term 2 oo (rows m for A, n for B)
-  const LpSeg seg0 = {t2L + ((p1 * o + q1) * v) * dk * ESZ, GwTL + ((r1 * v + y) * v) * dk * ESZ,
-            dk * ESZ, dk * ESZ, ps_t2 * ESZ, ps_Gw * ESZ, (int)(dk / BK), nv};
-  const LpSeg seg1 = {t2NL + ((p1 * v + y) * v) * lk * ESZ, GoTL + ((q1 * o + r1) * v) * lk * ESZ,
-            lk * ESZ, lk * ESZ, ps_t2N * ESZ, ps_Go * ESZ, (int)(lk / BK), no};
-  const LpSeg seg2 = {GwTL + ((r2 * v + y) * v) * dk * ESZ, t2L + ((p2 * o + q2) * v) * dk * ESZ,
-            dk * ESZ, dk * ESZ, ps_Gw * ESZ, ps_t2 * ESZ, (int)(dk / BK), nv};
-  const LpSeg seg3 = {GoTL + ((q2 * o + r2) * v) * lk * ESZ, t2NL + ((p2 * v + y) * v) * lk * ESZ,
-            lk * ESZ, lk * ESZ, ps_Go * ESZ, ps_t2N * ESZ, (int)(lk / BK), no};
+  // segments: term 1 vv, term 1 oo, term 2 vv, term 2 oo (rows m for A, n for B)
+  const LpSeg sg0 = {t2L + ((p1 * o + q1) * v) * dk * ESZ, GwTL + ((r1 * v + y) * v) * dk * ESZ,
+                     ps_t2, ps_Gw, rv, rv, (int)(dk / 32)};
+  const LpSeg sg1 = {t2NL + ((p1 * v + y) * v) * lk * ESZ, GoTL + ((q1 * o + r1) * v) * lk * ESZ,
+                     ps_t2N, ps_Go, ro, ro, (int)(lk / 32)};
+  const LpSeg sg2 = {GwTL + ((r2 * v + y) * v) * dk * ESZ, t2L + ((p2 * o + q2) * v) * dk * ESZ,
+                     ps_Gw, ps_t2, rv, rv, (int)(dk / 32)};
+  const LpSeg sg3 = {GoTL + ((q2 * o + r2) * v) * lk * ESZ, t2NL + ((p2 * v + y) * v) * lk * ESZ,
+                     ps_Go, ps_t2N, ro, ro, (int)(lk / 32)};
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave % LWM, wn = wave / LWM;
-  // this thread's 16-byte chunks of a tile: rows cr + c * RPP, chunk cc within the row
-  constexpr int CPR = BK * ESZ / 16;       // chunks per row
-  constexpr int RPP = LNT / CPR;           // rows per pass of the workgroup
-  constexpr int CH = LBM / RPP;            // chunks per thread
-  const int cr = tid / CPR, cc = tid % CPR;
+  const LpLanes<E> ln(wave, lane);
+  // rows past nv repeat row nv - 1 (their outputs are never stored)
+  int ar[L::NI], br[L::NI];
+#pragma unroll
+  for (int e = 0; e < L::NI; ++e) {
+    ar[e] = min(m0 + ln.row[e], nv - 1);
+    br[e] = min(n0 + ln.row[e], nv - 1);
+  }
 
-  u4v ra[P][CH], rb[P][CH];  // one stage of both operands in flight
-  // one term: acc[m][n] = sum over K of segment sa (K = nv) then sb (K = no); with
-  // FLUSH, acc holds one stage and the term is added into accd stage by stage
-  auto run_term = [&](const LpSeg& sa, const LpSeg& sb, f4v (&acc)[LFM][LFN],
-                      d4v (&accd)[LFM][LFN]) __attribute__((always_inline)) {
-#pragma unroll
-    for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-      for (int fn = 0; fn < LFN; ++fn) acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
-    const int nsteps = sa.ksteps + sb.ksteps;
-    auto load = [&](int s) __attribute__((always_inline)) {
-      const bool first = s < sa.ksteps;
-      const char* ga = first ? sa.a : sb.a;
-      const char* gb = first ? sa.b : sb.b;
-      const int64_t ars = first ? sa.a_rs : sb.a_rs, brs = first ? sa.b_rs : sb.b_rs;
-      const int64_t aps = first ? sa.a_ps : sb.a_ps, bps = first ? sa.b_ps : sb.b_ps;
-      const int ks = first ? s : s - sa.ksteps;
-      const int64_t koff = (int64_t)ks * BK * ESZ + cc * 16;
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int row = cr + c * RPP;
-        // rows past nv repeat row nv - 1 (their outputs are never stored)
-        const char* pa = ga + (int64_t)min(m0 + row, nv - 1) * ars + koff;
-        const char* pb = gb + (int64_t)min(n0 + row, nv - 1) * brs + koff;
-#pragma unroll
-        for (int pc = 0; pc < P; ++pc) {
-          ra[pc][c] = *(const u4v*)(pa + pc * aps);
-          rb[pc][c] = *(const u4v*)(pb + pc * bps);
-        }
-      }
-    };
-    auto store = [&](char* st) __attribute__((always_inline)) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int row = cr + c * RPP;
-#pragma unroll
-        for (int pc = 0; pc < P; ++pc) {
-          *(u4v*)(st + pc * TILEB + row * ROWB + cc * 16) = ra[pc][c];
-          *(u4v*)(st + (P + pc) * TILEB + row * ROWB + cc * 16) = rb[pc][c];
-        }
-      }
-    };
-    load(0);
-    store(lds);
-    __syncthreads();
-    for (int s = 0; s < nsteps; ++s) {
-      char* cur = lds + (s & 1) * STAGEB;
-      char* nxt = lds + ((s + 1) & 1) * STAGEB;
-      const bool more = s + 1 < nsteps;
-      if (more) load(s + 1);
-      if constexpr (P == 1) {
-        // FP32: k=4 MFMA steps; lane supplies A[m = l%16][k = l/16], B[k = l/16][n = l%16].
-        // The k-steps past the segment's real K hold zero padding and are skipped.
-        const bool first = s < sa.ksteps;
-        const int k0 = (first ? s : s - sa.ksteps) * BK;
-        const int ks = min(BK, (first ? sa.kreal : sb.kreal) - k0 + 3) / 4;
-#pragma unroll
-        for (int kk = 0; kk < BK / 4; ++kk) {
-          if (kk >= ks) break;
-          const int kc = kk * 4 + (lane >> 4);
-          float a[LFM], b[LFN];
-#pragma unroll
-          for (int fm = 0; fm < LFM; ++fm)
-            a[fm] = *(const float*)(cur + ((wm * LFM + fm) * 16 + (lane & 15)) * ROWB + kc * 4);
-#pragma unroll
-          for (int fn = 0; fn < LFN; ++fn)
-            b[fn] = *(const float*)(cur + TILEB + ((wn * LFN + fn) * 16 + (lane & 15)) * ROWB + kc * 4);
-#pragma unroll
-          for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-            for (int fn = 0; fn < LFN; ++fn)
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
-        }
-      } else {
-        // BF16: one k=32 step per product; lane supplies A[m = l%16][k = 8(l/16)..+7]
-        const int kb = (lane >> 4) * 16;  // byte offset of the 8 k values
-        bf8v a[P][LFM], b[P][LFN];
-#pragma unroll
-        for (int pc = 0; pc < P; ++pc) {
-#pragma unroll
-          for (int fm = 0; fm < LFM; ++fm)
-            a[pc][fm] = *(const bf8v*)(cur + pc * TILEB + ((wm * LFM + fm) * 16 + (lane & 15)) * ROWB + kb);
-#pragma unroll
-          for (int fn = 0; fn < LFN; ++fn)
-            b[pc][fn] = *(const bf8v*)(cur + (P + pc) * TILEB + ((wn * LFN + fn) * 16 + (lane & 15)) * ROWB + kb);
-        }
-#pragma unroll
-        for (int t = 0; t < E::NPROD; ++t) {
-          int pa, pb;
-          prod_pair(P, t, pa, pb);
-#pragma unroll
-          for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-            for (int fn = 0; fn < LFN; ++fn)
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa][fm], b[pb][fn], acc[fm][fn], 0, 0, 0);
-        }
-      }
-      if constexpr (E::FLUSH) {
-#pragma unroll
-        for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-          for (int fn = 0; fn < LFN; ++fn) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) accd[fm][fn][r] += (double)acc[fm][fn][r];
-            acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
-          }
-      }
-      if (more) store(nxt);
-      __syncthreads();
-    }
-  };
-
-  // term 1 (and term 2 when the plane has two), each accumulated in FP32; the
-  // plane value is their FP64 sum (exact FP32 values, one FP64 rounding)
+  // term 1 (and term 2 when the plane has two), each accumulated in FP32 (with
+  // FLUSH stage by stage into FP64); the plane value is their FP64 sum
   f4v acc1[LFM][LFN], acc2[LFM][LFN];
   d4v accd[LFM][LFN];
+  lp_zero(acc1);
+  lp_zero(acc2);
 #pragma unroll
   for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
     for (int fn = 0; fn < LFN; ++fn) accd[fm][fn] = d4v{0.0, 0.0, 0.0, 0.0};
-  run_term(seg0, seg1, acc1, accd);
+  int sidx = 0;
+  lp_load_stage<E>(sg0, 0, lds, ln.cb, ar, br, wave);
+  lp_stage_ready();
+  wlp_seg<E>(sg0, sg1, true, sidx, lds, ln.cb, ar, br, wave, lane, wm, wn, acc1, accd);
+  wlp_seg<E>(sg1, sg2, two, sidx, lds, ln.cb, ar, br, wave, lane, wm, wn, acc1, accd);
   if (two) {
-    run_term(seg2, seg3, E::FLUSH ? acc1 : acc2, accd);
-  }
-  if (E::FLUSH || !two) {
-#pragma unroll
-    for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-      for (int fn = 0; fn < LFN; ++fn) acc2[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
-  }
-  if constexpr (E::FLUSH) {
-#pragma unroll
-    for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-      for (int fn = 0; fn < LFN; ++fn) acc1[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
+    f4v (&acc)[LFM][LFN] = E::FLUSH ? acc1 : acc2;
+    wlp_seg<E>(sg2, sg3, true, sidx, lds, ln.cb, ar, br, wave, lane, wm, wn, acc, accd);
+    wlp_seg<E>(sg3, sg3, false, sidx, lds, ln.cb, ar, br, wave, lane, wm, wn, acc, accd);
   }
 
   // the FP32/BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
@@ -372,7 +438,7 @@ __device__ __forceinline__ void wbuild_lp_body(
 }
 
 template <class E>
-__global__ __launch_bounds__(LNT) void k_wbuild_lp(
+__global__ __launch_bounds__(LNT, E::MINW) void k_wbuild_lp(
     const char* __restrict__ t2L, const char* __restrict__ t2NL, const char* __restrict__ GwTL,
     const char* __restrict__ GoTL, const int* __restrict__ tri, double* __restrict__ cubes, int no,
     int nv, int tiles_m, int tiles_n, int all_terms) {
@@ -393,8 +459,7 @@ __global__ __launch_bounds__(LNT) void k_wbuild_lp(
 //   GL[piece][r][n'][kk]: Gbc (or Gcb for pi 2, 4) rows, n' = n for n < nv and
 //     nv + q (the Omega1 row) for n >= nv.
 // Each chunk sums in FP32 on the MFMA (with FLUSH, stage by stage into FP64);
-// k_reduce sums the chunks in FP64.  The tile, LDS layout and loads are those of
-// k_wbuild_lp.
+// k_reduce sums the chunks in FP64.  The tile engine is that of k_wbuild_lp.
 template <class E>
 __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
                                                   const char* __restrict__ GbcL,
@@ -402,10 +467,9 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
                                                   const int* __restrict__ tri,
                                                   double* __restrict__ Pvv, int no, int nv,
                                                   int nchunks, int tiles_n) {
-  constexpr int BK = E::BK, P = E::P, ESZ = E::ESZ, ROWB = E::ROWB;
-  constexpr int TILEB = LBM * ROWB;
-  constexpr int STAGEB = 2 * P * TILEB;
-  __shared__ __attribute__((aligned(16))) char lds[2 * STAGEB];
+  typedef LpTile<E> L;
+  constexpr int ESZ = E::ESZ;
+  __shared__ __attribute__((aligned(16))) char lds[2 * L::STAGEB];
   const int pi = blockIdx.y, z = blockIdx.z;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   if (!perm_active(tri_kind(i, j, k), pi)) return;
@@ -414,7 +478,7 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
   const int ch = blockIdx.x % nchunks, tile = blockIdx.x / nchunks;
   const int m0 = (tile / tiles_n) * LBM, n0 = (tile % tiles_n) * LBN;
   const int64_t Kp = kpad32((int64_t)nv * nv);
-  const int S = (int)(Kp / BK);
+  const int S = (int)(Kp / E::BK);
   const int s0 = (int)((int64_t)ch * S / nchunks), s1 = (int)((int64_t)(ch + 1) * S / nchunks);
   if (s0 >= s1) return;
   const int view = pi == 0 ? 0 : pi == 3 ? 3 : (pi == 1 || pi == 4) ? 1 : 2;
@@ -422,97 +486,39 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
   const int64_t rs = Kp * ESZ;                                   // row stride, bytes
   const int64_t y_ps = (int64_t)nv * rs;                         // piece stride of a view
   const int64_t g_ps = (int64_t)no * (nv + no) * rs;             // piece stride of GL
-  const char* ya = YL + ((int64_t)z * 4 + view) * P * y_ps;
-  const char* gb = (cb ? GcbL : GbcL) + (int64_t)r * (nv + no) * rs;
+  const LpSeg sg = {YL + ((int64_t)z * 4 + view) * E::P * y_ps,
+                    (cb ? GcbL : GbcL) + (int64_t)r * (nv + no) * rs, y_ps, g_ps,
+                    (unsigned)rs, (unsigned)rs, S};
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave % LWM, wn = wave / LWM;
-  constexpr int CPR = BK * ESZ / 16;  // 16-byte chunks per row
-  constexpr int RPP = LNT / CPR;      // rows per pass of the workgroup
-  constexpr int CH = LBM / RPP;       // chunks per thread
-  const int cr = tid / CPR, cc = tid % CPR;
-  int64_t arow[CH], brow[CH];  // byte offsets of this thread's rows
+  const LpLanes<E> ln(wave, lane);
+  // rows past nv repeat row nv - 1 (outputs never stored); B rows n >= nv read the
+  // Omega1 row nv + q
+  int ar[L::NI], br[L::NI];
 #pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    const int row = cr + c * RPP;
-    arow[c] = (int64_t)min(m0 + row, nv - 1) * rs;  // rows past nv: outputs never stored
-    const int n = n0 + row;
-    brow[c] = (int64_t)(n < nv ? n : nv + q) * rs;
+  for (int e = 0; e < L::NI; ++e) {
+    ar[e] = min(m0 + ln.row[e], nv - 1);
+    const int n = n0 + ln.row[e];
+    br[e] = n < nv ? n : nv + q;
   }
-  u4v ra[P][CH], rb[P][CH];
-  auto load = [&](int s) __attribute__((always_inline)) {
-    const int64_t koff = (int64_t)s * BK * ESZ + cc * 16;
-#pragma unroll
-    for (int c = 0; c < CH; ++c)
-#pragma unroll
-      for (int pc = 0; pc < P; ++pc) {
-        ra[pc][c] = *(const u4v*)(ya + pc * y_ps + arow[c] + koff);
-        rb[pc][c] = *(const u4v*)(gb + pc * g_ps + brow[c] + koff);
-      }
-  };
-  auto store = [&](char* st) __attribute__((always_inline)) {
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int row = cr + c * RPP;
-#pragma unroll
-      for (int pc = 0; pc < P; ++pc) {
-        *(u4v*)(st + pc * TILEB + row * ROWB + cc * 16) = ra[pc][c];
-        *(u4v*)(st + (P + pc) * TILEB + row * ROWB + cc * 16) = rb[pc][c];
-      }
-    }
-  };
   f4v acc[LFM][LFN];
   d4v accd[LFM][LFN];  // FLUSH: each stage's FP32 sum added in FP64
+  lp_zero(acc);
 #pragma unroll
   for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
-    for (int fn = 0; fn < LFN; ++fn) {
-      acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
-      accd[fm][fn] = d4v{0.0, 0.0, 0.0, 0.0};
-    }
-  load(s0);
-  store(lds);
-  __syncthreads();
+    for (int fn = 0; fn < LFN; ++fn) accd[fm][fn] = d4v{0.0, 0.0, 0.0, 0.0};
+  lp_load_stage<E>(sg, s0, lds, ln.cb, ar, br, wave);
+  lp_stage_ready();
   for (int s = s0; s < s1; ++s) {
-    char* cur = lds + ((s - s0) & 1) * STAGEB;
-    char* nxt = lds + ((s - s0 + 1) & 1) * STAGEB;
-    const bool more = s + 1 < s1;
-    if (more) load(s + 1);
-    // one k=32 step per product; lane supplies A[m = l%16][k = 8(l/16)..+7]
-    const int kb = (lane >> 4) * 16;
-    bf8v a[P][LFM], b[P][LFN];
-#pragma unroll
-    for (int pc = 0; pc < P; ++pc) {
-#pragma unroll
-      for (int fm = 0; fm < LFM; ++fm)
-        a[pc][fm] = *(const bf8v*)(cur + pc * TILEB + ((wm * LFM + fm) * 16 + (lane & 15)) * ROWB + kb);
-#pragma unroll
-      for (int fn = 0; fn < LFN; ++fn)
-        b[pc][fn] = *(const bf8v*)(cur + (P + pc) * TILEB + ((wn * LFN + fn) * 16 + (lane & 15)) * ROWB + kb);
-    }
-#pragma unroll
-    for (int t = 0; t < E::NPROD; ++t) {
-      int pa, pb;
-      prod_pair(P, t, pa, pb);
-#pragma unroll
-      for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-        for (int fn = 0; fn < LFN; ++fn)
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa][fm], b[pb][fn], acc[fm][fn], 0, 0, 0);
-    }
-    if constexpr (E::FLUSH) {
-#pragma unroll
-      for (int fm = 0; fm < LFM; ++fm)
-#pragma unroll
-        for (int fn = 0; fn < LFN; ++fn) {
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) accd[fm][fn][rr] += (double)acc[fm][fn][rr];
-          acc[fm][fn] = f4v{0.f, 0.f, 0.f, 0.f};
-        }
-    }
-    if (more) store(nxt);
-    __syncthreads();
+    char* cur = lds + ((s - s0) & 1) * L::STAGEB;
+    if (s + 1 < s1) lp_load_stage<E>(sg, s + 1, lds + ((s - s0 + 1) & 1) * L::STAGEB, ln.cb, ar, br, wave);
+    lp_mfma_stage<E>(cur, acc, lane, wm, wn);
+    if constexpr (E::FLUSH) lp_flush(acc, accd);
+    lp_stage_ready();
   }
   // the BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
   const int NV1 = nv + 1;

@@ -1,7 +1,7 @@
 """Whole residual calls at the benchmark sizes against the CPU oracle, on an MI355X.
 
 At no=12, nv=120, nchol=400 the oracle evaluates the whole call (about 40 s on
-the host); the device call runs in the launch configuration the benchmark times
+the host), and Algorithm 2 over every triple (about a minute); the device call runs in the launch configuration the benchmark times
 (the default plan: batches dealt round-robin over two streams).  The FP64 call
 is compared element by element at the FP64 bar, each low-precision form per
 result at its bound (test_gpu_mixed.py states the bounds and their derivation).
@@ -104,6 +104,32 @@ def test_mixed_all_whole_call_medium(medium, name):
     bd = bound_all(name, 120)
     say(f"whole call mixed-all {name}: rel err Omega1 {e1:.3e} Omega2 {e2:.3e} (bound {bd:.1e})")
     assert e1 <= bd and e2 <= bd, (name, e1, e2)
+
+
+def test_jacobian_prep_whole_call_medium(medium):
+    """Algorithm 2 at the benchmark size: the device's Z~v and Z~o of the whole call
+    against the oracle's, summed over the unordered triples in chunks (with progress
+    lines; about a minute on the host)."""
+    torch, cc3 = _setup()
+    d, g, ctx, _, _ = medium
+    zv, zo = ctx.jacobian_prep(g["eps"], g["L"], g["t1"], g["t2"])
+    torch.cuda.synchronize()
+    zv, zo = zv.cpu().numpy(), zo.cpu().numpy()
+    no = d["no"]
+    blk = O.IntegralBlocks(O.t1_transform(d["L"], d["t1"]), no)
+    tri = O.unordered_triples(no)
+    rv = np.zeros_like(zv)
+    ro = np.zeros_like(zo)
+    step = 40
+    for c0 in range(0, len(tri), step):
+        v, o = O.jacobian_prep_tilde(d["eps"], d["t2"], blk, triples=tri[c0:c0 + step])
+        rv += v
+        ro += o
+        say(f"  oracle Algorithm 2: {min(c0 + step, len(tri))} of {len(tri)} triples")
+    for name, got, ref in (("Zv", zv, rv), ("Zo", zo, ro)):
+        e2, em = rel2(got, ref), relmax(got, ref)
+        say(f"  {name}: rel2 {e2:.3e} relmax {em:.3e}")
+        assert e2 <= TOL and em <= TOL, (name, e2, em)
 
 
 def test_full_batch_no23_nv250():
