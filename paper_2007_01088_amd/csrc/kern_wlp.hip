@@ -182,11 +182,14 @@ struct LpTile {
   static_assert(LBM == LBN && NI * LNT * 16 == TILEB, "tile shape");
 };
 
-// LDS chunk of logical chunk c of row `row` (an involution in c)
+// LDS chunk of logical chunk c of row `row` (an involution in c).  Both forms
+// measured free of bank conflicts (SQ_LDS_BANK_CONFLICT = 0) for the fragment
+// reads, 16 rows by one chunk column per lane group; XOR with (row >> 2) & 3
+// for 64-byte rows, or no swizzle, gives two-way conflicts.
 template <class E>
 __device__ inline int lp_chunk(int row, int c) {
   if constexpr (LpTile<E>::CPR == 8) return c ^ ((row >> 1) & 7);
-  else return c ^ ((row >> 2) & 3);
+  else return c ^ ((row >> 1) & 3);
 }
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
