@@ -291,6 +291,8 @@ def main() -> int:
     ap.add_argument("--extra-steps", type=int, default=2,
                     help="timed calls of each extra measurement after the timed region")
     ap.add_argument("--prec", default="fp64", choices=["fp64"])
+    ap.add_argument("--mixed-forms", default="fp32,bf16x6,bf16x3,fp32_all,bf16x6_all,bf16x3_all",
+                    help="comma-separated low-precision forms to time after the FP64 steps")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip timing the mixed-precision W contractions (FP32, BF16x3, BF16x6)")
     ap.add_argument("--no-jacobian-prep", action="store_true",
@@ -428,7 +430,10 @@ def main() -> int:
     if not args.no_mixed:
         # the same call with the W contractions in low precision; errors against the FP64
         # result of this GPU (equal to the CPU oracle to ~1e-15 in the parity tests)
+        forms = set(args.mixed_forms.split(","))
         for name, prec in (("fp32", cc3.FP32), ("bf16x6", cc3.BF16X6), ("bf16x3", cc3.BF16X3)):
+            if name not in forms:
+                continue
             m1 = torch.empty_like(o1)
             m2 = torch.empty_like(o2)
             ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], m1, m2, prec=prec)
@@ -456,6 +461,8 @@ def main() -> int:
         # "mixed-all": the vv and Omega1 contraction in the low precision as well
         for name, prec in (("fp32_all", cc3.FP32), ("bf16x6_all", cc3.BF16X6),
                            ("bf16x3_all", cc3.BF16X3)):
+            if name not in forms:
+                continue
             m1 = torch.empty_like(o1)
             m2 = torch.empty_like(o2)
             fl = cc3.LOWP_CONTRACT
