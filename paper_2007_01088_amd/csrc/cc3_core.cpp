@@ -229,7 +229,8 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   // largest (triples x chunks) product over the batch sizes the loop can see
   size_t tc = 1;
   for (int nb = 1; nb <= batch; ++nb)
-    tc = std::max(tc, (size_t)nb * std::max(omega_kchunks(nv, nb), zo_nbchunks(nv, nb)));
+    tc = std::max(tc, (size_t)nb * std::max(omega_kchunks(nv, nb, (flags & CC3_LOWP_CONTRACT) != 0),
+                                            zo_nbchunks(nv, nb)));
   p->pvv_entries = tc;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
@@ -472,7 +473,8 @@ static int triple_loop_body(Runner& rn, Profiler* pf, const Plan& p, const Ws& w
     }
     {
       Timer tm(pf, sk, FAM_REDUCE, 0.0, 0.0);
-      launch_reduce(tb, nb, w.Pvv[k], w.Ot1, w.Ot2, p.no, p.nv, sk);
+      launch_reduce(tb, nb, w.Pvv[k], w.Ot1, w.Ot2, p.no, p.nv, (p.flags & CC3_LOWP_CONTRACT) != 0,
+                    sk);
     }
     if (!own) HIPCHK(hipEventRecord(rn.ev_red[k], sk));
   }
@@ -603,7 +605,8 @@ static int jacobian_prep_body(Runner& rn, Profiler* pf, const Plan& p, const Ws&
   HIPCHK(hipEventRecord(rn.ev_fork, st));
   for (int k = 0; k < NSTREAM; ++k) HIPCHK(hipStreamWaitEvent(rn.s[k], rn.ev_fork, 0));
   static const int env_serial = env_int("CC3_SERIAL", 0);
-  const int nstream = (env_serial || (p.flags & CC3_ONE_STREAM)) ? 1 : NSTREAM;
+  // one stream from nv = 192 on, as in the residual loop
+  const int nstream = (env_serial || (p.flags & CC3_ONE_STREAM) || p.nv > 192) ? 1 : NSTREAM;
   const int n = p.ntri;
   const int ngroups = nbatches(p);
   for (int nbatch = 0; nbatch < ngroups; ++nbatch) {

@@ -157,7 +157,7 @@ void launch_tau_export(const double* eps, const int* tri, const double* cubes, d
 void launch_omega(const double* cubes, const Blocks& b, const int* tri, int ntri, double* Pvv,
                   int no, int nv, hipStream_t st);
 void launch_reduce(const int* tri, int ntri, const double* Pvv, double* Ot1, double* Ot2, int no,
-                   int nv, hipStream_t st);
+                   int nv, bool fp32acc, hipStream_t st);
 void launch_omega_oo(const double* cubes, const Blocks& b, const int* tri, int ntri, double* OtT,
                      int no, int nv, hipStream_t st);
 // The mixed-all form of launch_omega: FP32 MFMA over FP32 copies of the cubes
@@ -178,7 +178,9 @@ void launch_omega_lp(int prec, const void* YL, const void* GbcL, const void* Gcb
 // Ot~2[p][q][a][b] = Ot2[p][q][a][b] + OtT[p][q][b][a]  (contravariant doubles residual)
 void launch_combine(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
                     double* O2, int no, int nv, hipStream_t st);
-int omega_kchunks(int nv, int ntri);  // K chunks of one Omega GEMM
+// K chunks of one Omega GEMM; fp32acc: its chunks are summed in FP32 (the mixed-all
+// forms), at most 4096 k each
+int omega_kchunks(int nv, int ntri, bool fp32acc = false);
 int zo_nbchunks(int nv, int ntri);    // b chunks of one Zo product
 void launch_back_transform(const double* Ot1, const double* Ot2, const double* OtT, double* O1,
                            double* O2, int no, int nv, bool accumulate, hipStream_t st);

@@ -1039,9 +1039,14 @@ __device__ __forceinline__ void omega_oo_body(const double* __restrict__ cubes,
   // the current step's MFMAs
   const int cs = (nv + 15) / 16;
   const int nit = n * cs;
+  // Elements with c past nv load a valid element (c clamped) and are zeroed when they
+  // are used (cm: bit i or tt set for c < nv), so that the next step's loads stay in
+  // flight over the current step's MFMAs.
   double u[2][NB][4], h[2][FNO][4];
   bool cc1[2];
-  auto load = [&](int it, double (&uu)[NB][4], double (&hh)[FNO][4], bool& ccont) {
+  unsigned cm1[2];
+  auto load = [&](int it, double (&uu)[NB][4], double (&hh)[FNO][4], bool& ccont,
+                  unsigned& cm) {
     const int t = it / cs, c0 = (it - t * cs) * 16;
     const int zp = lz[t], zz = zp / 6, pi = zp % 6;
     int slot, sbb, sm, sk;
@@ -1051,26 +1056,23 @@ __device__ __forceinline__ void omega_oo_body(const double* __restrict__ cubes,
     if (ccont) {  // element i: row a0 + 4 i + kq, c = c0 + m
       const int c = c0 + m;
       const int cc = min(c, nv - 1);
+      cm = c < nv ? 15u : 0u;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = min(a0 + 4 * i + kq, nv - 1);
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const double v = ub[(int64_t)row * sm + (int64_t)bb[j] * sbb + cc];
-          uu[j][i] = c < nv ? v : 0.0;
-        }
+        for (int j = 0; j < NB; ++j) uu[j][i] = ub[(int64_t)row * sm + (int64_t)bb[j] * sbb + cc];
       }
     } else {  // element tt: row a0 + m, c = c0 + 4 kq + tt
       const int64_t ra = (int64_t)min(a0 + m, nv - 1);
+      cm = 0u;
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         const int c = c0 + 4 * kq + tt;
         const int cc = min(c, nv - 1);
+        cm |= c < nv ? 1u << tt : 0u;
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const double v = ub[ra + (int64_t)bb[j] * sbb + (int64_t)cc * sk];
-          uu[j][tt] = c < nv ? v : 0.0;
-        }
+        for (int j = 0; j < NB; ++j) uu[j][tt] = ub[ra + (int64_t)bb[j] * sbb + (int64_t)cc * sk];
       }
     }
     const double* hb = Hs + (int64_t)lqr[t] * no * nvl;
@@ -1081,13 +1083,13 @@ __device__ __forceinline__ void omega_oo_body(const double* __restrict__ cubes,
       for (int f = 0; f < FNO; ++f) hh[f][tt] = hb[(int64_t)cc * no + min(16 * f + m, no - 1)];
     }
   };
-  auto mma = [&](const double (&uu)[NB][4], const double (&hh)[FNO][4], bool ccont) {
+  auto mma = [&](const double (&uu)[NB][4], const double (&hh)[FNO][4], bool ccont, unsigned cm) {
     double x[NB][4];
     if (ccont) {  // transpose through this wavefront's LDS tile
 #pragma unroll
       for (int j = 0; j < NB; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lt[wave][j][4 * i + kq][m] = uu[j][i];
+        for (int i = 0; i < 4; ++i) lt[wave][j][4 * i + kq][m] = cm ? uu[j][i] : 0.0;
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int j = 0; j < NB; ++j)
@@ -1098,7 +1100,7 @@ __device__ __forceinline__ void omega_oo_body(const double* __restrict__ cubes,
 #pragma unroll
       for (int j = 0; j < NB; ++j)
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) x[j][tt] = uu[j][tt];
+        for (int tt = 0; tt < 4; ++tt) x[j][tt] = ((cm >> tt) & 1u) ? uu[j][tt] : 0.0;
     }
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt)
@@ -1108,13 +1110,13 @@ __device__ __forceinline__ void omega_oo_body(const double* __restrict__ cubes,
         for (int f = 0; f < FNO; ++f)
           acc[j][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(hh[f][tt], x[j][tt], acc[j][f], 0, 0, 0);
   };
-  load(0, u[0], h[0], cc1[0]);
+  load(0, u[0], h[0], cc1[0], cm1[0]);
   for (int it = 0; it < nit; it += 2) {
-    if (it + 1 < nit) load(it + 1, u[1], h[1], cc1[1]);
-    mma(u[0], h[0], cc1[0]);
+    if (it + 1 < nit) load(it + 1, u[1], h[1], cc1[1], cm1[1]);
+    mma(u[0], h[0], cc1[0], cm1[0]);
     if (it + 1 < nit) {
-      if (it + 2 < nit) load(it + 2, u[0], h[0], cc1[0]);
-      mma(u[1], h[1], cc1[1]);
+      if (it + 2 < nit) load(it + 2, u[0], h[0], cc1[0], cm1[0]);
+      mma(u[1], h[1], cc1[1], cm1[1]);
     }
   }
   const int ac = a0 + m;
@@ -1374,7 +1376,7 @@ int zo_nbchunks(int nv, int ntri) {
 // the same XCD (workgroups go round-robin over the 8 XCDs in linear order, and
 // tiles of one chunk are nchunks apart) and meet in its L2; at least 16 stages
 // per chunk.
-int omega_kchunks(int nv, int ntri) {
+int omega_kchunks(int nv, int ntri, bool fp32acc) {
   static const int target = [] {
     const char* e = getenv("CC3_OMEGA_WG");
     const int v = e ? atoi(e) : 0;
@@ -1388,6 +1390,12 @@ int omega_kchunks(int nv, int ntri) {
   const int S = (nv * nv + T::BK - 1) / T::BK;
   const int cap = S / 16 > 1 ? S / 16 : 1;
   if (nch > cap) nch = cap;
+  // chunks that the MFMA sums in FP32 (the mixed-all forms) hold at most 4096 k, so
+  // that their rounding does not grow with the batch
+  if (fp32acc) {
+    const int need = (nv * nv + 4095) / 4096;
+    if (nch < need) nch = need > 8 ? (need + 7) / 8 * 8 : need;
+  }
   return nch < 1 ? 1 : nch;
 }
 
@@ -1404,7 +1412,7 @@ void launch_omega_f32(const float* cubesF, const float* GbcF, const float* GcbF,
                       int ntri, double* Pvv, int no, int nv, hipStream_t st) {
   typedef OCfg T;
   const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + 1 + T::BN - 1) / T::BN;
-  const int nch = omega_kchunks(nv, ntri);
+  const int nch = omega_kchunks(nv, ntri, true);
   hipLaunchKernelGGL(k_omega<float>, dim3(nch * tm * tn, 6, ntri), dim3(T::NT), 0, st, cubesF, 2,
                      (int)SLOT_TT, GbcF, GcbF, tri, Pvv, no, nv, nch, tn);
 }
@@ -1437,8 +1445,8 @@ void launch_omega_oo(const double* cubes, const Blocks& b, const int* tri, int n
 }
 
 void launch_reduce(const int* tri, int ntri, const double* Pvv, double* Ot1, double* Ot2, int no,
-                   int nv, hipStream_t st) {
-  const int nch = omega_kchunks(nv, ntri);
+                   int nv, bool fp32acc, hipStream_t st) {
+  const int nch = omega_kchunks(nv, ntri, fp32acc);
   const int64_t nv2 = (int64_t)nv * nv;
   hipLaunchKernelGGL(k_reduce, dim3(nblk(nv2, 256), no, no), dim3(256), 0, st, tri, ntri, Pvv, Ot1,
                      Ot2, no, nv, nch);

@@ -259,20 +259,25 @@ __device__ __forceinline__ void lp_mfma_stage(const char* buf, f4v (&acc)[LFM][L
                                               int wm, int wn) {
   typedef LpTile<E> L;
   const int g = lane >> 4, r16 = lane & 15;
+  // Fragment rows are 16 R + r16, and lp_chunk's XOR depends on bits 1-3 of the row
+  // only, that is on r16: the lane's byte offset within a fragment's rows is one value
+  // per chunk column, and the fragment's own offset (16 R RB) is a constant.
+  auto lane_off = [&](int c) __attribute__((always_inline)) {
+    return r16 * L::RB + lp_chunk<E>(r16, c) * 16;
+  };
+  const char* ab = buf + wm * LFM * 16 * L::RB;             // this wave's A rows
+  const char* bb = buf + L::P * L::TILEB + wn * LFN * 16 * L::RB;  // and B rows
   if constexpr (E::P == 1) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      const int lo = lane_off(4 * h + g);
       f4v a[LFM];
 #pragma unroll
-      for (int fm = 0; fm < LFM; ++fm) {
-        const int row = (wm * LFM + fm) * 16 + r16;
-        a[fm] = *(const f4v*)(buf + row * L::RB + lp_chunk<E>(row, 4 * h + g) * 16);
-      }
+      for (int fm = 0; fm < LFM; ++fm) a[fm] = *(const f4v*)(ab + fm * 16 * L::RB + lo);
       // one B fragment at a time (registers: the FP64 accumulator of FLUSH is large)
 #pragma unroll
       for (int fn = 0; fn < LFN; ++fn) {
-        const int row = (wn * LFN + fn) * 16 + r16;
-        const f4v b = *(const f4v*)(buf + L::TILEB + row * L::RB + lp_chunk<E>(row, 4 * h + g) * 16);
+        const f4v b = *(const f4v*)(bb + fn * 16 * L::RB + lo);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -281,20 +286,16 @@ __device__ __forceinline__ void lp_mfma_stage(const char* buf, f4v (&acc)[LFM][L
       }
     }
   } else {
+    const int lo = lane_off(g);
     bf8v a[L::P][LFM], b[L::P][LFN];
 #pragma unroll
     for (int pc = 0; pc < L::P; ++pc) {
 #pragma unroll
-      for (int fm = 0; fm < LFM; ++fm) {
-        const int row = (wm * LFM + fm) * 16 + r16;
-        a[pc][fm] = *(const bf8v*)(buf + pc * L::TILEB + row * L::RB + lp_chunk<E>(row, g) * 16);
-      }
+      for (int fm = 0; fm < LFM; ++fm)
+        a[pc][fm] = *(const bf8v*)(ab + pc * L::TILEB + fm * 16 * L::RB + lo);
 #pragma unroll
-      for (int fn = 0; fn < LFN; ++fn) {
-        const int row = (wn * LFN + fn) * 16 + r16;
-        b[pc][fn] = *(const bf8v*)(buf + (L::P + pc) * L::TILEB + row * L::RB +
-                                   lp_chunk<E>(row, g) * 16);
-      }
+      for (int fn = 0; fn < LFN; ++fn)
+        b[pc][fn] = *(const bf8v*)(bb + pc * L::TILEB + fn * 16 * L::RB + lo);
     }
 #pragma unroll
     for (int t = 0; t < E::NPROD; ++t) {
@@ -580,7 +581,7 @@ void launch_lp_contract_convert(const Blocks& b, int prec, int no, int nv, void*
 void launch_omega_lp(int prec, const void* YL, const void* GbcL, const void* GcbL, const int* tri,
                      int ntri, double* Pvv, int no, int nv, hipStream_t st) {
   const int tm = (nv + LBM - 1) / LBM, tn = (nv + 1 + LBN - 1) / LBN;
-  const int nch = omega_kchunks(nv, ntri);
+  const int nch = omega_kchunks(nv, ntri, true);
   const dim3 grid(nch * tm * tn, 6, ntri), block(LNT);
   const char *y = (const char*)YL, *gb = (const char*)GbcL, *gc = (const char*)GcbL;
   if (prec == CC3_BF16X3)

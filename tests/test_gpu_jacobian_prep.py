@@ -54,11 +54,12 @@ def close(name, got, ref, tol=TOL):
 @pytest.mark.parametrize("no,nv,nJ,t1z", [(4, 20, 60, False), (4, 20, 60, True), (3, 9, 12, False),
                                           (5, 37, 50, False), (6, 130, 40, False),
                                           (16, 16, 40, False), (20, 12, 30, False),
-                                          (35, 8, 16, False)])
+                                          (35, 8, 16, False), (3, 196, 24, False)])
 def test_jacobian_prep_parity(ctx, no, nv, nJ, t1z):
     """(16, 16): batches of 160 triples in which one occupied index heads up to 255
     (triple, permutation) pairs, beyond half the per-index list bound.  (20, 12) and
-    (35, 8): the Zo partials span two and three 16-wide tiles of l."""
+    (35, 8): the Zo partials span two and three 16-wide tiles of l.  (3, 196): above
+    nv = 192, where the batches run on one stream."""
     torch = _torch()
     say(f"jacobian prep no={no} nv={nv} nJ={nJ} t1_zero={t1z}")
     d = make_inputs(no, nv, nJ, t1_zero=t1z)

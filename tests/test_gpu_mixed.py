@@ -31,9 +31,9 @@ BOUND_SAMPLE = {"fp32": 1.5e-7, "bf16x6": 1.5e-7, "bf16x3": 3e-5}
 BOUND_T3 = {"fp32": 3e-7, "bf16x6": 3e-7, "bf16x3": 3e-5}
 # Mixed-all: tau~ and the (vv|ov) block are rounded to FP32 (or split BF16, whose three
 # pieces keep about as many bits) too, and each K chunk of the vv GEMM (nv^2 / chunks
-# terms, 900 at 12/120/400) sums in FP32 (BF16x6: stage by stage into FP64).  Omega1, one
-# column of that GEMM summed over all of K with cancellation, carries the most, and its
-# error grows with nv.  Measured Omega1 errors of whole calls at nv = 48, 120, 250, 400
+# terms, 900 at 12/120/400, at most 4096) sums in FP32 (BF16x6: stage by stage into FP64).
+# Omega1, one column of that GEMM summed over all of K with cancellation, carries the
+# most, and its error grows with nv.  Measured Omega1 errors of whole calls at nv = 48, 120, 250, 400
 # (no = 5, 12, 23, 31): FP32 1.8e-7, 3.0e-7, 4.2e-7, 5.8e-7, i.e. 0.44-0.48 u sqrt(nv)
 # with u = 2^-24; BF16x6 9.8e-8, 2.5e-7, 7.7e-7, 1.4e-6, i.e. 0.034-0.058 u nv; BF16x3
 # 4.3e-6, 4.1e-6, 4.1e-6, 7.1e-6 (its 2-piece split dominates).  Omega2 stays below
@@ -107,6 +107,32 @@ def test_mixed_t3_block():
         e = rel(t, ref)
         print(f"t3 {name}: {e:.3e}", flush=True)
         assert e <= BOUND_T3[name]
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["fp32", "bf16x3"])
+def test_mixed_all_chunk_length(name):
+    """The mixed-all forms sum each K chunk of the vv GEMM in FP32; at (3, 260, 20) one
+    batch of 7 triples alone would split K = 67600 into 6 chunks, and the chunks are held
+    to at most 4096 k (24 of them), so that the error does not grow with the batch.
+    Against the device's FP64 result (equal to the oracle's to about 1e-15 at every
+    size compared), within bound_all at nv = 260."""
+    torch, cc3 = _setup()
+    prec = {"fp32": cc3.FP32, "bf16x3": cc3.BF16X3}[name]
+    ctx = cc3.Context(0)
+    no, nv, nJ = 3, 260, 20
+    d = make_inputs(no, nv, nJ)
+    g = {k: torch.from_numpy(d[k]).cuda() for k in ("eps", "L", "t1", "t2")}
+    r1, r2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"])
+    o1, o2 = ctx.triples_residual(g["eps"], g["L"], g["t1"], g["t2"], prec=prec,
+                                  flags=cc3.LOWP_CONTRACT)
+    torch.cuda.synchronize()
+    e1 = rel(o1.cpu().numpy(), r1.cpu().numpy())
+    e2 = rel(o2.cpu().numpy(), r2.cpu().numpy())
+    bd = bound_all(name, nv)
+    print(f"mixed-all {name} no={no} nv={nv}: rel err Omega1 {e1:.3e} Omega2 {e2:.3e} "
+          f"(bound {bd:.1e})", flush=True)
+    assert e1 <= bd and e2 <= bd, (no, nv, e1, e2)
     ctx.close()
 
 
