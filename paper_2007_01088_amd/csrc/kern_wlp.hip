@@ -135,16 +135,17 @@ constexpr int LBM = 16 * LWM * LFM, LBN = 16 * LWN * LFN;  // 128 x 128
 // dominate the error (FP32 and the 3-piece BF16 split); the 2-piece split is
 // limited by its operands and keeps one FP32 accumulator per term.
 // MINW: waves per SIMD the W kernel is built for (4: two workgroups per CU).
+// NS: LDS stage buffers of the ring (NS - 1 stages of loads in flight).
 struct EngF32 {
   static constexpr int BK = 32, P = 1, NPROD = 1, ESZ = 4;
   static constexpr bool FLUSH = true;
-  static constexpr int MINW = 4;
+  static constexpr int MINW = 4, NS = 2;
 };
 template <int P_>
 struct EngBF16 {
   static constexpr int BK = 32, P = P_, NPROD = (P_ == 2 ? 3 : 6), ESZ = 2;
   static constexpr bool FLUSH = (P_ == 3);
-  static constexpr int MINW = (P_ == 2 ? 4 : 2);
+  static constexpr int MINW = (P_ == 2 ? 4 : 2), NS = (P_ == 2 ? 2 : 3);
 };
 
 // the piece pairs of the split products
@@ -179,7 +180,10 @@ struct LpTile {
   static constexpr int TILEB = LBM * RB;         // one operand piece of one stage
   static constexpr int NI = TILEB / (LNT * 16);  // loads per lane per operand piece
   static constexpr int STAGEB = 2 * P * TILEB;
+  static constexpr int NS = E::NS;               // stage buffers
+  static constexpr int LPS = 2 * P * NI;         // direct loads per lane per stage
   static_assert(LBM == LBN && NI * LNT * 16 == TILEB, "tile shape");
+  static_assert(NS >= 2 && (NS - 2) * LPS <= 63, "vmcnt range");
 };
 
 // LDS chunk of logical chunk c of row `row` (an involution in c).  Both forms
@@ -243,9 +247,32 @@ __device__ __forceinline__ void lp_load_stage(const LpSeg& sg, int st, char* buf
   }
 }
 
-// The loads of this lane have reached LDS, then every lane's have.
-__device__ __forceinline__ void lp_stage_ready() {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+// The oldest stage in flight has reached LDS for every lane: this lane waits until at
+// most `later` stages of its loads are outstanding (they return in order), then the
+// workgroup barrier.  The barrier also ends every wave's reads of the previous stage,
+// whose buffer the next loads overwrite.
+template <int N>
+__device__ __forceinline__ void lp_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+template <class E>
+__device__ __forceinline__ void lp_stage_ready(int later) {
+  typedef LpTile<E> L;
+  if constexpr (L::NS >= 3) {
+    if (later >= 1) {
+      if constexpr (L::NS >= 4) {
+        if (later >= 2) {
+          lp_vmcnt<2 * L::LPS>();
+          __syncthreads();
+          return;
+        }
+      }
+      lp_vmcnt<L::LPS>();
+      __syncthreads();
+      return;
+    }
+  }
+  lp_vmcnt<0>();
   __syncthreads();
 }
 
@@ -330,24 +357,38 @@ __device__ __forceinline__ void lp_flush(f4v (&acc)[LFM][LFN], d4v (&accd)[LFM][
 // ---------------------------------------------------------------------------
 // W build in low precision
 // ---------------------------------------------------------------------------
-// The stages of one K segment `cur` into acc (with FLUSH into accd); the last
-// one prefetches the first stage of `nxt` when has_next.  sidx counts the
-// stages of the plane (it selects the stage buffer).  The segments are passed
-// by value and chosen statically by the caller, so that they stay in registers.
+// Issue the loads of stage t of the plane (its four K segments in turn) into buf.
+// The segments are passed by value and each call site names one of them, so that they
+// stay in scalar registers.
 template <class E>
-__device__ __forceinline__ void wlp_seg(const LpSeg cur, const LpSeg nxt, bool has_next, int& sidx,
-                                        char* lds, const unsigned* cb, const int* ar,
-                                        const int* br, int wave, int lane, int wm, int wn,
+__device__ __forceinline__ void wlp_load(int t, char* buf, const LpSeg s0, const LpSeg s1,
+                                         const LpSeg s2, const LpSeg s3, const unsigned* cb,
+                                         const int* ar, const int* br, int wave) {
+  if (t < s0.nst) { lp_load_stage<E>(s0, t, buf, cb, ar, br, wave); return; }
+  t -= s0.nst;
+  if (t < s1.nst) { lp_load_stage<E>(s1, t, buf, cb, ar, br, wave); return; }
+  t -= s1.nst;
+  if (t < s2.nst) { lp_load_stage<E>(s2, t, buf, cb, ar, br, wave); return; }
+  t -= s2.nst;
+  lp_load_stage<E>(s3, t, buf, cb, ar, br, wave);
+}
+
+// Stages [sb, se) of the plane's nsteps into acc (with FLUSH into accd), the loads
+// running NS - 1 stages ahead in the ring of NS stage buffers.
+template <class E>
+__device__ __forceinline__ void wlp_run(int sb, int se, int nsteps, char* lds, const LpSeg s0,
+                                        const LpSeg s1, const LpSeg s2, const LpSeg s3,
+                                        const unsigned* cb, const int* ar, const int* br,
+                                        int wave, int lane, int wm, int wn,
                                         f4v (&acc)[LFM][LFN], d4v (&accd)[LFM][LFN]) {
   typedef LpTile<E> L;
-  for (int st = 0; st < cur.nst; ++st, ++sidx) {
-    char* cbuf = lds + (sidx & 1) * L::STAGEB;
-    char* nbuf = lds + ((sidx + 1) & 1) * L::STAGEB;
-    if (st + 1 < cur.nst) lp_load_stage<E>(cur, st + 1, nbuf, cb, ar, br, wave);
-    else if (has_next) lp_load_stage<E>(nxt, 0, nbuf, cb, ar, br, wave);
-    lp_mfma_stage<E>(cbuf, acc, lane, wm, wn);
+  for (int s = sb; s < se; ++s) {
+    lp_stage_ready<E>(min(L::NS - 2, nsteps - 1 - s));
+    const int ahead = s + L::NS - 1;
+    if (ahead < nsteps)
+      wlp_load<E>(ahead, lds + (ahead % L::NS) * L::STAGEB, s0, s1, s2, s3, cb, ar, br, wave);
+    lp_mfma_stage<E>(lds + (s % L::NS) * L::STAGEB, acc, lane, wm, wn);
     if constexpr (E::FLUSH) lp_flush(acc, accd);
-    lp_stage_ready();
   }
 }
 
@@ -358,7 +399,7 @@ __device__ __forceinline__ void wbuild_lp_body(
     int nv, int tiles_m, int tiles_n, int all_terms, int bx, int by, int bz) {
   typedef LpTile<E> L;
   constexpr int ESZ = E::ESZ;
-  __shared__ __attribute__((aligned(16))) char lds[2 * L::STAGEB];
+  __shared__ __attribute__((aligned(16))) char lds[L::NS * L::STAGEB];
   const int tpp = tiles_m * tiles_n;
   const int y = bx / tpp;
   const int tile = bx % tpp;
@@ -414,15 +455,16 @@ __device__ __forceinline__ void wbuild_lp_body(
   for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
     for (int fn = 0; fn < LFN; ++fn) accd[fm][fn] = d4v{0.0, 0.0, 0.0, 0.0};
-  int sidx = 0;
-  lp_load_stage<E>(sg0, 0, lds, ln.cb, ar, br, wave);
-  lp_stage_ready();
-  wlp_seg<E>(sg0, sg1, true, sidx, lds, ln.cb, ar, br, wave, lane, wm, wn, acc1, accd);
-  wlp_seg<E>(sg1, sg2, two, sidx, lds, ln.cb, ar, br, wave, lane, wm, wn, acc1, accd);
+  const int nt1 = sg0.nst + sg1.nst;  // stages of one term
+  const int nsteps = two ? 2 * nt1 : nt1;
+#pragma unroll
+  for (int t = 0; t < L::NS - 1; ++t)
+    if (t < nsteps) wlp_load<E>(t, lds + t * L::STAGEB, sg0, sg1, sg2, sg3, ln.cb, ar, br, wave);
+  wlp_run<E>(0, nt1, nsteps, lds, sg0, sg1, sg2, sg3, ln.cb, ar, br, wave, lane, wm, wn, acc1, accd);
   if (two) {
     f4v (&acc)[LFM][LFN] = E::FLUSH ? acc1 : acc2;
-    wlp_seg<E>(sg2, sg3, true, sidx, lds, ln.cb, ar, br, wave, lane, wm, wn, acc, accd);
-    wlp_seg<E>(sg3, sg3, false, sidx, lds, ln.cb, ar, br, wave, lane, wm, wn, acc, accd);
+    wlp_run<E>(nt1, nsteps, nsteps, lds, sg0, sg1, sg2, sg3, ln.cb, ar, br, wave, lane, wm, wn,
+               acc, accd);
   }
 
   // the FP32/BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
@@ -473,7 +515,7 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
                                                   int nchunks, int tiles_n) {
   typedef LpTile<E> L;
   constexpr int ESZ = E::ESZ;
-  __shared__ __attribute__((aligned(16))) char lds[2 * L::STAGEB];
+  __shared__ __attribute__((aligned(16))) char lds[L::NS * L::STAGEB];
   const int pi = blockIdx.y, z = blockIdx.z;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   if (!perm_active(tri_kind(i, j, k), pi)) return;
@@ -515,14 +557,17 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
   for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
     for (int fn = 0; fn < LFN; ++fn) accd[fm][fn] = d4v{0.0, 0.0, 0.0, 0.0};
-  lp_load_stage<E>(sg, s0, lds, ln.cb, ar, br, wave);
-  lp_stage_ready();
+  // the loads run NS - 1 stages ahead in the ring of NS stage buffers
+#pragma unroll
+  for (int t = 0; t < L::NS - 1; ++t)
+    if (s0 + t < s1) lp_load_stage<E>(sg, s0 + t, lds + t * L::STAGEB, ln.cb, ar, br, wave);
   for (int s = s0; s < s1; ++s) {
-    char* cur = lds + ((s - s0) & 1) * L::STAGEB;
-    if (s + 1 < s1) lp_load_stage<E>(sg, s + 1, lds + ((s - s0 + 1) & 1) * L::STAGEB, ln.cb, ar, br, wave);
-    lp_mfma_stage<E>(cur, acc, lane, wm, wn);
+    lp_stage_ready<E>(min(L::NS - 2, s1 - 1 - s));
+    const int ahead = s - s0 + L::NS - 1;
+    if (s0 + ahead < s1)
+      lp_load_stage<E>(sg, s0 + ahead, lds + (ahead % L::NS) * L::STAGEB, ln.cb, ar, br, wave);
+    lp_mfma_stage<E>(lds + ((s - s0) % L::NS) * L::STAGEB, acc, lane, wm, wn);
     if constexpr (E::FLUSH) lp_flush(acc, accd);
-    lp_stage_ready();
   }
   // the BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
   const int NV1 = nv + 1;
