@@ -301,6 +301,8 @@ def main() -> int:
                     help="calls with CC3_ONE_STREAM after the timed region, for kernel durations "
                          "without batch overlap (0: skip)")
     ap.add_argument("--no-cvs", action="store_true", help="skip the CVS worklist timing")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the Algorithm 3 (transition-density) timing")
     ap.add_argument("--no-host-buffers", action="store_true",
                     help="skip the timing of the call with host-memory arrays")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -538,6 +540,42 @@ def main() -> int:
         }
         log(f"jacobian prep: {out['jacobian_prep']['value']:.2f} TFLOP/s, {dtj * 1e3:.1f} ms per call")
         del zv, zo
+    if not args.no_density:
+        # Algorithm 3 (the triples contributions to the transition densities, FP64) for a
+        # seeded left state on the same inputs; nominal cost 13 nv^4 no^3, the paper's count
+        # for its occupied plus virtual loops; one untimed and one timed call
+        from paper_2007_01088_amd.synth import make_left_inputs
+        lf = make_left_inputs(no, nv)
+        l1 = torch.from_numpy(lf["l1"]).to(dev)
+        l2 = torch.from_numpy(lf["l2"]).to(dev)
+        dens = ctx.transition_density(g["eps"], g["L"], g["t1"], g["t2"], l1, l2, lf["omega"])
+        torch.cuda.synchronize()
+        log("transition density: untimed call done")
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        ctx.transition_density(g["eps"], g["L"], g["t1"], g["t2"], l1, l2, lf["omega"], out=dens + (None,))
+        torch.cuda.synchronize()
+        dtd = time.perf_counter() - t0
+        std = ctx.profile_get()
+        ctx.profile_enable(False)
+        nominal_d = 13.0 * nv ** 4 * no ** 3
+        fams = {k: {"launches": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
+                    "tflops": (v["flops"] / (v["total_ms"] * 1e-3) / 1e12)
+                    if v["flops"] and v["total_ms"] else None}
+                for k, v in std.items()}
+        ddom = max((k for k in std if std[k]["flops"]), key=lambda k: std[k]["total_ms"])
+        dach = fams[ddom]["tflops"]
+        out["transition_density"] = {
+            "what": "Algorithm 3: D_cd, D_kc, D_ld, D_lk (FP64) for a seeded left state",
+            "value": nominal_d / dtd / 1e12, "unit": "TFLOP/s", "ms_per_call": dtd * 1e3,
+            "nominal_flop_per_call": nominal_d,
+            "roofline": {"bound": "mfma", "kernel": ddom, "achieved": dach, "peak": PEAK_TFLOPS["fp64"],
+                         "unit": "TFLOP/s", "frac": dach / PEAK_TFLOPS["fp64"]},
+            "kernels": fams,
+        }
+        log(f"transition density: {out['transition_density']['value']:.2f} TFLOP/s, "
+            f"{dtd * 1e3:.1f} ms per call")
+        del dens, l1, l2
     if not args.no_cvs:
         # the core-valence separation worklist: only the triples that contain the lowest
         # occupied orbital (one core orbital of interest), through the subset entry point

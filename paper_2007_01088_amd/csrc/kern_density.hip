@@ -117,17 +117,30 @@ __global__ __launch_bounds__(VecCfg::NT) void k_d3_vec(const double* __restrict_
   const int64_t S[3] = {nv2, nvl, 1};
   const int axa = kPerm[ord][0], axb = kPerm[ord][1], axc = kPerm[ord][2];
   const double* U = cubes + (KC ? D3_TAUC : D3_LC) * ss + (int64_t)z * nv3;
+  // K = (a, b), split over its outer index.  When the view's a is the cube's contiguous
+  // axis, K runs in (b, a) order instead, so that the A loads run along a; B then reads
+  // the pair-symmetric copy of its row, t2[l][q][a][b] = t2[q][l][b][a] and
+  // l2[p][q][a][b] = l2[q][p][b][a], with a contiguous as well.
+  const bool ba = (axa == 2);
   const int a0 = (int)((int64_t)ch * nv / nch), a1 = (int)((int64_t)(ch + 1) * nv / nch);
   const int cs = (nv + T::BK - 1) / T::BK;
   const int ncol = KC ? 1 : no;
   auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
-    const int aa = a0 + s / cs;
+    const int oo = a0 + s / cs;  // a, or b when ba
     k0 = (s % cs) * T::BK;
-    A = make_opnd(U + aa * S[axa], S[axc], S[axb], nv, nv, S[axc] == 1);
-    if (KC)  // the single row l2[p][q][a][.]
-      B = make_opnd(X + ((int64_t)p * no + q) * nv2 + (int64_t)aa * nv, 0, 1, 1, nv, false);
-    else  // rows l of t2[l][q][a][.]
-      B = make_opnd(X + (int64_t)q * nv2 + (int64_t)aa * nv, (int64_t)no * nv2, 1, no, nv, false);
+    if (!ba) {
+      A = make_opnd(U + oo * S[axa], S[axc], S[axb], nv, nv, S[axc] == 1);
+      if (KC)  // the single row l2[p][q][a][.]
+        B = make_opnd(X + ((int64_t)p * no + q) * nv2 + (int64_t)oo * nv, 0, 1, 1, nv, false);
+      else  // rows l of t2[l][q][a][.]
+        B = make_opnd(X + (int64_t)q * nv2 + (int64_t)oo * nv, (int64_t)no * nv2, 1, no, nv, false);
+    } else {
+      A = make_opnd(U + oo * S[axb], S[axc], S[axa], nv, nv, false);
+      if (KC)  // l2[q][p][b][.]
+        B = make_opnd(X + ((int64_t)q * no + p) * nv2 + (int64_t)oo * nv, 0, 1, 1, nv, false);
+      else  // rows l of t2[q][l][b][.]
+        B = make_opnd(X + (int64_t)q * no * nv2 + (int64_t)oo * nv, nv2, 1, no, nv, false);
+    }
   };
   d4v acc[T::FM][T::FN];
   zero_acc<T>(acc);

@@ -34,9 +34,9 @@ BOUND_T3 = {"fp32": 3e-7, "bf16x6": 3e-7, "bf16x3": 3e-5}
 # terms, 900 at 12/120/400, at most 4096) sums in FP32 (BF16x6: stage by stage into FP64).
 # Omega1, one column of that GEMM summed over all of K with cancellation, carries the
 # most, and its error grows with nv.  Measured Omega1 errors of whole calls at nv = 48, 120, 250, 400
-# (no = 5, 12, 23, 31): FP32 1.8e-7, 3.0e-7, 4.2e-7, 5.8e-7, i.e. 0.44-0.48 u sqrt(nv)
+# (no = 5, 12, 23, 31): FP32 1.8e-7, 3.0e-7, 5.2e-7, 4.6e-7, i.e. 0.39-0.55 u sqrt(nv)
 # with u = 2^-24; BF16x6 9.8e-8, 2.5e-7, 7.7e-7, 1.4e-6, i.e. 0.034-0.058 u nv; BF16x3
-# 4.3e-6, 4.1e-6, 4.1e-6, 7.1e-6 (its 2-piece split dominates).  Omega2 stays below
+# 4.3e-6, 4.1e-6, 4.4e-6, 5.8e-6 (its 2-piece split dominates).  Omega2 stays below
 # 1e-7 in every form.  The bounds follow those growth laws with at least a factor 2 of
 # headroom: FP32 u sqrt(nv), BF16x6 0.12 u nv, BF16x3 3e-5.  No mixed-all form meets
 # 1e-7 on Omega1 (the W-only forms do).
