@@ -203,7 +203,7 @@ int make_plan_ex(int no, int nv, int nchol, int prec, unsigned flags, bool with_
   p->no = no; p->nv = nv; p->nchol = nchol; p->prec = prec; p->flags = flags;
   const size_t o = no, v = nv, J = nchol;
   p->ntri = (int)((size_t)no * (no + 1) * (no + 2) / 6 - no);
-  p->cube = v * v * v;
+  p->cube = (size_t)cube_slot(nv);  // one padded cube slot
   // triples per batch: enough W-build workgroups per launch to fill 256 CUs
   // many times over, and at least min(no, 16) triples, so that the kernels that
   // are parallel over the first occupied index p (the oo contraction, the

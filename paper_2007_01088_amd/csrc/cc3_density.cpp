@@ -226,7 +226,7 @@ extern "C" int cc3_transition_density(cc3_ctx* c, int no, int nv, int nchol, con
     const double wfl = wbuild_flops(no, nv, kinds.data(), no);
     {
       Timer tm(pf, st, FAM_W, wfl, 0.0);
-      launch_wbuild_ex(0, t2, t2N, Gw, Go, tb, no, cubes, nv3, ss, no, nv, false, st);
+      launch_wbuild_ex(0, t2, t2N, Gw, Go, tb, no, cubes, nv3, ss, nv, no, nv, false, st);
     }
     {
       Timer tm(pf, st, FAM_MIX, 0.0, 0.0);
@@ -234,7 +234,7 @@ extern "C" int cc3_transition_density(cc3_ctx* c, int no, int nv, int nchol, con
     }
     {
       Timer tm(pf, st, FAM_L3, wfl, 0.0);
-      launch_wbuild_ex(1, l2, l2M, Gl, Go3, tb, no, cubes, nv3, ss, no, nv, false, st);
+      launch_wbuild_ex(1, l2, l2M, Gl, Go3, tb, no, cubes, nv3, ss, nv, no, nv, false, st);
     }
     {
       Timer tm(pf, st, FAM_MIX, 0.0, 0.0);

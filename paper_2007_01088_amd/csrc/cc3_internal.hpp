@@ -53,6 +53,17 @@ __host__ __device__ inline void perm_pqr(int pi, int i, int j, int k, int& p, in
 // K padded to a multiple of 32 (the low-precision operand rows)
 __host__ __device__ inline int64_t kpad32(int64_t k) { return (k + 31) / 32 * 32; }
 
+// The cubes of the triple loop (W planes P0..P2, tau~ and tau~T, [x][y][z] per slot)
+// keep their rows of nv values at a pitch padded to a multiple of 8 doubles, so that the
+// row segments of 8 or 16 values that the W build, the mix and the Omega kernels move
+// start on 64-byte boundaries; the padding columns are never read.  cube_slot is the
+// doubles of one slot.  (The low-precision copies and the transition-density cubes
+// are not padded.)
+__host__ __device__ inline int cube_pitch(int nv) { return (nv + 7) & ~7; }
+__host__ __device__ inline int64_t cube_slot(int nv) {
+  return (int64_t)nv * nv * cube_pitch(nv);
+}
+
 // Device-resident, internally laid out integral blocks (all float64):
 //   Gw[r][y][z][d] = g_{ydzr}         (vv|vo), the W contraction operand (d fastest)
 //   Go[q][r][z][l] = g_{lqzr}         (oo|vo) (l fastest)
@@ -86,7 +97,7 @@ struct Plan {
   int ntri;     // unordered triples i >= j >= k, not all equal
   int batch;    // triples per batch of the triple loop
   size_t pvv_entries;  // max (triples x chunks) of one Omega or Zo launch
-  size_t cube;  // doubles per nv^3 cube
+  size_t cube;  // doubles per cube slot (cube_slot: nv x nv rows at the padded pitch)
   // byte offsets into the workspace
   size_t off_blocks;  // integral blocks (when the workspace holds them)
   size_t off_Ot1, off_Ot2, off_OtT, off_lp, off_t2N, off_Pvv, off_tri, off_flag, off_cubes;
@@ -137,12 +148,13 @@ void launch_t2N(const double* t2, double* t2N, int no, int nv, hipStream_t st);
 void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
                    double* cubes, int no, int nv, bool all_terms, hipStream_t st);
 // The W build's engine with explicit operands and output strides (doubles between
-// triples, zs, and between the three planes, ss).  mode 0: the t3 terms (X = t2,
-// XN = t2N, G = Gw, H = Go); mode 1: the left-state L3 terms of Algorithm 3 without
-// their outer-product parts (X = l2, XN = l2M, G = Gl, H = Go3).
+// triples, zs, between the three planes, ss, and between the rows of a plane, pitch).
+// mode 0: the t3 terms (X = t2, XN = t2N, G = Gw, H = Go); mode 1: the left-state L3
+// terms of Algorithm 3 without their outer-product parts (X = l2, XN = l2M, G = Gl,
+// H = Go3).
 void launch_wbuild_ex(int mode, const double* X, const double* XN, const double* G, const double* H,
-                      const int* tri, int ntri, double* cubes, int64_t zs, int64_t ss, int no,
-                      int nv, bool all_terms, hipStream_t st);
+                      const int* tri, int ntri, double* cubes, int64_t zs, int64_t ss, int pitch,
+                      int no, int nv, bool all_terms, hipStream_t st);
 // Mixed-all copies (nullable): cubesF, FP32 tau~ and tau~T, [triple][2][nv^3]; YL,
 // the split-BF16 k-major views of k_omega_lp with lpP pieces
 void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, float* cubesF,

@@ -55,7 +55,7 @@ __device__ __forceinline__ void wbuild_body(const double* __restrict__ t2,
                                             const double* __restrict__ Go,
                                             const int* __restrict__ tri,
                                             double* __restrict__ cubes, int64_t zs, int64_t ss,
-                                            int no, int nv, int tiles_m, int tiles_n,
+                                            int pitch, int no, int nv, int tiles_m, int tiles_n,
                                             int all_terms, int bx, int by, int bz) {
   typedef WCfg T;
   __shared__ double lds[T::LDS_DOUBLES];
@@ -181,7 +181,7 @@ __device__ __forceinline__ void wbuild_body(const double* __restrict__ t2,
     __syncthreads();
   }
 
-  double* out = cubes + (int64_t)z * zs + (int64_t)plane * ss + (int64_t)y * nv2;
+  double* out = cubes + (int64_t)z * zs + (int64_t)plane * ss + (int64_t)y * nv * pitch;
 #pragma unroll
   for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
@@ -190,7 +190,7 @@ __device__ __forceinline__ void wbuild_body(const double* __restrict__ t2,
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + acc_row<T>(wm, fm, lane, r);
         const int n = n0 + acc_col<T>(wn, fn, lane);
-        if (m < nv && n < nv) out[(int64_t)m * nv + n] = acc[fm][fn][r];
+        if (m < nv && n < nv) out[(int64_t)m * pitch + n] = acc[fm][fn][r];
       }
 }
 
@@ -201,31 +201,31 @@ __global__ __launch_bounds__(WCfg::NT) void k_wbuild(const double* __restrict__ 
                                                      const double* __restrict__ Go,
                                                      const int* __restrict__ tri,
                                                      double* __restrict__ cubes, int64_t zs,
-                                                     int64_t ss, int no, int nv, int tiles_m,
-                                                     int tiles_n, int all_terms) {
-  wbuild_body<MODE>(t2, t2N, Gw, Go, tri, cubes, zs, ss, no, nv, tiles_m, tiles_n, all_terms,
-                    blockIdx.x, blockIdx.y, blockIdx.z);
+                                                     int64_t ss, int pitch, int no, int nv,
+                                                     int tiles_m, int tiles_n, int all_terms) {
+  wbuild_body<MODE>(t2, t2N, Gw, Go, tri, cubes, zs, ss, pitch, no, nv, tiles_m, tiles_n,
+                    all_terms, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 void launch_wbuild_ex(int mode, const double* X, const double* XN, const double* G, const double* H,
-                      const int* tri, int ntri, double* cubes, int64_t zs, int64_t ss, int no,
-                      int nv, bool all_terms, hipStream_t st) {
+                      const int* tri, int ntri, double* cubes, int64_t zs, int64_t ss, int pitch,
+                      int no, int nv, bool all_terms, hipStream_t st) {
   typedef WCfg T;
   if (ntri <= 0) return;
   const int tm = (nv + T::BM - 1) / T::BM, tn = (nv + T::BN - 1) / T::BN;
   if (mode == 0)
     hipLaunchKernelGGL(k_wbuild<0>, dim3(nv * tm * tn, 3, ntri), dim3(T::NT), 0, st, X, XN, G, H,
-                       tri, cubes, zs, ss, no, nv, tm, tn, all_terms ? 1 : 0);
+                       tri, cubes, zs, ss, pitch, no, nv, tm, tn, all_terms ? 1 : 0);
   else
     hipLaunchKernelGGL(k_wbuild<1>, dim3(nv * tm * tn, 3, ntri), dim3(T::NT), 0, st, X, XN, G, H,
-                       tri, cubes, zs, ss, no, nv, tm, tn, all_terms ? 1 : 0);
+                       tri, cubes, zs, ss, pitch, no, nv, tm, tn, all_terms ? 1 : 0);
 }
 
 void launch_wbuild(const double* t2, const double* t2N, const Blocks& b, const int* tri, int ntri,
                    double* cubes, int no, int nv, bool all_terms, hipStream_t st) {
-  const int64_t nv3 = (int64_t)nv * nv * nv;
-  launch_wbuild_ex(0, t2, t2N, b.Gw, b.Go, tri, ntri, cubes, NSLOT * nv3, nv3, no, nv, all_terms,
-                   st);
+  const int64_t cs = cube_slot(nv);
+  launch_wbuild_ex(0, t2, t2N, b.Gw, b.Go, tri, ntri, cubes, NSLOT * cs, cs, cube_pitch(nv), no,
+                   nv, all_terms, st);
 }
 
 // t2N[p][y][x][l] = -t2[p][l][x][y]
@@ -286,18 +286,18 @@ __device__ inline void decode_block_triple(int idx, int& A, int& B, int& C) {
 
 __device__ inline double xval(const double* __restrict__ cz, int kind, int64_t nv, int a, int b,
                               int c) {
-  const int64_t nv2 = nv * nv, nv3 = nv2 * nv;
-  const double* P0 = cz + SLOT_P0 * nv3;
-  const double* P1 = cz + SLOT_P1 * nv3;
-  const double* P2 = cz + SLOT_P2 * nv3;
+  const int64_t rp = cube_pitch((int)nv), pl = nv * rp, cs = cube_slot((int)nv);
+  const double* P0 = cz + SLOT_P0 * cs;
+  const double* P1 = cz + SLOT_P1 * cs;
+  const double* P2 = cz + SLOT_P2 * cs;
   if (kind == TRI_DISTINCT)
-    return P0[b * nv2 + a * nv + c] + P1[a * nv2 + b * nv + c] + P2[c * nv2 + a * nv + b];
+    return P0[b * pl + a * rp + c] + P1[a * pl + b * rp + c] + P2[c * pl + a * rp + b];
   if (kind == TRI_IJ)  // P1 = P0, P2[c][a][b] = Q[c][a][b] + Q[c][b][a]
-    return P0[b * nv2 + a * nv + c] + P0[a * nv2 + b * nv + c] + P2[c * nv2 + a * nv + b] +
-           P2[c * nv2 + b * nv + a];
+    return P0[b * pl + a * rp + c] + P0[a * pl + b * rp + c] + P2[c * pl + a * rp + b] +
+           P2[c * pl + b * rp + a];
   // TRI_JK: P2 = P0, P1[a][b][c] = R[a][b][c] + R[a][c][b]
-  return P0[b * nv2 + a * nv + c] + P1[a * nv2 + b * nv + c] + P1[a * nv2 + c * nv + b] +
-         P0[c * nv2 + a * nv + b];
+  return P0[b * pl + a * rp + c] + P1[a * pl + b * rp + c] + P1[a * pl + c * rp + b] +
+         P0[c * pl + a * rp + b];
 }
 
 // The split-BF16 pieces of x at row `row`, column kk of view v of triple z in
@@ -334,8 +334,10 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
   const int z = by, ob = bx;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   const int kind = tri_kind(i, j, k);
-  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
-  double* cz = cubes + (int64_t)z * NSLOT * nv3;
+  const int64_t nvl = nv, nv3 = nvl * nvl * nvl;
+  // the padded cube rows: pitch rp, plane pl, slot cs
+  const int64_t rp = cube_pitch(nv), pl = nvl * rp, cs = cube_slot(nv);
+  double* cz = cubes + (int64_t)z * NSLOT * cs;
   int blk[3];
   decode_block_triple(ob, blk[0], blk[1], blk[2]);
   // With equal blocks some orientations repeat an earlier one: canon[o] is the
@@ -356,9 +358,9 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
     }
   }
   const double eijk = eps[i] + eps[j] + eps[k];
-  const double* P0 = cz + SLOT_P0 * nv3;
-  const double* P1 = cz + SLOT_P1 * nv3;
-  const double* P2 = cz + SLOT_P2 * nv3;
+  const double* P0 = cz + SLOT_P0 * cs;
+  const double* P1 = cz + SLOT_P1 * cs;
+  const double* P2 = cz + SLOT_P2 * cs;
   const int t = threadIdx.x;
   // 1. X on the orbit.  Each orientation tile is summed in up to three passes
   //    whose thread mapping makes the contiguous index of the cubes read in
@@ -376,7 +378,7 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
       const int a = A0 + u, b = B0 + v, c = C0 + w;
       double x = 0.0;
       if (a < nv && b < nv && c < nv)
-        x = P0[b * nv2 + a * nvl + c] + (kind == TRI_IJ ? P0 : P1)[a * nv2 + b * nvl + c];
+        x = P0[b * pl + a * rp + c] + (kind == TRI_IJ ? P0 : P1)[a * pl + b * rp + c];
       Xs[o * TSZ + TP(u, v, w)] = x;
     }
   }
@@ -394,8 +396,8 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
       const int a = A0 + u, b = B0 + v, c = C0 + w;
       if (a < nv && b < nv && c < nv) {
         double x;
-        if (kind == TRI_JK) x = P1[a * nv2 + c * nvl + b] + P0[c * nv2 + a * nvl + b];
-        else x = P2[c * nv2 + a * nvl + b];
+        if (kind == TRI_JK) x = P1[a * pl + c * rp + b] + P0[c * pl + a * rp + b];
+        else x = P2[c * pl + a * rp + b];
         Xs[o * TSZ + TP(u, v, w)] += x;
       }
     }
@@ -413,7 +415,7 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
         const int e = t + MIXT * h;
         const int v = e >> 6, w = (e >> 3) & 7, u = e & 7;  // pass 2: a fastest
         const int a = A0 + u, b = B0 + v, c = C0 + w;
-        if (a < nv && b < nv && c < nv) Xs[o * TSZ + TP(u, v, w)] += P2[c * nv2 + b * nvl + a];
+        if (a < nv && b < nv && c < nv) Xs[o * TSZ + TP(u, v, w)] += P2[c * pl + b * rp + a];
       }
     }
   }
@@ -461,8 +463,8 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
   }
   __syncthreads();
   // 3. write tau~[a][b][c] (w fastest) and tau~T[a][c][b] (v fastest)
-  double* TT = cz + SLOT_TT * nv3;
-  double* TTT = cz + SLOT_TTT * nv3;
+  double* TT = cz + SLOT_TT * cs;
+  double* TTT = cz + SLOT_TTT * cs;
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
     if (canon[o] != o) continue;
@@ -477,7 +479,7 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
         const int a = A0 + u, b = B0 + v, c = C0 + w;
         if (a < nv && b < nv && c < nv) {
           const double x = Xs[o * TSZ + TP(u, v, w)];
-          TT[(a * nvl + b) * nvl + c] = x;
+          TT[(a * nvl + b) * rp + c] = x;
           if (cubesF) cubesF[(int64_t)z * 2 * nv3 + (a * nvl + b) * nvl + c] = (float)x;
           if (YL) {  // view 0 at [a][b nv + c], view 1 at [b][a nv + c]
             yl_put(YL, lpP, z, 0, a, b * nvl + c, nv, x);
@@ -490,7 +492,7 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
         const int a = A0 + u, b = B0 + v, c = C0 + w;
         if (a < nv && b < nv && c < nv) {
           const double x = Xs[o * TSZ + TP(u, v, w)];
-          TTT[(a * nvl + c) * nvl + b] = x;
+          TTT[(a * nvl + c) * rp + b] = x;
           if (cubesF) cubesF[((int64_t)z * 2 + 1) * nv3 + (a * nvl + c) * nvl + b] = (float)x;
           if (YL) {  // view 2 at [c][a nv + b], view 3 at [a][c nv + b]
             yl_put(YL, lpP, z, 2, c, a * nvl + b, nv, x);
@@ -697,9 +699,9 @@ void launch_tau_export(const double* eps, const int* tri, const double* cubes, d
 // (c, b) order (Gcb).  Each of the six views U_pi of the contravariant cubes
 // (TT[x][y][z] = tau~[x][y][z], TTT[x][y][z] = tau~[x][z][y]) is affine in K in
 // one of the two orders:
-//   pi 0: tau~[a][b][c] = TT[a][(b,c)]      k contiguous, row stride nv^2
+//   pi 0: tau~[a][b][c] = TT[a][(b,c)]      k contiguous (within the padded rows)
 //   pi 3: tau~[a][c][b] = TTT[a][(b,c)]
-//   pi 1: tau~[b][a][c] = TTT[(b,c)][a]     a contiguous, k stride nv
+//   pi 1: tau~[b][a][c] = TTT[(b,c)][a]     a contiguous, k stride: the row pitch
 //   pi 5: tau~[b][c][a] = TT[(b,c)][a]
 //   pi 2: tau~[c][b][a] = TT[(c,b)][a]      the same, K in (c, b) order
 //   pi 4: tau~[c][a][b] = TTT[(c,b)][a]
@@ -763,21 +765,26 @@ __device__ __forceinline__ void omega_body(const E* __restrict__ cubes, int nslo
   const int s0 = (int)((int64_t)ch * S / nchunks), s1 = (int)((int64_t)(ch + 1) * S / nchunks);
   if (s0 >= s1) return;  // nchunks <= S, so never taken
   const bool cb = (pi == 2 || pi == 4);
-  const bool amaj = !(pi == 0 || pi == 3);  // a contiguous, k stride nv
+  const bool amaj = !(pi == 0 || pi == 3);  // a contiguous, k stride pp
   const int slot = (pi == 1 || pi == 3 || pi == 4) ? SLOT_TTT : SLOT_TT;
-  const E* U = cubes + ((int64_t)z * nslot + slot - slot0) * nv3;
+  // the FP64 cubes keep padded rows (pitch pp, slot css); the FP32 copies do not
+  const int pp = (ES == 8) ? cube_pitch(nv) : nv;
+  const int64_t css = (ES == 8) ? cube_slot(nv) : nv3;
+  const E* U = cubes + ((int64_t)z * nslot + slot - slot0) * css;
   const E* G = (cb ? Gcb : Gbc) + (int64_t)r * (nv + no) * nv2;
-  const int ask = amaj ? nv : 1;  // k stride of A in doubles
-  // tile origins (k = 0) of the two operands
-  const E* A0 = amaj ? U + m0 : U + (int64_t)m0 * K;
+  const int ask = amaj ? pp : 1;  // k stride of A in elements (within a padded row for !amaj)
+  // tile origins (k = 0) of the two operands; the A rows of the views with k
+  // contiguous are nv padded rows (b, .) apart: nv * pp elements
+  const E* A0 = amaj ? U + m0 : U + (int64_t)m0 * nv * pp;
   const E* B0 = G + (int64_t)n0 * K;
 
   // Per-thread part of every stage.  A: element e at (row/column x_e, k_e) of the
-  // stage, global byte offset aoff[e] + k_e * ask * 8 from the stage origin
-  // A0 + k0 * ask, LDS slot alds[e].  Rows past nv repeat row nv - 1 (their outputs
-  // are never stored).  B rows n < nv are G rows n; rows n >= nv (only in the last
-  // column tile) read the Omega1 row nv + q.  Offsets are relative to the tile
-  // origin: below 191 rows of stride nv^2 <= 2^20, so below 2^31 bytes.
+  // stage, global byte offset aoff[e] plus that of k_e from the stage origin (k_e ask
+  // elements, or for k = (b, c) in padded rows the columns c past nv skipped), LDS
+  // slot alds[e].  Rows past nv repeat row nv - 1 (their outputs are never stored).
+  // B rows n < nv are G rows n; rows n >= nv (only in the last column tile) read the
+  // Omega1 row nv + q.  Offsets are relative to the tile origin: below 191 rows of
+  // stride nv * pp <= 2^20, so below 2^31 bytes.
   const int tid = threadIdx.x;
   constexpr int RP = T::NT / T::BK;  // k-fast mapping: 32 rows per element step
   constexpr int KP = T::NT / T::BM;  // a-fast mapping: 4 k per element step
@@ -797,7 +804,7 @@ __device__ __forceinline__ void omega_body(const E* __restrict__ cubes, int nslo
 #pragma unroll
     for (int e = 0; e < T::EA; ++e) {
       ak[e] = kt;
-      aoff[e] = (unsigned)(min(m0 + xt + e * RP, nv - 1) - m0) * (unsigned)K * ES;
+      aoff[e] = (unsigned)(min(m0 + xt + e * RP, nv - 1) - m0) * (unsigned)(nv * pp) * ES;
       alds[e] = lds_idx<T::BK>(kt, xt + e * RP, T::LDA);
     }
   }
@@ -816,15 +823,31 @@ __device__ __forceinline__ void omega_body(const E* __restrict__ cubes, int nslo
   bool inb = true;
   auto fetch = [&](int s) {
     const int k0 = s * T::BK;
-    const BufRsrc sa = buf_rsrc(A0 + (int64_t)k0 * ask), sb = buf_rsrc(B0 + k0);
+    const BufRsrc sb = buf_rsrc(B0 + k0);
     const int kl = K - 1 - k0;  // last valid k of this stage (only the last stage is partial)
     amask = 0u;
+    if (amaj) {
+      const BufRsrc sa = buf_rsrc(A0 + (int64_t)k0 * ask);
 #pragma unroll
-    for (int e = 0; e < T::EA; ++e) {
-      const bool in = ak[e] <= kl;
-      const int kc = in ? ak[e] : kl;  // k past K reads a valid element
-      ra[e] = M::load(sa, aoff[e] + (unsigned)kc * ask8);
-      amask |= in ? (1u << e) : 0u;
+      for (int e = 0; e < T::EA; ++e) {
+        const bool in = ak[e] <= kl;
+        const int kc = in ? ak[e] : kl;  // k past K reads a valid element
+        ra[e] = M::load(sa, aoff[e] + (unsigned)kc * ask8);
+        amask |= in ? (1u << e) : 0u;
+      }
+    } else {
+      // k = b nv + c lies at b pp + c: the stage starts at (b0, c0), and the lane's k
+      // (the same for all its elements) skips pp - nv columns per row end it passes
+      const int b0 = k0 / nv, c0 = k0 - b0 * nv;
+      const BufRsrc sa = buf_rsrc(A0 + (int64_t)b0 * pp + c0);
+      const bool in = kt <= kl;
+      const int kc = in ? kt : kl;  // k past K reads a valid element
+      const unsigned ko = (unsigned)(kc + (pp != nv ? (c0 + kc) / nv * (pp - nv) : 0)) * ES;
+#pragma unroll
+      for (int e = 0; e < T::EA; ++e) {
+        ra[e] = M::load(sa, aoff[e] + ko);
+        amask |= in ? (1u << e) : 0u;
+      }
     }
     inb = kt <= kl;
     const unsigned kb = (unsigned)(inb ? kt : kl) * ES;
@@ -978,15 +1001,17 @@ __device__ inline int pairs_with_p(const int* __restrict__ tri, int ntri, int p,
   return n;
 }
 
-// The view of U_pi[a, b, c] at fixed b as a strided (a, c) matrix: base + b * sbb, (sm, sk).
-__device__ inline void u_view(int pi, int nv, int& slot, int& sbb, int& sm, int& sk) {
+// The view of U_pi[a, b, c] at fixed b as a strided (a, c) matrix: base + b * sbb, (sm, sk),
+// in the cubes [x][y][z] with the row pitch rp (x stride nv rp, y stride rp).
+__device__ inline void u_view(int pi, int nv, int rp, int& slot, int& sbb, int& sm, int& sk) {
+  const int pl = nv * rp;
   switch (pi) {
-    case 0: slot = SLOT_TT; sbb = nv; sm = nv * nv; sk = 1; break;    // tau~[a][b][c]
-    case 1: slot = SLOT_TT; sbb = nv * nv; sm = nv; sk = 1; break;    // tau~[b][a][c]
-    case 2: slot = SLOT_TT; sbb = nv; sm = 1; sk = nv * nv; break;    // tau~[c][b][a]
-    case 3: slot = SLOT_TTT; sbb = nv; sm = nv * nv; sk = 1; break;   // tau~T[a][b][c]
-    case 4: slot = SLOT_TTT; sbb = nv; sm = 1; sk = nv * nv; break;   // tau~T[c][b][a]
-    default: slot = SLOT_TT; sbb = nv * nv; sm = 1; sk = nv; break;   // tau~[b][c][a]
+    case 0: slot = SLOT_TT; sbb = rp; sm = pl; sk = 1; break;    // tau~[a][b][c]
+    case 1: slot = SLOT_TT; sbb = pl; sm = rp; sk = 1; break;    // tau~[b][a][c]
+    case 2: slot = SLOT_TT; sbb = rp; sm = 1; sk = pl; break;    // tau~[c][b][a]
+    case 3: slot = SLOT_TTT; sbb = rp; sm = pl; sk = 1; break;   // tau~T[a][b][c]
+    case 4: slot = SLOT_TTT; sbb = rp; sm = 1; sk = pl; break;   // tau~T[c][b][a]
+    default: slot = SLOT_TT; sbb = pl; sm = 1; sk = rp; break;   // tau~[b][c][a]
   }
 }
 
@@ -1029,7 +1054,7 @@ __device__ __forceinline__ void omega_oo_body(const double* __restrict__ cubes,
   int bb[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) bb[j] = min(NB * bp + j, nv - 1);
-  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
+  const int64_t nvl = nv, nv2 = nvl * nvl;
   d4v acc[NB][FNO];
 #pragma unroll
   for (int j = 0; j < NB; ++j)
@@ -1050,8 +1075,8 @@ __device__ __forceinline__ void omega_oo_body(const double* __restrict__ cubes,
     const int t = it / cs, c0 = (it - t * cs) * 16;
     const int zp = lz[t], zz = zp / 6, pi = zp % 6;
     int slot, sbb, sm, sk;
-    u_view(pi, nv, slot, sbb, sm, sk);
-    const double* ub = cubes + ((int64_t)zz * NSLOT + slot) * nv3;
+    u_view(pi, nv, cube_pitch(nv), slot, sbb, sm, sk);
+    const double* ub = cubes + ((int64_t)zz * NSLOT + slot) * cube_slot(nv);
     ccont = (sk == 1);
     if (ccont) {  // element i: row a0 + 4 i + kq, c = c0 + m
       const int c = c0 + m;
@@ -1223,16 +1248,16 @@ __global__ __launch_bounds__(ZvCfg::NT) void k_zv(const double* __restrict__ cub
   cnt = pairs_with_p(tri, ntri, p, no, lz, lqr, cz);
   const int n = cnt;
   if (n == 0) return;
-  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
+  const int64_t nvl = nv, nv2 = nvl * nvl;
   const int cs = (nv + T::BK - 1) / T::BK;
   auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
     const int t = s / cs;
     k0 = (s % cs) * T::BK;
     const int zp = lz[t], z = zp / 6, pi = zp % 6;
     int slot, sbb, sm, sk;
-    u_view(pi, nv, slot, sbb, sm, sk);
-    A = make_opnd(cubes + ((int64_t)z * NSLOT + slot) * nv3 + (int64_t)b * sbb, sm, sk, nv, nv,
-                  sm == 1);
+    u_view(pi, nv, cube_pitch(nv), slot, sbb, sm, sk);
+    A = make_opnd(cubes + ((int64_t)z * NSLOT + slot) * cube_slot(nv) + (int64_t)b * sbb, sm, sk,
+                  nv, nv, sm == 1);
     B = make_opnd(Jo + (int64_t)lqr[t] * nv2, nv, 1, nv, nv, false);  // rows d, k = c
   };
   d4v acc[T::FM][T::FN];
@@ -1277,10 +1302,10 @@ __global__ __launch_bounds__(ZoCfg::NT) void k_zo(const double* __restrict__ cub
   const int bb0 = (int)((int64_t)bc * nv / nbchunks);
   const int bb1 = (int)((int64_t)(bc + 1) * nv / nbchunks);
   if (bb0 >= bb1) return;
-  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
+  const int64_t nvl = nv, nv2 = nvl * nvl;
   int slot, sbb, sm, sk;
-  u_view(pi, nv, slot, sbb, sm, sk);
-  const double* ub = cubes + ((int64_t)z * NSLOT + slot) * nv3;
+  u_view(pi, nv, cube_pitch(nv), slot, sbb, sm, sk);
+  const double* ub = cubes + ((int64_t)z * NSLOT + slot) * cube_slot(nv);
   const int cs = (nv + T::BK - 1) / T::BK;
   auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
     const int b = bb0 + s / cs;
@@ -1473,9 +1498,10 @@ __global__ __launch_bounds__(WCfg::NT) void k_pack_wbuild(const PackJob* __restr
     const unsigned local = item - J.first[PK_W];
     const int tm = (J.nv + T::BM - 1) / T::BM, tn = (J.nv + T::BN - 1) / T::BN;
     const unsigned gx = (unsigned)J.nv * tm * tn;
-    const int64_t nv3 = (int64_t)J.nv * J.nv * J.nv;
-    wbuild_body<0>(J.t2, J.t2N, J.Gw, J.Go, J.tri, J.cubes, NSLOT * nv3, nv3, J.no, J.nv, tm, tn,
-                   0, (int)(local % gx), (int)((local / gx) % 3), (int)(local / (gx * 3)));
+    const int64_t cs = cube_slot(J.nv);
+    wbuild_body<0>(J.t2, J.t2N, J.Gw, J.Go, J.tri, J.cubes, NSLOT * cs, cs, cube_pitch(J.nv), J.no,
+                   J.nv, tm, tn, 0, (int)(local % gx), (int)((local / gx) % 3),
+                   (int)(local / (gx * 3)));
     __syncthreads();
   }
 }

@@ -468,8 +468,9 @@ __device__ __forceinline__ void wbuild_lp_body(
   }
 
   // the FP32/BF16 MFMA leaves D[row = 4 (lane/16) + r][col = lane%16] in register r
-  const int64_t nv2 = (int64_t)nv * nv, nv3 = nv2 * nv;
-  double* dst = cubes + ((int64_t)z * 5 + plane) * nv3 + (int64_t)y * nv2;
+  // the padded rows of the triple loop's cubes
+  const int64_t rp = cube_pitch(nv);
+  double* dst = cubes + ((int64_t)z * 5 + plane) * cube_slot(nv) + (int64_t)y * nv * rp;
 #pragma unroll
   for (int fm = 0; fm < LFM; ++fm)
 #pragma unroll
@@ -479,7 +480,7 @@ __device__ __forceinline__ void wbuild_lp_body(
         const int m = m0 + (wm * LFM + fm) * 16 + 4 * (lane >> 4) + r;
         const int n = n0 + (wn * LFN + fn) * 16 + (lane & 15);
         if (m < nv && n < nv)
-          dst[(int64_t)m * nv + n] = accd[fm][fn][r] + ((double)acc1[fm][fn][r] + (double)acc2[fm][fn][r]);
+          dst[(int64_t)m * rp + n] = accd[fm][fn][r] + ((double)acc1[fm][fn][r] + (double)acc2[fm][fn][r]);
       }
 }
 
