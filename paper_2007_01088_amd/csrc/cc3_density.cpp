@@ -41,7 +41,7 @@ const int kPermH[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1},
 void make_dplan(int no, int nv, int nchol, DPlan* p) {
   const size_t o = no, v = nv, J = nchol;
   p->no = no; p->nv = nv; p->nchol = nchol;
-  p->cube = v * v * v;
+  p->cube = (size_t)cube_slot(nv);  // one padded cube
   p->npairs = no * (no + 1) / 2;
   p->htri.clear(); p->htask.clear(); p->task0.clear(); p->ntasks.clear(); p->pi.clear();
   p->pj.clear();
@@ -190,7 +190,7 @@ extern "C" int cc3_transition_density(cc3_ctx* c, int no, int nv, int nchol, con
     cs.M = take(J * o * o * 8);
   }
   double* gtmp = (double*)(base + p.off_cubes + p.chol_bytes);
-  const int64_t nv3 = (int64_t)p.cube, ss = (int64_t)no * nv3;
+  const int64_t csl = (int64_t)p.cube, ss = (int64_t)no * csl;
   std::lock_guard<std::mutex> g(c->mu);
   Profiler* pf = &c->prof;
   HIPCHK(hipMemcpyAsync(dtri, p.htri.data(), p.htri.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -226,7 +226,7 @@ extern "C" int cc3_transition_density(cc3_ctx* c, int no, int nv, int nchol, con
     const double wfl = wbuild_flops(no, nv, kinds.data(), no);
     {
       Timer tm(pf, st, FAM_W, wfl, 0.0);
-      launch_wbuild_ex(0, t2, t2N, Gw, Go, tb, no, cubes, nv3, ss, nv, no, nv, false, st);
+      launch_wbuild_ex(0, t2, t2N, Gw, Go, tb, no, cubes, csl, ss, cube_pitch(nv), no, nv, false, st);
     }
     {
       Timer tm(pf, st, FAM_MIX, 0.0, 0.0);
@@ -234,7 +234,7 @@ extern "C" int cc3_transition_density(cc3_ctx* c, int no, int nv, int nchol, con
     }
     {
       Timer tm(pf, st, FAM_L3, wfl, 0.0);
-      launch_wbuild_ex(1, l2, l2M, Gl, Go3, tb, no, cubes, nv3, ss, nv, no, nv, false, st);
+      launch_wbuild_ex(1, l2, l2M, Gl, Go3, tb, no, cubes, csl, ss, cube_pitch(nv), no, nv, false, st);
     }
     {
       Timer tm(pf, st, FAM_MIX, 0.0, 0.0);

@@ -46,11 +46,11 @@ __global__ __launch_bounds__(CdCfg::NT) void k_d3_cd(const double* __restrict__ 
   const int m = blockIdx.y, t = blockIdx.z;
   const int ch = blockIdx.x % nch, tile = blockIdx.x / nch;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
-  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
-  const int64_t S[3] = {nv2, nvl, 1};
+  const int64_t nvl = nv, nv2 = nvl * nvl, rp = cube_pitch(nv), csl = cube_slot(nv);
+  const int64_t S[3] = {nvl * rp, rp, 1};  // axis strides of the padded cubes
   const int u = (m == 0) ? 1 : 0, v = (m == 2) ? 1 : 2;  // the other two axes, u < v
-  const double* Lc = cubes + D3_LC * ss + (int64_t)(z0 + t) * nv3;
-  const double* Ta = cubes + D3_TAU * ss + (int64_t)(z0 + t) * nv3;
+  const double* Lc = cubes + D3_LC * ss + (int64_t)(z0 + t) * csl;
+  const double* Ta = cubes + D3_TAU * ss + (int64_t)(z0 + t) * csl;
   const int u0 = (int)((int64_t)ch * nv / nch), u1 = (int)((int64_t)(ch + 1) * nv / nch);
   const int cs = (nv + T::BK - 1) / T::BK;
   auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
@@ -113,10 +113,10 @@ __global__ __launch_bounds__(VecCfg::NT) void k_d3_vec(const double* __restrict_
   const int z = tk[0], ord = tk[1], p = tk[2], q = tk[3];
   const int ch = blockIdx.x % nch, tile = blockIdx.x / nch;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
-  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
-  const int64_t S[3] = {nv2, nvl, 1};
+  const int64_t nvl = nv, nv2 = nvl * nvl, rp = cube_pitch(nv), csl = cube_slot(nv);
+  const int64_t S[3] = {nvl * rp, rp, 1};  // axis strides of the padded cubes
   const int axa = kPerm[ord][0], axb = kPerm[ord][1], axc = kPerm[ord][2];
-  const double* U = cubes + (KC ? D3_TAUC : D3_LC) * ss + (int64_t)z * nv3;
+  const double* U = cubes + (KC ? D3_TAUC : D3_LC) * ss + (int64_t)z * csl;
   // K = (a, b), split over its outer index.  When the view's a is the cube's contiguous
   // axis, K runs in (b, a) order instead, so that the A loads run along a; B then reads
   // the pair-symmetric copy of its row, t2[l][q][a][b] = t2[q][l][b][a] and
@@ -204,16 +204,17 @@ __global__ __launch_bounds__(GrCfg::NT) void k_d3_gram(const double* __restrict_
   __shared__ double lds[T::LDS_DOUBLES];
   const int ch = blockIdx.x % nch, tile = blockIdx.x / nch;
   const int m0 = (tile / tiles_n) * T::BM, n0 = (tile % tiles_n) * T::BN;
-  const int64_t nv3 = (int64_t)nv * nv * nv;
-  const int K = (int)nv3;
+  // K = the whole padded cube; its padding columns hold zeros in both operands
+  const int64_t cs = cube_slot(nv);
+  const int K = (int)cs;
   const int S = (K + T::BK - 1) / T::BK;
   const int s0 = (int)((int64_t)ch * S / nch), s1 = (int)((int64_t)(ch + 1) * S / nch);
-  const double* Lc = cubes + D3_LC * ss + (int64_t)z0 * nv3;
-  const double* Ta = cubes + D3_TAU * ss + (int64_t)z0 * nv3;
+  const double* Lc = cubes + D3_LC * ss + (int64_t)z0 * cs;
+  const double* Ta = cubes + D3_TAU * ss + (int64_t)z0 * cs;
   auto ops = [&](int s, Opnd& A, Opnd& B, int& k0) {
     k0 = (s0 + s) * T::BK;
-    A = make_opnd(Lc, nv3, 1, nz, K, false);
-    B = make_opnd(Ta, nv3, 1, nz, K, false);
+    A = make_opnd(Lc, cs, 1, nz, K, false);
+    B = make_opnd(Ta, cs, 1, nz, K, false);
   };
   d4v acc[T::FM][T::FN];
   zero_acc<T>(acc);
@@ -233,14 +234,23 @@ __global__ __launch_bounds__(GrCfg::NT) void k_d3_gram(const double* __restrict_
 }
 
 // D_lk[l][k] += scale * sum over chunks of M[k][l]
-__global__ void k_d3_red_lk(const double* __restrict__ P, double* __restrict__ D, int no, int nch,
-                            double scale) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= no * no) return;
+// One workgroup per element D_lk[l][k]: thread t sums the chunks t, t + 256, ... in
+// order, then a fixed binary tree over the 256 partial sums (deterministic).
+__global__ __launch_bounds__(256) void k_d3_red_lk(const double* __restrict__ P,
+                                                   double* __restrict__ D, int no, int nch,
+                                                   double scale) {
+  __shared__ double part[256];
+  const int e = blockIdx.x;
   const int l = e / no, k = e % no;
   double s = 0.0;
-  for (int ch = 0; ch < nch; ++ch) s += P[(int64_t)ch * no * no + (int64_t)k * no + l];
-  D[e] += scale * s;
+  for (int ch = threadIdx.x; ch < nch; ch += 256) s += P[(int64_t)ch * no * no + (int64_t)k * no + l];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) D[e] += scale * part[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -327,7 +337,7 @@ int d3_vec_chunks(int nv, int ntask, int ncol) {
 
 int d3_gram_chunks(int nv, int nz) {
   const int t = (nz + GrCfg::BM - 1) / GrCfg::BM;
-  const int S = (nv * nv * nv + GrCfg::BK - 1) / GrCfg::BK;
+  const int S = (int)((cube_slot(nv) + GrCfg::BK - 1) / GrCfg::BK);
   int n = (2048 + t * t - 1) / (t * t);
   return n > S ? S : n;
 }
@@ -380,8 +390,7 @@ void launch_d3_gram(const double* cubes, int64_t ss, int z0, int nz, double* P, 
   const int nch = d3_gram_chunks(nv, nz);
   hipLaunchKernelGGL(k_d3_gram, dim3(t * t * nch), dim3(T::NT), 0, st, cubes, ss, z0, nz, P, nv,
                      nch, t);
-  hipLaunchKernelGGL(k_d3_red_lk, dim3(nblk((int64_t)no * no, 256)), dim3(256), 0, st, P, Dlk, no,
-                     nch, scale);
+  hipLaunchKernelGGL(k_d3_red_lk, dim3(no * no), dim3(256), 0, st, P, Dlk, no, nch, scale);
 }
 
 void launch_d3_ld(const double* Y, const double* t2, double* P, double* Dld, int no, int nv,

@@ -562,10 +562,12 @@ __global__ __launch_bounds__(512) void k_mix3(const double* __restrict__ eps,
   const int z = blockIdx.y, ob = blockIdx.x;
   const int i = tri[3 * z], j = tri[3 * z + 1], k = tri[3 * z + 2];
   const int kind = tri_kind(i, j, k);
-  const int64_t nvl = nv, nv2 = nvl * nvl, nv3 = nv2 * nvl;
-  const double* P0 = cubes + D3_P0 * ss + (int64_t)z * nv3;
-  const double* P1 = cubes + D3_P1 * ss + (int64_t)z * nv3;
-  const double* P2 = cubes + D3_P2 * ss + (int64_t)z * nv3;
+  const int64_t nvl = nv;
+  // the padded cube rows: pitch rp, plane pl, cube cs
+  const int64_t rp = cube_pitch(nv), pl = nvl * rp, cs = cube_slot(nv);
+  const double* P0 = cubes + D3_P0 * ss + (int64_t)z * cs;
+  const double* P1 = cubes + D3_P1 * ss + (int64_t)z * cs;
+  const double* P2 = cubes + D3_P2 * ss + (int64_t)z * cs;
   int blk[3];
   decode_block_triple(ob, blk[0], blk[1], blk[2]);
   int canon[6];
@@ -594,7 +596,7 @@ __global__ __launch_bounds__(512) void k_mix3(const double* __restrict__ eps,
     const int a = blk[q0] * MT + u, b = blk[q1] * MT + v, c = blk[q2] * MT + w;
     double x = 0.0;
     if (a < nv && b < nv && c < nv) {
-      x = P0[b * nv2 + a * nvl + c] + (kind == TRI_IJ ? P0 : P1)[a * nv2 + b * nvl + c];
+      x = P0[b * pl + a * rp + c] + (kind == TRI_IJ ? P0 : P1)[a * pl + b * rp + c];
       if (LMODE) x += l3_outer(l1, l2, Jo, F, no, nvl, i, j, k, a, b, c);
     }
     Xs[o * TSZ + TP(u, v, w)] = x;
@@ -609,8 +611,8 @@ __global__ __launch_bounds__(512) void k_mix3(const double* __restrict__ eps,
     const int a = blk[q0] * MT + uu, b = blk[q1] * MT + vv, c = blk[q2] * MT + ww;
     if (a < nv && b < nv && c < nv) {
       double x;
-      if (kind == TRI_JK) x = P1[a * nv2 + c * nvl + b] + P0[c * nv2 + a * nvl + b];
-      else x = P2[c * nv2 + a * nvl + b];
+      if (kind == TRI_JK) x = P1[a * pl + c * rp + b] + P0[c * pl + a * rp + b];
+      else x = P2[c * pl + a * rp + b];
       Xs[o * TSZ + TP(uu, vv, ww)] += x;
     }
   }
@@ -623,21 +625,29 @@ __global__ __launch_bounds__(512) void k_mix3(const double* __restrict__ eps,
       orient(o, q0, q1, q2);
       const int vv = t >> 6, ww = (t >> 3) & 7, uu = t & 7;  // a fastest
       const int a = blk[q0] * MT + uu, b = blk[q1] * MT + vv, c = blk[q2] * MT + ww;
-      if (a < nv && b < nv && c < nv) Xs[o * TSZ + TP(uu, vv, ww)] += P2[c * nv2 + b * nvl + a];
+      if (a < nv && b < nv && c < nv) Xs[o * TSZ + TP(uu, vv, ww)] += P2[c * pl + b * rp + a];
     }
   }
   __syncthreads();
-  // the denominators and the contravariant combination; outputs in [a][b][c] order
+  // the denominators and the contravariant combination; outputs in [a][b][c] order,
+  // with zeros in the padding columns c >= nv of each row (the Gram contraction runs
+  // over whole padded cubes)
   const double eijk = eps[i] + eps[j] + eps[k];
-  double* outC = cubes + (LMODE ? D3_LC : D3_TAUC) * ss + (int64_t)z * nv3;
-  double* outT = cubes + D3_TAU * ss + (int64_t)z * nv3;
+  double* outC = cubes + (LMODE ? D3_LC : D3_TAUC) * ss + (int64_t)z * cs;
+  double* outT = cubes + D3_TAU * ss + (int64_t)z * cs;
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
     if (canon[o] != o) continue;
     int q0, q1, q2;
     orient(o, q0, q1, q2);
     const int a = blk[q0] * MT + u, b = blk[q1] * MT + v, c = blk[q2] * MT + w;
-    if (!(a < nv && b < nv && c < nv)) continue;
+    if (!(a < nv && b < nv)) continue;
+    if (c >= nv) {  // a padding column (c < rp: the blocks cover exactly rp values)
+      const int64_t e = (a * nvl + b) * rp + c;
+      outC[e] = 0.0;
+      if (!LMODE) outT[e] = 0.0;
+      continue;
+    }
     const int o_acb = canon[orient_of(q0, q2)], o_cba = canon[orient_of(q2, q1)];
     const int o_bac = canon[orient_of(q1, q0)], o_bca = canon[orient_of(q1, q2)];
     const int o_cab = canon[orient_of(q2, q0)];
@@ -648,7 +658,7 @@ __global__ __launch_bounds__(512) void k_mix3(const double* __restrict__ eps,
     const double x_bca = Xs[o_bca * TSZ + TP(v, w, u)];
     const double x_cab = Xs[o_cab * TSZ + TP(w, u, v)];
     const double D = eps[no + a] + eps[no + b] + eps[no + c] - eijk - (LMODE ? omega : 0.0);
-    const int64_t e = (a * nvl + b) * nvl + c;
+    const int64_t e = (a * nvl + b) * rp + c;
     outC[e] = -(4.0 * x_abc - 2.0 * x_acb - 2.0 * x_cba - 2.0 * x_bac + x_bca + x_cab) / D;
     if (!LMODE) outT[e] = -x_abc / D;
   }
