@@ -53,6 +53,19 @@ __host__ __device__ inline void perm_pqr(int pi, int i, int j, int k, int& p, in
 // K padded to a multiple of 32 (the low-precision operand rows)
 __host__ __device__ inline int64_t kpad32(int64_t k) { return (k + 31) / 32 * 32; }
 
+// K of the split-BF16 Omega contraction (the mixed-all form): the pair (x, y) of the
+// contracted virtual indices in 8 x 8 blocks, kb = ((X nb + Y) 8 + x % 8) 8 + y % 8 with
+// X = x / 8, Y = y / 8 and nb = ceil(nv / 8), so that the 64 values of one block, which
+// the mix holds together, are contiguous; positions with x or y >= nv hold zeros.
+__host__ __device__ inline int64_t lp_kb_len(int nv) {
+  const int64_t nb = (nv + 7) / 8;
+  return nb * nb * 64;
+}
+__host__ __device__ inline int64_t lp_kb(int x, int y, int nv) {
+  const int nb = (nv + 7) / 8;
+  return ((int64_t)((x >> 3) * nb + (y >> 3)) * 8 + (x & 7)) * 8 + (y & 7);
+}
+
 // The cubes of the triple loop (W planes P0..P2, tau~ and tau~T, [x][y][z] per slot)
 // keep their rows of nv values at a pitch padded to a multiple of 8 doubles, so that the
 // row segments of 8 or 16 values that the W build, the mix and the Omega kernels move

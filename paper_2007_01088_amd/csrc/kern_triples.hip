@@ -300,13 +300,13 @@ __device__ inline double xval(const double* __restrict__ cz, int kind, int64_t n
          P0[c * pl + a * rp + b];
 }
 
-// The split-BF16 pieces of x at row `row`, column kk of view v of triple z in
-// YL[z][4][P][nv][Kp] (Kp = kpad32(nv^2)).
-__device__ inline void yl_put(uint16_t* YL, int P, int z, int v, int row, int64_t kk, int nv,
+// The split-BF16 pieces of x at row `row` and K pair (kx, ky) of view v of triple z in
+// YL[z][4][P][nv][Kb] (Kb = lp_kb_len(nv), the pair at lp_kb(kx, ky)).
+__device__ inline void yl_put(uint16_t* YL, int P, int z, int v, int row, int kx, int ky, int nv,
                               double x) {
-  const int64_t Kp = kpad32((int64_t)nv * nv);
-  uint16_t* base = YL + (((int64_t)z * 4 + v) * P * nv + row) * Kp + kk;
-  const int64_t ps = (int64_t)nv * Kp;
+  const int64_t Kb = lp_kb_len(nv);
+  uint16_t* base = YL + (((int64_t)z * 4 + v) * P * nv + row) * Kb + lp_kb(kx, ky, nv);
+  const int64_t ps = (int64_t)nv * Kb;
   if (P == 2) {
     uint16_t pc[2];
     split_bf16<2>(x, pc);
@@ -481,9 +481,9 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
           const double x = Xs[o * TSZ + TP(u, v, w)];
           TT[(a * nvl + b) * rp + c] = x;
           if (cubesF) cubesF[(int64_t)z * 2 * nv3 + (a * nvl + b) * nvl + c] = (float)x;
-          if (YL) {  // view 0 at [a][b nv + c], view 1 at [b][a nv + c]
-            yl_put(YL, lpP, z, 0, a, b * nvl + c, nv, x);
-            yl_put(YL, lpP, z, 1, b, a * nvl + c, nv, x);
+          if (YL) {  // view 0 at [a][(b, c)], view 1 at [b][(a, c)]
+            yl_put(YL, lpP, z, 0, a, b, c, nv, x);
+            yl_put(YL, lpP, z, 1, b, a, c, nv, x);
           }
         }
       }
@@ -494,9 +494,9 @@ __device__ __forceinline__ void mix_body(const double* __restrict__ eps,
           const double x = Xs[o * TSZ + TP(u, v, w)];
           TTT[(a * nvl + c) * rp + b] = x;
           if (cubesF) cubesF[((int64_t)z * 2 + 1) * nv3 + (a * nvl + c) * nvl + b] = (float)x;
-          if (YL) {  // view 2 at [c][a nv + b], view 3 at [a][c nv + b]
-            yl_put(YL, lpP, z, 2, c, a * nvl + b, nv, x);
-            yl_put(YL, lpP, z, 3, a, c * nvl + b, nv, x);
+          if (YL) {  // view 2 at [c][(a, b)], view 3 at [a][(c, b)]
+            yl_put(YL, lpP, z, 2, c, a, b, nv, x);
+            yl_put(YL, lpP, z, 3, a, c, b, nv, x);
           }
         }
       }
@@ -852,7 +852,8 @@ __device__ __forceinline__ void omega_body(const E* __restrict__ cubes, int nslo
       const BufRsrc sa = buf_rsrc(A0 + (int64_t)b0 * pp + c0);
       const bool in = kt <= kl;
       const int kc = in ? kt : kl;  // k past K reads a valid element
-      const unsigned ko = (unsigned)(kc + (pp != nv ? (c0 + kc) / nv * (pp - nv) : 0)) * ES;
+      const unsigned ko =
+          (unsigned)(kc + (ES == 8 && pp != nv ? (c0 + kc) / nv * (pp - nv) : 0)) * ES;
 #pragma unroll
       for (int e = 0; e < T::EA; ++e) {
         ra[e] = M::load(sa, aoff[e] + ko);
@@ -1426,9 +1427,10 @@ int omega_kchunks(int nv, int ntri, bool fp32acc) {
   const int cap = S / 16 > 1 ? S / 16 : 1;
   if (nch > cap) nch = cap;
   // chunks that the MFMA sums in FP32 (the mixed-all forms) hold at most 4096 k, so
-  // that their rounding does not grow with the batch
+  // that their rounding does not grow with the batch (the split-BF16 form's K is the
+  // blocked lp_kb_len(nv) >= nv^2)
   if (fp32acc) {
-    const int need = (nv * nv + 4095) / 4096;
+    const int need = (int)((lp_kb_len(nv) + 4095) / 4096);
     if (nch < need) nch = need > 8 ? (need + 7) / 8 * 8 : need;
   }
   return nch < 1 ? 1 : nch;

@@ -498,9 +498,10 @@ __global__ __launch_bounds__(LNT, E::MINW) void k_wbuild_lp(
 // ---------------------------------------------------------------------------
 // The long-K GEMM of k_omega per (triple, permutation, 128 x 128 tile, K chunk):
 //   Pvv[z][pi][chunk][a][n] = sum_{kk in chunk} Y_v(pi)[a][kk] G[r][n'][kk],
-// with every operand row k-contiguous and zero-padded to Kp = kpad32(nv^2):
+// with every operand row k-contiguous, K = (x, y) in the blocked order lp_kb (8 x 8
+// blocks of 64 contiguous values, Kp = lp_kb_len(nv), zero where x or y >= nv):
 //   YL[z][v][piece][a][kk]: the four k-major views of tau~ that the six
-//     permutations need, kk = x nv + y, written by k_mix:
+//     permutations need, kk = lp_kb(x, y), written by k_mix:
 //     v = 0: tau~[a][x][y] (pi 0);  1: tau~[x][a][y] (pi 1, 4);
 //     v = 2: tau~[x][y][a] (pi 2, 5);  3: tau~[a][y][x] (pi 3);
 //   GL[piece][r][n'][kk]: Gbc (or Gcb for pi 2, 4) rows, n' = n for n < nv and
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
   perm_pqr(pi, i, j, k, p, q, r);
   const int ch = blockIdx.x % nchunks, tile = blockIdx.x / nchunks;
   const int m0 = (tile / tiles_n) * LBM, n0 = (tile % tiles_n) * LBN;
-  const int64_t Kp = kpad32((int64_t)nv * nv);
+  const int64_t Kp = lp_kb_len(nv);  // the blocked K of the views and of GL
   const int S = (int)(Kp / E::BK);
   const int s0 = (int)((int64_t)ch * S / nchunks), s1 = (int)((int64_t)(ch + 1) * S / nchunks);
   if (s0 >= s1) return;
@@ -585,42 +586,69 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
       }
 }
 
-// Zero the K padding [nv^2, Kp) of `rows` rows of stride Kp (the YL views; k_mix
-// writes only kk < nv^2).
-__global__ void k_zero_pad(uint16_t* __restrict__ p, int64_t rows, int64_t K, int64_t Kp) {
-  const int64_t w = Kp - K;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rows * w;
+// Zero n 16-bit values (the YL views, whose blocked K positions with an index past nv
+// k_mix never writes), 8 per thread and pass.
+__global__ void k_zero_pad(uint16_t* __restrict__ p, int64_t n) {
+  const int64_t n8 = n / 8;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n8;
        e += (int64_t)gridDim.x * blockDim.x)
-    p[(e / w) * Kp + K + e % w] = 0;
+    ((uint4*)p)[e] = make_uint4(0u, 0u, 0u, 0u);
+  for (int64_t e = n8 * 8 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = 0;
 }
 
 void launch_lp_zero_pad(void* YL, int64_t rows, int nv, hipStream_t st) {
-  const int64_t K = (int64_t)nv * nv, Kp = kpad32(K);
-  if (Kp == K || rows == 0) return;
-  unsigned g = nblk(rows * (Kp - K), 256);
+  if (nv % 8 == 0 || rows == 0) return;  // no position of the blocked K lies past nv
+  const int64_t n = rows * lp_kb_len(nv);
+  unsigned g = nblk(n / 8 + 1, 256);
   if (g > 65536) g = 65536;
-  hipLaunchKernelGGL(k_zero_pad, dim3(g), dim3(256), 0, st, (uint16_t*)YL, rows, K, Kp);
+  hipLaunchKernelGGL(k_zero_pad, dim3(g), dim3(256), 0, st, (uint16_t*)YL, n);
 }
 
 size_t lp_contract_g_bytes(int prec, int no, int nv) {
   const int P = prec == CC3_BF16X3 ? 2 : 3;
-  return (size_t)P * no * (nv + no) * (size_t)kpad32((int64_t)nv * nv) * 2;  // one of Gbc, Gcb
+  return (size_t)P * no * (nv + no) * (size_t)lp_kb_len(nv) * 2;  // one of Gbc, Gcb
 }
 size_t lp_contract_cube_bytes(int prec, int nv) {
   const int P = prec == CC3_BF16X3 ? 2 : 3;
-  return (size_t)4 * P * nv * (size_t)kpad32((int64_t)nv * nv) * 2;  // per triple
+  return (size_t)4 * P * nv * (size_t)lp_kb_len(nv) * 2;  // per triple
+}
+
+// Split-BF16 pieces of the rows of Gbc or Gcb with K = (x, y) (x nv + y in the source)
+// in the blocked order lp_kb: dst[piece][row][kb], zero where x or y is past nv.
+template <int P>
+__global__ void k_lp_copy_blocked(const double* __restrict__ src, int64_t rows, int nv,
+                                  uint16_t* __restrict__ dst, int64_t piece_stride) {
+  const int64_t Kb = lp_kb_len(nv), K = (int64_t)nv * nv;
+  const int nb = (nv + 7) / 8;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * Kb) return;
+  const int64_t row = e / Kb;
+  const int kb = (int)(e % Kb);
+  const int blk = kb >> 6, x = (blk / nb) * 8 + ((kb >> 3) & 7), y = (blk % nb) * 8 + (kb & 7);
+  const double v = (x < nv && y < nv) ? src[row * K + (int64_t)x * nv + y] : 0.0;
+  uint16_t pc[P];
+  split_bf16<P>(v, pc);
+#pragma unroll
+  for (int i = 0; i < P; ++i) dst[i * piece_stride + e] = pc[i];
 }
 
 void launch_lp_contract_convert(const Blocks& b, int prec, int no, int nv, void* GbcL, void* GcbL,
                                 hipStream_t st) {
-  const int64_t v = nv, o = no, K = v * v, Kp = kpad32(K);
-  const int64_t ps = o * (v + o) * Kp;  // piece stride (elements)
+  const int64_t rows = (int64_t)no * (nv + no), n = rows * lp_kb_len(nv);
+  const int64_t ps = n;  // piece stride (elements)
+  const unsigned g = nblk(n, 256);
   if (prec == CC3_BF16X3) {
-    lp_copy<2>(b.Gbc, (v + o) * K, K, 1, 1.0, no, nv + no, (int)K, GbcL, ps, st);
-    lp_copy<2>(b.Gcb, (v + o) * K, K, 1, 1.0, no, nv + no, (int)K, GcbL, ps, st);
+    hipLaunchKernelGGL(k_lp_copy_blocked<2>, dim3(g), dim3(256), 0, st, b.Gbc, rows, nv,
+                       (uint16_t*)GbcL, ps);
+    hipLaunchKernelGGL(k_lp_copy_blocked<2>, dim3(g), dim3(256), 0, st, b.Gcb, rows, nv,
+                       (uint16_t*)GcbL, ps);
   } else {
-    lp_copy<3>(b.Gbc, (v + o) * K, K, 1, 1.0, no, nv + no, (int)K, GbcL, ps, st);
-    lp_copy<3>(b.Gcb, (v + o) * K, K, 1, 1.0, no, nv + no, (int)K, GcbL, ps, st);
+    hipLaunchKernelGGL(k_lp_copy_blocked<3>, dim3(g), dim3(256), 0, st, b.Gbc, rows, nv,
+                       (uint16_t*)GbcL, ps);
+    hipLaunchKernelGGL(k_lp_copy_blocked<3>, dim3(g), dim3(256), 0, st, b.Gcb, rows, nv,
+                       (uint16_t*)GcbL, ps);
   }
 }
 

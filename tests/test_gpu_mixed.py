@@ -136,16 +136,17 @@ def test_mixed_all_chunk_length(name):
     ctx.close()
 
 
+@pytest.mark.parametrize("no,nv,nJ", [(5, 48, 60), (4, 37, 40)])
 @pytest.mark.parametrize("name", ["fp32", "bf16x6", "bf16x3"])
-def test_mixed_all(name):
+def test_mixed_all(name, no, nv, nJ):
     """"Mixed-all" (CC3_LOWP_CONTRACT): the vv and Omega1 contraction in the low precision
-    too (FP32 MFMA, or split BF16), against the oracle at (5,48,60) (the whole call at
+    too (FP32 MFMA, or split BF16), against the oracle at (5,48,60) and at nv = 37, whose
+    last 8 x 8 block of the split-BF16 form's blocked K is ragged (the whole call at
     12/120/400 and a full batch at 23/250/800 are in test_gpu_whole_call_oracle.py); the
     measured errors are printed and bounded by bound_all."""
     torch, cc3 = _setup()
     prec = {"fp32": cc3.FP32, "bf16x6": cc3.BF16X6, "bf16x3": cc3.BF16X3}[name]
     ctx = cc3.Context(0)
-    no, nv, nJ = 5, 48, 60
     d = make_inputs(no, nv, nJ)
     g = {k: torch.from_numpy(d[k]).cuda() for k in ("eps", "L", "t1", "t2")}
     r1, r2 = O.triples_residual(d["eps"], d["L"], d["t1"], d["t2"])
