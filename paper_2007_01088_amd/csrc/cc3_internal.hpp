@@ -61,6 +61,9 @@ __host__ __device__ inline int64_t lp_kb_len(int nv) {
   const int64_t nb = (nv + 7) / 8;
   return nb * nb * 64;
 }
+// Row pitch of those operands: Kb plus 32 values, so that rows do not fall a power of
+// two apart (Kb is one whenever nv / 8 is) and share memory channels.
+__host__ __device__ inline int64_t lp_kb_pitch(int nv) { return lp_kb_len(nv) + 32; }
 __host__ __device__ inline int64_t lp_kb(int x, int y, int nv) {
   const int nb = (nv + 7) / 8;
   return ((int64_t)((x >> 3) * nb + (y >> 3)) * 8 + (x & 7)) * 8 + (y & 7);

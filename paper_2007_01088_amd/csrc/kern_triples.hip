@@ -301,12 +301,12 @@ __device__ inline double xval(const double* __restrict__ cz, int kind, int64_t n
 }
 
 // The split-BF16 pieces of x at row `row` and K pair (kx, ky) of view v of triple z in
-// YL[z][4][P][nv][Kb] (Kb = lp_kb_len(nv), the pair at lp_kb(kx, ky)).
+// YL[z][4][P][nv][Kr] (rows of pitch Kr = lp_kb_pitch(nv), the pair at lp_kb(kx, ky)).
 __device__ inline void yl_put(uint16_t* YL, int P, int z, int v, int row, int kx, int ky, int nv,
                               double x) {
-  const int64_t Kb = lp_kb_len(nv);
-  uint16_t* base = YL + (((int64_t)z * 4 + v) * P * nv + row) * Kb + lp_kb(kx, ky, nv);
-  const int64_t ps = (int64_t)nv * Kb;
+  const int64_t Kr = lp_kb_pitch(nv);
+  uint16_t* base = YL + (((int64_t)z * 4 + v) * P * nv + row) * Kr + lp_kb(kx, ky, nv);
+  const int64_t ps = (int64_t)nv * Kr;
   if (P == 2) {
     uint16_t pc[2];
     split_bf16<2>(x, pc);

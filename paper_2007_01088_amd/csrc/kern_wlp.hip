@@ -527,11 +527,12 @@ __global__ __launch_bounds__(LNT) void k_omega_lp(const char* __restrict__ YL,
   const int m0 = (tile / tiles_n) * LBM, n0 = (tile % tiles_n) * LBN;
   const int64_t Kp = lp_kb_len(nv);  // the blocked K of the views and of GL
   const int S = (int)(Kp / E::BK);
+  const int64_t Kr = lp_kb_pitch(nv);  // their row pitch
   const int s0 = (int)((int64_t)ch * S / nchunks), s1 = (int)((int64_t)(ch + 1) * S / nchunks);
   if (s0 >= s1) return;
   const int view = pi == 0 ? 0 : pi == 3 ? 3 : (pi == 1 || pi == 4) ? 1 : 2;
   const bool cb = (pi == 2 || pi == 4);
-  const int64_t rs = Kp * ESZ;                                   // row stride, bytes
+  const int64_t rs = Kr * ESZ;                                   // row stride, bytes
   const int64_t y_ps = (int64_t)nv * rs;                         // piece stride of a view
   const int64_t g_ps = (int64_t)no * (nv + no) * rs;             // piece stride of GL
   const LpSeg sg = {YL + ((int64_t)z * 4 + view) * E::P * y_ps,
@@ -600,7 +601,7 @@ __global__ void k_zero_pad(uint16_t* __restrict__ p, int64_t n) {
 
 void launch_lp_zero_pad(void* YL, int64_t rows, int nv, hipStream_t st) {
   if (nv % 8 == 0 || rows == 0) return;  // no position of the blocked K lies past nv
-  const int64_t n = rows * lp_kb_len(nv);
+  const int64_t n = rows * lp_kb_pitch(nv);
   unsigned g = nblk(n / 8 + 1, 256);
   if (g > 65536) g = 65536;
   hipLaunchKernelGGL(k_zero_pad, dim3(g), dim3(256), 0, st, (uint16_t*)YL, n);
@@ -608,19 +609,20 @@ void launch_lp_zero_pad(void* YL, int64_t rows, int nv, hipStream_t st) {
 
 size_t lp_contract_g_bytes(int prec, int no, int nv) {
   const int P = prec == CC3_BF16X3 ? 2 : 3;
-  return (size_t)P * no * (nv + no) * (size_t)lp_kb_len(nv) * 2;  // one of Gbc, Gcb
+  return (size_t)P * no * (nv + no) * (size_t)lp_kb_pitch(nv) * 2;  // one of Gbc, Gcb
 }
 size_t lp_contract_cube_bytes(int prec, int nv) {
   const int P = prec == CC3_BF16X3 ? 2 : 3;
-  return (size_t)4 * P * nv * (size_t)lp_kb_len(nv) * 2;  // per triple
+  return (size_t)4 * P * nv * (size_t)lp_kb_pitch(nv) * 2;  // per triple
 }
 
 // Split-BF16 pieces of the rows of Gbc or Gcb with K = (x, y) (x nv + y in the source)
-// in the blocked order lp_kb: dst[piece][row][kb], zero where x or y is past nv.
+// in the blocked order lp_kb: dst[piece][row][kb] at row pitch lp_kb_pitch, zero where x
+// or y is past nv (the pitch's tail is never read).
 template <int P>
 __global__ void k_lp_copy_blocked(const double* __restrict__ src, int64_t rows, int nv,
                                   uint16_t* __restrict__ dst, int64_t piece_stride) {
-  const int64_t Kb = lp_kb_len(nv), K = (int64_t)nv * nv;
+  const int64_t Kb = lp_kb_len(nv), Kr = lp_kb_pitch(nv), K = (int64_t)nv * nv;
   const int nb = (nv + 7) / 8;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * Kb) return;
@@ -631,13 +633,13 @@ __global__ void k_lp_copy_blocked(const double* __restrict__ src, int64_t rows, 
   uint16_t pc[P];
   split_bf16<P>(v, pc);
 #pragma unroll
-  for (int i = 0; i < P; ++i) dst[i * piece_stride + e] = pc[i];
+  for (int i = 0; i < P; ++i) dst[i * piece_stride + row * Kr + kb] = pc[i];
 }
 
 void launch_lp_contract_convert(const Blocks& b, int prec, int no, int nv, void* GbcL, void* GcbL,
                                 hipStream_t st) {
   const int64_t rows = (int64_t)no * (nv + no), n = rows * lp_kb_len(nv);
-  const int64_t ps = n;  // piece stride (elements)
+  const int64_t ps = rows * lp_kb_pitch(nv);  // piece stride (elements)
   const unsigned g = nblk(n, 256);
   if (prec == CC3_BF16X3) {
     hipLaunchKernelGGL(k_lp_copy_blocked<2>, dim3(g), dim3(256), 0, st, b.Gbc, rows, nv,
