@@ -24,7 +24,7 @@ size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct DPlan {
   int no, nv, nchol, npairs, ntask;
-  size_t cube;  // doubles per nv^3 cube
+  size_t cube;  // doubles per cube (cube_slot: nv x nv rows at the padded pitch)
   size_t off_Gw, off_Gl, off_Go, off_Go3, off_Jo, off_F, off_t2N, off_l2M, off_Y;
   size_t off_part, off_py, off_pkc, off_tri, off_task, off_cubes;
   size_t part_doubles, py_doubles, pkc_doubles, chol_bytes;

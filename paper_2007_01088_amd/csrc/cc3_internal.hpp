@@ -247,7 +247,7 @@ void launch_packed_step(const PackJob* dev_jobs, const PackJob* host_jobs, int n
                         hipStream_t st);
 
 // ---- transition densities (Algorithm 3) ----
-// Slots of the density loop's cubes, slot-major: cubes[slot][z][nv^3].
+// Slots of the density loop's cubes, slot-major: cubes[slot][z][cube_slot(nv)].
 enum { D3_P0 = 0, D3_P1 = 1, D3_P2 = 2, D3_TAU = 3, D3_TAUC = 4, D3_LC = 5, D3_NSLOT = 6 };
 // tau, tau~ (lmode false) or L~ (lmode true, with the outer products of the L3
 // statement from l1, l2, Jo, F and the shift omega) from the planes of each triple

@@ -529,8 +529,8 @@ void launch_mix(const double* eps, const int* tri, int ntri, double* cubes, floa
 
 // ---------------------------------------------------------------------------
 // Mix of the transition-density loop (Algorithm 3).  Cubes are slot-major,
-// cubes[slot][z][nv^3] (slot stride ss), so that each slot of a batch is one
-// contiguous run of cubes.  LMODE false: from the t3 planes, tau = -X/eps and
+// cubes[slot][z][cube] (slot stride ss; each cube nv x nv rows at the padded pitch
+// cube_pitch), so that each slot of a batch is one contiguous run of cubes.  LMODE false: from the t3 planes, tau = -X/eps and
 // tau~ (the contravariant combination) into slots D3_TAU, D3_TAUC.  LMODE true:
 // from the L3 planes plus the outer-product terms of the L3 statement,
 //   sum over the six simultaneous permutations (p,q,r; x,y,z) of (i,j,k; a,b,c) of
